@@ -1,0 +1,233 @@
+/*
+ * libwdirac -- even-odd preconditioned Wilson-Dirac operator for fermions in a
+ * representation R of SU(N) (fundamental, adjoint, two-index symmetric and
+ * antisymmetric), its conjugate-gradient solve and its fermion force, on AMD
+ * MI355X (gfx950).  Definitions follow arXiv:2503.06721 (HiRep v2).
+ *
+ * C ABI.  Every `void *` field argument is DEVICE memory owned by the caller
+ * (for example the data pointer of a torch tensor on the GPU); `stream` is a
+ * hipStream_t passed as `void *` (NULL = the null stream).  No call allocates
+ * device memory: scratch space is passed in as `workspace`, sized by
+ * wdirac_workspace_bytes().  All calls are asynchronous on `stream` except
+ * wdirac_cg_eo() and wdirac_force_eo(), which synchronise `stream`.  No call
+ * aborts or throws; each returns a wdirac_status code, and on error the
+ * thread-local message of wdirac_last_error() says what was wrong.
+ *
+ * Geometry.  dims = {T, X, Y, Z}, direction mu = 0 is time (Sec. 2.1); every
+ * extent must be even and >= 2.  The lexicographic site index is
+ * ((t*X + x)*Y + y)*Z + z; a site is even when (t+x+y+z) is even (Sec. 5.3.3).
+ * bc[mu] = +1 periodic, -1 antiperiodic for the fermion field (Sec. 6.3.1).
+ *
+ * Canonical layouts (the caller's), all row-major, complex = (re, im) pairs:
+ *   fundamental links  complex128 [T][X][Y][Z][4][N][N]
+ *   represented links  complex128 [T][X][Y][Z][4][d][d] (ADJ: float64, real)
+ *   spinor (full)      [nrhs][T][X][Y][Z][4][d], complex128 for WDIRAC_F64
+ *                      and complex64 for WDIRAC_F32 (spin index, then colour)
+ *   force              complex128 [T][X][Y][Z][4][N][N]
+ * Packed layouts (the library's, opaque sizes from wdirac_field_bytes()):
+ *   half spinor  one parity, structure of arrays: component (spin*d + colour)
+ *                major, site (index among sites of that parity, in
+ *                lexicographic order) minor, so that consecutive GPU lanes
+ *                touch consecutive addresses.
+ *   links        U_R for both parities and the four positive directions in the
+ *                same site-minor order, with the fermion boundary phase folded
+ *                in (Sec. 6.3.1).
+ */
+#ifndef WDIRAC_H
+#define WDIRAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wdirac_ctx wdirac_ctx;
+
+typedef enum {
+  WDIRAC_OK = 0,
+  WDIRAC_EINVAL = -1,       /* bad argument: null pointer, odd extent, nrhs out of range, ... */
+  WDIRAC_EUNSUPPORTED = -2, /* (N, representation) pair not built, e.g. SU(2) 2AS (d = 1)     */
+  WDIRAC_EHIP = -3,         /* HIP runtime error (message in wdirac_last_error)              */
+  WDIRAC_ENOCONV = -4,      /* solver reached maxit; x holds the last iterate, stats filled   */
+  WDIRAC_EBREAKDOWN = -5    /* solver met a non-finite value or <p, A p> <= 0                 */
+} wdirac_status;
+
+typedef enum { WDIRAC_FUND = 0, WDIRAC_ADJ = 1, WDIRAC_SYM = 2, WDIRAC_ASYM = 3 } wdirac_rep;
+typedef enum { WDIRAC_F64 = 0, WDIRAC_F32 = 1 } wdirac_prec;
+typedef enum { WDIRAC_CG_F64 = 0, WDIRAC_CG_MIXED = 1 } wdirac_cg_mode;
+
+/* Kinds of packed objects, for wdirac_field_bytes(). */
+typedef enum { WDIRAC_FIELD_HALF_SPINOR = 0, WDIRAC_FIELD_LINKS = 1 } wdirac_field_kind;
+/* Operations that need scratch memory, for wdirac_workspace_bytes(). */
+typedef enum { WDIRAC_OP_DHAT = 0, WDIRAC_OP_CG = 1, WDIRAC_OP_FORCE = 2, WDIRAC_OP_NORM = 3 } wdirac_op;
+
+typedef struct {
+  int32_t dims[4]; /* T, X, Y, Z: even, >= 2                                */
+  int32_t bc[4];   /* +1 periodic or -1 antiperiodic fermion BC per direction */
+} wdirac_geom;
+
+typedef struct {
+  int32_t iters;            /* CG iterations (outer plus inner for mixed)            */
+  int32_t reliable_updates; /* FP64 residual replacements                            */
+  int32_t hops;             /* hopping-term applications issued for this solve       */
+  int32_t status;           /* wdirac_status of this right-hand side                 */
+  double true_rel_resid;    /* ||b - A x|| / ||b|| recomputed in FP64 at the end      */
+  double seconds;           /* wall time of the whole call                           */
+} wdirac_cg_stats;
+
+/* Create a context for SU(Ng) fermions in representation `rep` on the lattice
+ * `geom`.  Host only: validates arguments and records the geometry; touches no
+ * GPU.  Supported: Ng in {2, 3, 4} with every representation of the paper's
+ * table of representations (Sec. 2.3) except SU(2) 2AS, whose d_R = 1.
+ * *ctx receives the new context (owned by the caller, released with
+ * wdirac_destroy).  Errors: EINVAL, EUNSUPPORTED. */
+int wdirac_create(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *geom);
+
+/* Release a context (NULL is accepted). */
+int wdirac_destroy(wdirac_ctx *ctx);
+
+/* Tuning options (host only; they change speed, never results beyond
+ * rounding):
+ *   WDIRAC_OPT_HOP_VARIANT_F64 / _F32  0 = one lane per site (d_R <= 6 only),
+ *                                      1 = one wavefront per colour row of a
+ *                                          64-site tile (default)
+ *   WDIRAC_OPT_XCD_REMAP               1 (default) = give each XCD a
+ *                                      contiguous range of site tiles
+ *   WDIRAC_OPT_CG_CHECK_EVERY          CG iterations between host checks of
+ *                                      convergence (default 4, 1..1000)
+ *   WDIRAC_OPT_MIXED_DELTA             reliable-update trigger of mixed CG,
+ *                                      ||r|| < delta max ||r|| (default 0.1)
+ * Errors: EINVAL (unknown option or value), EUNSUPPORTED. */
+typedef enum {
+  WDIRAC_OPT_HOP_VARIANT_F64 = 0,
+  WDIRAC_OPT_HOP_VARIANT_F32 = 1,
+  WDIRAC_OPT_XCD_REMAP = 2,
+  WDIRAC_OPT_CG_CHECK_EVERY = 3,
+  WDIRAC_OPT_MIXED_DELTA = 4
+} wdirac_option;
+int wdirac_set_option(wdirac_ctx *ctx, int option, double value);
+
+/* Representation dimension d_R and whether links are stored as real numbers
+ * (ADJ; Sec. 4.1.2).  Host only. */
+int wdirac_rep_info(const wdirac_ctx *ctx, int *d_R, int *real_links);
+
+/* Bytes of one packed object of `kind` holding `nrhs` right-hand sides (1 for
+ * links) in precision `prec`.  Returns 0 for invalid arguments.  Host only. */
+size_t wdirac_field_bytes(const wdirac_ctx *ctx, int kind, int nrhs, int prec);
+
+/* Bytes of scratch memory `op` needs for `nrhs` right-hand sides (for
+ * WDIRAC_OP_CG, `prec` is a wdirac_cg_mode).  Returns 0 for invalid arguments. */
+size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec);
+
+/* Pack the sites of parity `parity` of the canonical full spinor `canon`
+ * ([nrhs][T][X][Y][Z][4][d]) into the packed half spinor `packed`.  Both in
+ * precision `prec`.  Errors: EINVAL, EHIP. */
+int wdirac_pack_spinor(const wdirac_ctx *ctx, void *packed, const void *canon, int parity, int nrhs,
+                       int prec, void *stream);
+
+/* Inverse of wdirac_pack_spinor: writes the sites of parity `parity` of the
+ * canonical full spinor `canon`; sites of the other parity are left as they
+ * are.  Errors: EINVAL, EHIP. */
+int wdirac_unpack_spinor(const wdirac_ctx *ctx, void *canon, const void *packed, int parity, int nrhs,
+                         int prec, void *stream);
+
+/* Represented links (Sec. 2.3): U_R(x,mu) = R(U(x,mu)) for every link of the
+ * canonical fundamental field `U`, written packed to `UR` in precision
+ * `prec`, with the fermion boundary phase bc[mu] multiplied into the links
+ * U_R(x,mu) whose x_mu = L_mu - 1 (the hops that cross the boundary; Sec.
+ * 6.3.1 applies the antiperiodic sign to one slice of the represented field).
+ * Bases of R: generalised Gell-Mann generators, ADJ (U_R)_ab =
+ * 2 tr(T^a U T^b U^+), SYM/2AS on the orthonormal (anti)symmetric basis
+ * matrices in lexicographic pair order.  Errors: EINVAL, EHIP. */
+int wdirac_rep_links(const wdirac_ctx *ctx, void *UR, const void *U, int prec, void *stream);
+
+/* Unpack packed links `UR` (precision `prec`) to the canonical represented
+ * layout in float64/complex128 (boundary phase included).  For checks. */
+int wdirac_unpack_links(const wdirac_ctx *ctx, void *UR_canon, const void *UR, int prec, void *stream);
+
+/* Hopping block of the Wilson-Dirac operator (Sec. 2.3, even-odd split of
+ * Sec. 5.3.3), applied to `nrhs` packed half spinors at once:
+ *   out = alpha * x_add + beta * H in,
+ *   H in (x) = -1/2 sum_mu [ (1 - g_mu) U_R(x,mu) in(x+mu)
+ *                            + (1 + g_mu) U_R(x-mu,mu)^+ in(x-mu) ]
+ * for the sites x of parity `out_parity` (0: D_eo, input odd; 1: D_oe, input
+ * even).  With dagger = 1, H is replaced by the (out_parity, 1-out_parity)
+ * block of H^+, i.e. the adjoint of the opposite block (the two spin
+ * projectors trade places).  x_add may be NULL (then alpha is ignored); it may
+ * alias `out` but `in` may not.  `UR` comes from wdirac_rep_links in the same
+ * precision `prec`.  Errors: EINVAL, EHIP. */
+int wdirac_dslash_eo(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, int out_parity,
+                     int dagger, int nrhs, double alpha, const void *x_add, double beta, int prec,
+                     void *stream);
+
+/* Diagonal blocks of the unimproved Wilson operator (Sec. 5.3.3):
+ * D_ee = D_oo = (4 + m0) 1; out = (4 + m0) in, or in / (4 + m0) when
+ * inverse = 1.  out may alias in.  Errors: EINVAL (also m0 = -4 with
+ * inverse), EHIP. */
+int wdirac_apply_Mee(const wdirac_ctx *ctx, void *out, const void *in, double m0, int inverse, int nrhs,
+                     int prec, void *stream);
+int wdirac_apply_Moo(const wdirac_ctx *ctx, void *out, const void *in, double m0, int inverse, int nrhs,
+                     int prec, void *stream);
+
+/* Preconditioned operator (Sec. 5.3.3) on packed even half spinors:
+ *   dagger = 0: out = D-hat in   = (4+m0)^2 in - D_eo D_oe in,
+ *   dagger = 1: out = D-hat^+ in = (4+m0)^2 in - D_oe^+ D_eo^+ in.
+ * workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_DHAT, nrhs, prec) bytes.
+ * Errors: EINVAL, EHIP. */
+int wdirac_apply_dhat(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, double m0,
+                      int dagger, int nrhs, int prec, void *workspace, void *stream);
+
+/* Even-odd source preparation (Sec. 5.3.3, from the block form of D_m psi =
+ * eta): b_e = (4+m0) eta_e - D_eo eta_o.  Packed FP64 halves.  Errors: EINVAL, EHIP. */
+int wdirac_eo_source(const wdirac_ctx *ctx, void *b_e, const void *eta_e, const void *eta_o,
+                     const void *UR, double m0, int nrhs, void *stream);
+
+/* Odd half of the solution: psi_o = (eta_o - D_oe psi_e) / (4 + m0).  Packed
+ * FP64 halves.  Errors: EINVAL, EHIP. */
+int wdirac_eo_reconstruct(const wdirac_ctx *ctx, void *psi_o, const void *psi_e, const void *eta_o,
+                          const void *UR, double m0, int nrhs, void *stream);
+
+/* Squared norms ||v_k||^2 of the nrhs packed half spinors v (precision prec),
+ * summed in FP64 with compensated (Neumaier, Sec. 5.1.1) accumulation of the
+ * block partial sums; written to the host array out[nrhs].  Synchronises.
+ * workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_NORM, nrhs, prec). */
+int wdirac_norm2(const wdirac_ctx *ctx, double *out, const void *v, int nrhs, int prec, void *workspace,
+                 void *stream);
+
+/* Conjugate gradient (Sec. 5.1.2) on (D-hat^+ D-hat) x = b over the even sites,
+ * independently for each of nrhs right-hand sides.  x (packed FP64, in: the
+ * initial guess, out: the solution), b (packed FP64).  Stops when the FP64
+ * true residual ||b - A x|| <= tol ||b|| (recomputed, not the recursive one).
+ * mode WDIRAC_CG_F64: all in FP64, UR32 unused (may be NULL).  mode
+ * WDIRAC_CG_MIXED: FP32 hops and vectors inside, FP64 solution, FP64
+ * residual replacements ("reliable updates") and FP64 inner-product sums;
+ * UR32 = the FP32 links.  stats: host array of nrhs records.  Returns OK,
+ * ENOCONV (some rhs reached maxit), EBREAKDOWN, EINVAL or EHIP.  workspace:
+ * wdirac_workspace_bytes(ctx, WDIRAC_OP_CG, nrhs, mode).  Synchronises. */
+int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32,
+                 double m0, double tol, int maxit, int nrhs, int mode, void *workspace,
+                 wdirac_cg_stats *stats, void *stream);
+
+/* Fermion force of S_f = phi^+ (D-hat^+ D-hat)^{-1} phi (Sec. 5.3.1, force of
+ * Sec. 2.5 in even-odd form) given the solution x = (D-hat^+ D-hat)^{-1} phi
+ * (packed FP64 even half): for every link, the Hermitian traceless matrix
+ *   P_mu(x) = sum_a (dS/dw^a_mu(x)) T^a_F,  dS/dw^a = Im tr[T^a_R U_R Sigma_mu],
+ *   Sigma_mu(x) = tr_spin[(1 - g_mu) X(x+mu) Y(x)^+ + (1 + g_mu) Y(x+mu) X(x)^+],
+ * X = (x, D_oe x), Y = (D-hat x, D_eo^+ D-hat x), for the variation
+ * U -> exp(i w^a T^a_F) U.  P (canonical complex128 force layout) receives
+ * scale * P (accumulate = 0) or P += scale * P (accumulate = 1).  workspace:
+ * wdirac_workspace_bytes(ctx, WDIRAC_OP_FORCE, 1, WDIRAC_F64).  Errors:
+ * EINVAL, EHIP. */
+int wdirac_force_eo(const wdirac_ctx *ctx, void *P, const void *x_e, const void *UR64, double m0,
+                    double scale, int accumulate, void *workspace, void *stream);
+
+/* Thread-local description of the last error (empty string if none). */
+const char *wdirac_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDIRAC_H */

@@ -54,6 +54,21 @@ def hopping(psi, UR, bc, dagger=False):
     return -0.5 * out
 
 
+def links_with_boundary_phase(UR, bc):
+    """U_R with the fermion boundary phase bc[mu] multiplied into the links
+    U_R(x, mu) with x_mu = L_mu - 1, the hops that cross the boundary (Sec.
+    6.3.1 implements antiperiodic conditions as a sign on one slice of the
+    represented field).  Periodic hopping on these links equals hopping with
+    the boundary condition on the fermion field."""
+    out = np.array(UR, copy=True)
+    for mu in range(4):
+        if bc[mu] != 1:
+            idx = [slice(None)] * 4 + [mu]
+            idx[mu] = -1
+            out[tuple(idx)] *= bc[mu]
+    return out
+
+
 def dirac(psi, UR, m, bc):
     """D_m psi = (4 + m) psi + H psi."""
     return (4.0 + m) * psi + hopping(psi, UR, bc)

@@ -1,0 +1,570 @@
+// C ABI of libwdirac: argument checking, dispatch to the kernels, and the
+// host loop of the conjugate-gradient solver.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/wdirac.h"
+#include "wd_common.h"
+#include "wd_kernels.h"
+
+struct wdirac_ctx {
+  int N, rep, d, real;
+  wd::Geom g;
+  int hop_variant[2];   // per precision (F64, F32): wd::HOP_SITE or wd::HOP_COLOUR
+  int xcd_remap;
+  int cg_check_every;   // CG iterations between host convergence checks
+  double mixed_delta;   // reliable-update trigger ||r|| < delta max||r||
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define WD_HIP(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(WDIRAC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define WD_TRY(expr)            \
+  do {                          \
+    int rc_ = (expr);           \
+    if (rc_ != WDIRAC_OK) return rc_; \
+  } while (0)
+
+int rep_dim(int N, int rep) {
+  switch (rep) {
+    case WDIRAC_FUND: return N;
+    case WDIRAC_ADJ: return N * N - 1;
+    case WDIRAC_SYM: return N * (N + 1) / 2;
+    case WDIRAC_ASYM: return N * (N - 1) / 2;
+  }
+  return 0;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+size_t half_bytes(const wdirac_ctx *c, int nrhs, int prec) {
+  return (size_t)nrhs * 4 * c->d * c->g.stride * (prec == WDIRAC_F64 ? 16 : 8);
+}
+
+wd::FieldShape shape(const wdirac_ctx *c, int nrhs) { return wd::FieldShape{c->g.Vh, c->g.stride, 4 * c->d, nrhs}; }
+
+hipStream_t S(void *s) { return static_cast<hipStream_t>(s); }
+
+int check_ctx(const wdirac_ctx *c) {
+  if (!c) return fail(WDIRAC_EINVAL, "ctx is NULL");
+  return WDIRAC_OK;
+}
+int check_prec(int prec) {
+  if (prec != WDIRAC_F64 && prec != WDIRAC_F32) return fail(WDIRAC_EINVAL, "prec must be WDIRAC_F64 or WDIRAC_F32");
+  return WDIRAC_OK;
+}
+int check_nrhs(int nrhs) {
+  if (nrhs < 1 || nrhs > 12) return fail(WDIRAC_EINVAL, "nrhs must be in [1, 12]");
+  return WDIRAC_OK;
+}
+int check_parity(int p) {
+  if (p != 0 && p != 1) return fail(WDIRAC_EINVAL, "parity must be 0 (even) or 1 (odd)");
+  return WDIRAC_OK;
+}
+int check_ptr(const void *p, const char *name) {
+  if (!p) return fail(WDIRAC_EINVAL, std::string(name) + " is NULL");
+  return WDIRAC_OK;
+}
+
+// Workspace carving: consecutive 256-byte aligned pieces.
+struct Carver {
+  char *base;
+  size_t off = 0;
+  void *take(size_t n) {
+    void *p = base ? base + off : nullptr;
+    off += align256(n);
+    return p;
+  }
+};
+
+size_t partial_doubles(const wdirac_ctx *c, int nrhs) {
+  // enough for any producer of per-block partial sums
+  const int nb = std::max(wd::hop_nblocks(c->g.Vh, c->d, wd::HOP_COLOUR),
+                          std::max(wd::hop_nblocks(c->g.Vh, c->d, wd::HOP_SITE),
+                                   wd::blas_nblocks(shape(c, nrhs))));
+  return (size_t)nrhs * nb;
+}
+
+struct CgWork {
+  void *r, *p, *q, *t, *u, *v;            // FP64
+  void *r32, *p32, *x32, *q32, *t32, *u32, *v32;  // FP32 (mixed)
+  double *P1, *P2;
+  wd::CgScalars *sc;
+  size_t bytes;
+};
+
+CgWork carve_cg(const wdirac_ctx *c, int nrhs, int mode, void *ws) {
+  Carver cv{static_cast<char *>(ws)};
+  CgWork w{};
+  const size_t h64 = half_bytes(c, nrhs, WDIRAC_F64), h32 = half_bytes(c, nrhs, WDIRAC_F32);
+  w.r = cv.take(h64); w.p = cv.take(h64); w.q = cv.take(h64);
+  w.t = cv.take(h64); w.u = cv.take(h64); w.v = cv.take(h64);
+  if (mode == WDIRAC_CG_MIXED) {
+    w.r32 = cv.take(h32); w.p32 = cv.take(h32); w.x32 = cv.take(h32); w.q32 = cv.take(h32);
+    w.t32 = cv.take(h32); w.u32 = cv.take(h32); w.v32 = cv.take(h32);
+  }
+  w.P1 = static_cast<double *>(cv.take(partial_doubles(c, nrhs) * sizeof(double)));
+  w.P2 = static_cast<double *>(cv.take(partial_doubles(c, nrhs) * sizeof(double)));
+  w.sc = static_cast<wd::CgScalars *>(cv.take(nrhs * sizeof(wd::CgScalars)));
+  w.bytes = cv.off;
+  return w;
+}
+
+// One hopping-term launch.
+int hop(const wdirac_ctx *c, void *out, const void *in, const void *UR, int out_parity, int dagger, int nrhs,
+        double alpha, const void *xadd, double beta, int prec, double *partial, hipStream_t st, int *nblk = nullptr) {
+  wd::HopArgs a;
+  a.out = out;
+  a.in = in;
+  a.links = UR;
+  a.xadd = xadd;
+  a.g = c->g;
+  a.parity = out_parity;
+  a.xcd_remap = c->xcd_remap;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.partial = partial;
+  int nb = 0;
+  WD_HIP(wd::launch_hop(a, c->d, c->real, prec, dagger, nrhs, c->hop_variant[prec], st, &nb));
+  if (nblk) *nblk = nb;
+  return WDIRAC_OK;
+}
+
+// out = D-hat in (dagger = 0) or D-hat^+ in (dagger = 1); tmp is an odd half field.
+int dhat(const wdirac_ctx *c, void *out, const void *in, const void *UR, double m0, int dagger, int nrhs, int prec,
+         void *tmp, double *partial, hipStream_t st, int *nblk = nullptr) {
+  const double m4 = (4.0 + m0) * (4.0 + m0);
+  WD_TRY(hop(c, tmp, in, UR, 1, dagger, nrhs, 0.0, nullptr, 1.0, prec, nullptr, st));
+  WD_TRY(hop(c, out, tmp, UR, 0, dagger, nrhs, m4, in, -1.0, prec, partial, st, nblk));
+  return WDIRAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *wdirac_last_error(void) { return g_err.c_str(); }
+
+int wdirac_create(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *geom) {
+  g_err.clear();
+  if (!ctx) return fail(WDIRAC_EINVAL, "ctx is NULL");
+  *ctx = nullptr;
+  if (!geom) return fail(WDIRAC_EINVAL, "geom is NULL");
+  if (rep < WDIRAC_FUND || rep > WDIRAC_ASYM) return fail(WDIRAC_EINVAL, "unknown representation");
+  if (Ng < 2 || Ng > 4) return fail(WDIRAC_EUNSUPPORTED, "Ng must be 2, 3 or 4");
+  if (Ng == 2 && rep == WDIRAC_ASYM) return fail(WDIRAC_EUNSUPPORTED, "SU(2) 2AS is one-dimensional (d_R = 1)");
+  int64_t V = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    const int L = geom->dims[mu];
+    if (L < 2 || (L & 1)) return fail(WDIRAC_EINVAL, "every lattice extent must be even and >= 2");
+    if (geom->bc[mu] != 1 && geom->bc[mu] != -1) return fail(WDIRAC_EINVAL, "bc must be +1 or -1");
+    V *= L;
+  }
+  if (V > (int64_t)1 << 30) return fail(WDIRAC_EINVAL, "lattice volume above 2^30 sites");
+  wdirac_ctx *c = new wdirac_ctx();
+  c->N = Ng;
+  c->rep = rep;
+  c->d = rep_dim(Ng, rep);
+  c->real = rep == WDIRAC_ADJ;
+  c->g.T = geom->dims[0];
+  c->g.X = geom->dims[1];
+  c->g.Y = geom->dims[2];
+  c->g.Z = geom->dims[3];
+  c->g.Vh = (int)(V / 2);
+  c->g.stride = (c->g.Vh + 255) & ~255;   // whole 256-site tiles, see hop.hip
+  for (int mu = 0; mu < 4; ++mu) c->g.bc[mu] = geom->bc[mu];
+  c->hop_variant[0] = wd::HOP_COLOUR;
+  c->hop_variant[1] = wd::HOP_COLOUR;
+  c->xcd_remap = 1;
+  c->cg_check_every = 4;
+  c->mixed_delta = 0.1;
+  *ctx = c;
+  return WDIRAC_OK;
+}
+
+int wdirac_destroy(wdirac_ctx *ctx) {
+  delete ctx;
+  return WDIRAC_OK;
+}
+
+int wdirac_rep_info(const wdirac_ctx *ctx, int *d_R, int *real_links) {
+  WD_TRY(check_ctx(ctx));
+  if (d_R) *d_R = ctx->d;
+  if (real_links) *real_links = ctx->real;
+  return WDIRAC_OK;
+}
+
+size_t wdirac_field_bytes(const wdirac_ctx *ctx, int kind, int nrhs, int prec) {
+  if (!ctx || (prec != WDIRAC_F64 && prec != WDIRAC_F32)) return 0;
+  const size_t el = prec == WDIRAC_F64 ? 8 : 4;
+  if (kind == WDIRAC_FIELD_HALF_SPINOR) {
+    if (nrhs < 1 || nrhs > 12) return 0;
+    return half_bytes(ctx, nrhs, prec);
+  }
+  if (kind == WDIRAC_FIELD_LINKS) return (size_t)8 * ctx->d * ctx->d * ctx->g.stride * el * (ctx->real ? 1 : 2);
+  return 0;
+}
+
+size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec) {
+  if (!ctx || nrhs < 1 || nrhs > 12) return 0;
+  switch (op) {
+    case WDIRAC_OP_DHAT:
+      if (prec != WDIRAC_F64 && prec != WDIRAC_F32) return 0;
+      return align256(half_bytes(ctx, nrhs, prec));
+    case WDIRAC_OP_CG:
+      if (prec != WDIRAC_CG_F64 && prec != WDIRAC_CG_MIXED) return 0;
+      return carve_cg(ctx, nrhs, prec, nullptr).bytes;
+    case WDIRAC_OP_FORCE:
+      return 3 * align256(half_bytes(ctx, 1, WDIRAC_F64));
+    case WDIRAC_OP_NORM:
+      return align256(partial_doubles(ctx, nrhs) * sizeof(double)) + align256(nrhs * sizeof(double));
+  }
+  return 0;
+}
+
+int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
+  WD_TRY(check_ctx(ctx));
+  switch (option) {
+    case WDIRAC_OPT_HOP_VARIANT_F64:
+    case WDIRAC_OPT_HOP_VARIANT_F32: {
+      const int v = (int)value;
+      if ((v != wd::HOP_SITE && v != wd::HOP_COLOUR) || !wd::hop_variant_ok(ctx->d, v))
+        return fail(WDIRAC_EUNSUPPORTED, "hop variant not available for this representation");
+      ctx->hop_variant[option == WDIRAC_OPT_HOP_VARIANT_F64 ? 0 : 1] = v;
+      return WDIRAC_OK;
+    }
+    case WDIRAC_OPT_XCD_REMAP:
+      ctx->xcd_remap = value != 0.0;
+      return WDIRAC_OK;
+    case WDIRAC_OPT_CG_CHECK_EVERY:
+      if (value < 1 || value > 1000) return fail(WDIRAC_EINVAL, "check interval must be in [1, 1000]");
+      ctx->cg_check_every = (int)value;
+      return WDIRAC_OK;
+    case WDIRAC_OPT_MIXED_DELTA:
+      if (!(value > 0.0 && value < 1.0)) return fail(WDIRAC_EINVAL, "delta must be in (0, 1)");
+      ctx->mixed_delta = value;
+      return WDIRAC_OK;
+  }
+  return fail(WDIRAC_EINVAL, "unknown option");
+}
+
+int wdirac_pack_spinor(const wdirac_ctx *ctx, void *packed, const void *canon, int parity, int nrhs, int prec,
+                       void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(packed, "packed"));
+  WD_TRY(check_ptr(canon, "canon"));
+  WD_TRY(check_parity(parity));
+  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_prec(prec));
+  WD_HIP(wd::launch_pack_spinor(packed, canon, ctx->g, ctx->d, parity, nrhs, prec, 0, S(stream)));
+  return WDIRAC_OK;
+}
+
+int wdirac_unpack_spinor(const wdirac_ctx *ctx, void *canon, const void *packed, int parity, int nrhs, int prec,
+                         void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(packed, "packed"));
+  WD_TRY(check_ptr(canon, "canon"));
+  WD_TRY(check_parity(parity));
+  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_prec(prec));
+  WD_HIP(wd::launch_pack_spinor(const_cast<void *>(packed), canon, ctx->g, ctx->d, parity, nrhs, prec, 1,
+                                S(stream)));
+  return WDIRAC_OK;
+}
+
+int wdirac_rep_links(const wdirac_ctx *ctx, void *UR, const void *U, int prec, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_ptr(U, "U"));
+  WD_TRY(check_prec(prec));
+  WD_HIP(wd::launch_rep_links(U, UR, ctx->g, ctx->N, ctx->rep, prec, S(stream)));
+  return WDIRAC_OK;
+}
+
+int wdirac_unpack_links(const wdirac_ctx *ctx, void *UR_canon, const void *UR, int prec, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_ptr(UR_canon, "UR_canon"));
+  WD_TRY(check_prec(prec));
+  WD_HIP(wd::launch_unpack_links(UR_canon, UR, ctx->g, ctx->d, ctx->real, prec, S(stream)));
+  return WDIRAC_OK;
+}
+
+int wdirac_dslash_eo(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, int out_parity, int dagger,
+                     int nrhs, double alpha, const void *x_add, double beta, int prec, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(in, "in"));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_parity(out_parity));
+  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_prec(prec));
+  if (dagger != 0 && dagger != 1) return fail(WDIRAC_EINVAL, "dagger must be 0 or 1");
+  if (in == out) return fail(WDIRAC_EINVAL, "in and out must not alias");
+  return hop(ctx, out, in, UR, out_parity, dagger, nrhs, alpha, x_add, beta, prec, nullptr, S(stream));
+}
+
+static int apply_M(const wdirac_ctx *ctx, void *out, const void *in, double m0, int inverse, int nrhs, int prec,
+                   void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(in, "in"));
+  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_prec(prec));
+  if (inverse && 4.0 + m0 == 0.0) return fail(WDIRAC_EINVAL, "4 + m0 = 0 has no inverse");
+  const double f = inverse ? 1.0 / (4.0 + m0) : 4.0 + m0;
+  WD_HIP(wd::launch_lincomb(out, f, in, 0.0, nullptr, shape(ctx, nrhs), prec, S(stream)));
+  return WDIRAC_OK;
+}
+
+int wdirac_apply_Mee(const wdirac_ctx *ctx, void *out, const void *in, double m0, int inverse, int nrhs, int prec,
+                     void *stream) {
+  return apply_M(ctx, out, in, m0, inverse, nrhs, prec, stream);
+}
+
+int wdirac_apply_Moo(const wdirac_ctx *ctx, void *out, const void *in, double m0, int inverse, int nrhs, int prec,
+                     void *stream) {
+  return apply_M(ctx, out, in, m0, inverse, nrhs, prec, stream);
+}
+
+int wdirac_apply_dhat(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, double m0, int dagger,
+                      int nrhs, int prec, void *workspace, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(in, "in"));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_prec(prec));
+  if (dagger != 0 && dagger != 1) return fail(WDIRAC_EINVAL, "dagger must be 0 or 1");
+  if (in == out) return fail(WDIRAC_EINVAL, "in and out must not alias");
+  return dhat(ctx, out, in, UR, m0, dagger, nrhs, prec, workspace, nullptr, S(stream));
+}
+
+int wdirac_eo_source(const wdirac_ctx *ctx, void *b_e, const void *eta_e, const void *eta_o, const void *UR,
+                     double m0, int nrhs, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(b_e, "b_e"));
+  WD_TRY(check_ptr(eta_e, "eta_e"));
+  WD_TRY(check_ptr(eta_o, "eta_o"));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_nrhs(nrhs));
+  if (b_e == eta_o) return fail(WDIRAC_EINVAL, "b_e must not alias eta_o");
+  return hop(ctx, b_e, eta_o, UR, 0, 0, nrhs, 4.0 + m0, eta_e, -1.0, WDIRAC_F64, nullptr, S(stream));
+}
+
+int wdirac_eo_reconstruct(const wdirac_ctx *ctx, void *psi_o, const void *psi_e, const void *eta_o, const void *UR,
+                          double m0, int nrhs, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(psi_o, "psi_o"));
+  WD_TRY(check_ptr(psi_e, "psi_e"));
+  WD_TRY(check_ptr(eta_o, "eta_o"));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_nrhs(nrhs));
+  if (4.0 + m0 == 0.0) return fail(WDIRAC_EINVAL, "4 + m0 = 0 has no inverse");
+  if (psi_o == psi_e) return fail(WDIRAC_EINVAL, "psi_o must not alias psi_e");
+  const double f = 1.0 / (4.0 + m0);
+  return hop(ctx, psi_o, psi_e, UR, 1, 0, nrhs, f, eta_o, -f, WDIRAC_F64, nullptr, S(stream));
+}
+
+int wdirac_norm2(const wdirac_ctx *ctx, double *out, const void *v, int nrhs, int prec, void *workspace,
+                 void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(v, "v"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_prec(prec));
+  Carver cv{static_cast<char *>(workspace)};
+  double *part = static_cast<double *>(cv.take(partial_doubles(ctx, nrhs) * sizeof(double)));
+  double *dout = static_cast<double *>(cv.take(nrhs * sizeof(double)));
+  const wd::FieldShape f = shape(ctx, nrhs);
+  WD_HIP(wd::launch_norm2_partial(part, v, f, prec, S(stream)));
+  WD_HIP(wd::launch_finalize_sum(dout, part, wd::blas_nblocks(f), nrhs, S(stream)));
+  WD_HIP(hipMemcpyAsync(out, dout, nrhs * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
+  WD_HIP(hipStreamSynchronize(S(stream)));
+  return WDIRAC_OK;
+}
+
+// ------------------------------------------------------------------- CG
+// Per right-hand side, the Hestenes-Stiefel recurrence on A = D-hat^+ D-hat:
+//   q = A p (u = D-hat p gives <p, A p> = ||u||^2, then q = D-hat^+ u),
+//   alpha = rho / <p,Ap>;  x += alpha p;  r -= alpha q;  rho' = ||r||^2;
+//   beta = rho'/rho;  p = r + beta p.
+// All scalars stay on the device; kernels of right-hand sides that are done
+// return at once, so the host only reads the scalars every few iterations.
+// When the recursive residual reaches the target, r is recomputed as b - A x
+// in FP64 (the "true" residual); if it is above target the recurrence resumes
+// from it with p kept (residual replacement).  Mixed mode runs the
+// recurrence in FP32 (hops, vectors; sums in FP64) on the correction
+// equation and replaces the residual in FP64 whenever ||r|| drops below
+// delta times its largest value since the previous replacement (reliable
+// updates), accumulating the FP32 correction into the FP64 solution.
+int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32, double m0,
+                 double tol, int maxit, int nrhs, int mode, void *workspace, wdirac_cg_stats *stats, void *stream) {
+  const auto t0 = std::chrono::steady_clock::now();
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(x, "x"));
+  WD_TRY(check_ptr(b, "b"));
+  WD_TRY(check_ptr(UR64, "UR64"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  WD_TRY(check_ptr(stats, "stats"));
+  WD_TRY(check_nrhs(nrhs));
+  if (mode != WDIRAC_CG_F64 && mode != WDIRAC_CG_MIXED) return fail(WDIRAC_EINVAL, "unknown CG mode");
+  if (mode == WDIRAC_CG_MIXED) WD_TRY(check_ptr(UR32, "UR32"));
+  if (!(tol > 0.0) || maxit < 0) return fail(WDIRAC_EINVAL, "tol must be > 0 and maxit >= 0");
+  if (x == b) return fail(WDIRAC_EINVAL, "x and b must not alias");
+  const hipStream_t st = S(stream);
+  const bool mixed = mode == WDIRAC_CG_MIXED;
+  CgWork w = carve_cg(ctx, nrhs, mode, workspace);
+  const wd::FieldShape f = shape(ctx, nrhs);
+  const int nbb = wd::blas_nblocks(f);
+  std::vector<wd::CgScalars> hs(nrhs);
+  std::vector<int> hops(nrhs, 0), rel(nrhs, 0);
+  int hop_count = 0, updates = 0;
+
+  // b2, stop2
+  WD_HIP(wd::launch_norm2_partial(w.P2, b, f, WDIRAC_F64, st));
+  WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, nrhs, tol, 1, 1, st));
+  // r = b - A x (FP64)
+  auto true_residual = [&]() -> int {
+    WD_TRY(dhat(ctx, w.u, x, UR64, m0, 0, nrhs, WDIRAC_F64, w.t, nullptr, st));
+    WD_TRY(dhat(ctx, w.q, w.u, UR64, m0, 1, nrhs, WDIRAC_F64, w.v, nullptr, st));
+    WD_HIP(wd::launch_residual(w.r, b, w.q, w.P2, f, st));
+    hop_count += 4;
+    return WDIRAC_OK;
+  };
+  WD_TRY(true_residual());
+  WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, nrhs, tol, 0, 1, st));
+  void *r = w.r, *p = w.p, *q = w.q, *t = w.t, *u = w.u, *v = w.v, *xi = x;
+  const void *UR = UR64;
+  int prec = WDIRAC_F64;
+  if (mixed) {
+    WD_HIP(wd::launch_convert(w.r32, WDIRAC_F32, w.r, WDIRAC_F64, f, st));
+    WD_HIP(wd::launch_lincomb(w.x32, 0.0, w.r32, 0.0, nullptr, f, WDIRAC_F32, st));
+    r = w.r32; p = w.p32; q = w.q32; t = w.t32; u = w.u32; v = w.v32; xi = w.x32;
+    UR = UR32;
+    prec = WDIRAC_F32;
+  }
+  WD_HIP(wd::launch_lincomb(p, 1.0, r, 0.0, nullptr, f, prec, st));
+  const double delta = mixed ? ctx->mixed_delta : 0.0;
+  const int check = ctx->cg_check_every;
+  int rc = WDIRAC_OK;
+  int launched = 0;   // iterations launched since start
+  for (;;) {
+    WD_HIP(hipMemcpyAsync(hs.data(), w.sc, nrhs * sizeof(wd::CgScalars), hipMemcpyDeviceToHost, st));
+    WD_HIP(hipStreamSynchronize(st));
+    bool any_active = false, any_update = false;
+    for (int k = 0; k < nrhs; ++k) {
+      any_active |= hs[k].active != 0;
+      any_update |= hs[k].need_update != 0;
+    }
+    int max_iters = 0;
+    for (int k = 0; k < nrhs; ++k) max_iters = std::max(max_iters, hs[k].iters);
+    if (!any_active && any_update) {
+      // residual replacement in FP64 (verifies convergence of the recursion)
+      if (mixed) WD_HIP(wd::launch_accum_x(x, w.x32, f, st));
+      WD_TRY(true_residual());
+      WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, nrhs, tol, 0, 0, st));
+      if (mixed) WD_HIP(wd::launch_convert(w.r32, WDIRAC_F32, w.r, WDIRAC_F64, f, st));
+      ++updates;
+      for (int k = 0; k < nrhs; ++k)
+        if (hs[k].need_update) ++rel[k];
+      continue;
+    }
+    if (!any_active) break;
+    if (max_iters >= maxit) {
+      rc = WDIRAC_ENOCONV;
+      break;
+    }
+    const int nit = std::min(check, std::max(1, maxit - max_iters));
+    for (int it = 0; it < nit; ++it) {
+      int nb2 = 0;
+      WD_TRY(dhat(ctx, u, p, UR, m0, 0, nrhs, prec, t, w.P1, st, &nb2));
+      WD_HIP(wd::launch_cg_alpha(w.sc, w.P1, nb2, nrhs, st));
+      WD_TRY(dhat(ctx, q, u, UR, m0, 1, nrhs, prec, v, nullptr, st));
+      WD_HIP(wd::launch_cg_update_xr(xi, prec, r, p, q, w.sc, w.P2, f, prec, st));
+      WD_HIP(wd::launch_cg_beta(w.sc, w.P2, nbb, nrhs, delta, st));
+      WD_HIP(wd::launch_cg_update_p(p, r, w.sc, f, prec, st));
+      hop_count += 4;
+      ++launched;
+    }
+  }
+  if (mixed) WD_HIP(wd::launch_accum_x(x, w.x32, f, st));
+  // final FP64 true residual of the returned x
+  WD_TRY(true_residual());
+  WD_HIP(wd::launch_finalize_sum(w.P1, w.P2, nbb, nrhs, st));
+  std::vector<double> res2(nrhs);
+  WD_HIP(hipMemcpyAsync(res2.data(), w.P1, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+  WD_HIP(hipMemcpyAsync(hs.data(), w.sc, nrhs * sizeof(wd::CgScalars), hipMemcpyDeviceToHost, st));
+  WD_HIP(hipStreamSynchronize(st));
+  // b = 0: the solution is x = 0 whatever the initial guess
+  for (int k = 0; k < nrhs; ++k)
+    if (!(hs[k].b2 > 0.0)) {
+      const size_t hb = half_bytes(ctx, 1, WDIRAC_F64);
+      WD_HIP(hipMemsetAsync(static_cast<char *>(x) + k * hb, 0, hb, st));
+      res2[k] = 0.0;
+    }
+  WD_HIP(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = WDIRAC_OK;
+  for (int k = 0; k < nrhs; ++k) {
+    wdirac_cg_stats &s = stats[k];
+    s.iters = hs[k].iters;
+    s.reliable_updates = rel[k];
+    s.hops = hop_count;
+    s.true_rel_resid = hs[k].b2 > 0.0 ? std::sqrt(res2[k] / hs[k].b2) : 0.0;
+    s.seconds = secs;
+    int stk = hs[k].status;
+    if (stk == WDIRAC_OK && hs[k].b2 > 0.0 && !(s.true_rel_resid <= tol)) stk = WDIRAC_ENOCONV;
+    s.status = stk;
+    if (stk == WDIRAC_EBREAKDOWN) worst = WDIRAC_EBREAKDOWN;
+    else if (stk == WDIRAC_ENOCONV && worst == WDIRAC_OK) worst = WDIRAC_ENOCONV;
+  }
+  (void)launched;
+  (void)updates;
+  if (rc == WDIRAC_ENOCONV && worst == WDIRAC_OK) worst = WDIRAC_ENOCONV;
+  if (worst == WDIRAC_ENOCONV) fail(worst, "CG did not reach the tolerance within maxit");
+  if (worst == WDIRAC_EBREAKDOWN) fail(worst, "CG breakdown (non-finite value or <p,Ap> <= 0)");
+  return worst;
+}
+
+int wdirac_force_eo(const wdirac_ctx *ctx, void *P, const void *x_e, const void *UR64, double m0, double scale,
+                    int accumulate, void *workspace, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(P, "P"));
+  WD_TRY(check_ptr(x_e, "x_e"));
+  WD_TRY(check_ptr(UR64, "UR64"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  const hipStream_t st = S(stream);
+  Carver cv{static_cast<char *>(workspace)};
+  const size_t h = half_bytes(ctx, 1, WDIRAC_F64);
+  void *z_o = cv.take(h), *y_e = cv.take(h), *w_o = cv.take(h);
+  // z_o = D_oe x;  y_e = (4+m)^2 x - D_eo z_o = D-hat x;  w_o = D_eo^+ y_e
+  WD_TRY(hop(ctx, z_o, x_e, UR64, 1, 0, 1, 0.0, nullptr, 1.0, WDIRAC_F64, nullptr, st));
+  WD_TRY(hop(ctx, y_e, z_o, UR64, 0, 0, 1, (4.0 + m0) * (4.0 + m0), x_e, -1.0, WDIRAC_F64, nullptr, st));
+  WD_TRY(hop(ctx, w_o, y_e, UR64, 1, 1, 1, 0.0, nullptr, 1.0, WDIRAC_F64, nullptr, st));
+  WD_HIP(wd::launch_force_links(P, x_e, z_o, y_e, w_o, UR64, ctx->g, ctx->N, ctx->rep, scale, accumulate, st));
+  WD_HIP(hipStreamSynchronize(st));
+  return WDIRAC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,357 @@
+// Linear algebra on packed half spinors and the per-iteration kernels of the
+// conjugate-gradient solver.  Sums are accumulated in FP64 whatever the field
+// precision; block partial sums are combined by one block per right-hand
+// side with Neumaier's compensated summation (Sec. 5.1.1), in a fixed order,
+// so results are deterministic (no floating-point atomics).
+#include "wd_common.h"
+#include "wd_kernels.h"
+
+namespace wd {
+
+constexpr int BT = 256;   // threads per block of the streaming kernels
+
+int blas_nblocks(const FieldShape &f) { return (f.Vh + BT - 1) / BT; }
+
+template <typename T>
+__device__ __forceinline__ cplx<T> ld(const void *p, size_t o) {
+  return static_cast<const cplx<T> *>(p)[o];
+}
+template <typename T>
+__device__ __forceinline__ void st(void *p, size_t o, cplx<double> v) {
+  static_cast<cplx<T> *>(p)[o] = mk<T>((T)v.re, (T)v.im);
+}
+template <typename T>
+__device__ __forceinline__ cplx<double> up(cplx<T> v) {
+  return mk<double>((double)v.re, (double)v.im);
+}
+
+// Compensated accumulation (Neumaier): (s, c) += v.
+__device__ __forceinline__ void neumaier_add(double &s, double &c, double v) {
+  const double t = s + v;
+  if (fabs(s) >= fabs(v)) c += (s - t) + v;
+  else c += (v - t) + s;
+  s = t;
+}
+
+// One block per rhs: out = compensated sum of partial[r][0..nblk).
+__device__ double sum_partials(const double *partial, int nblk) {
+  __shared__ double vals[BT];
+  double s = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += BT) neumaier_add(s, c, partial[k]);
+  vals[threadIdx.x] = s + c;
+  __syncthreads();
+  double tot = 0.0;
+  if (threadIdx.x == 0) {
+    double ts = 0.0, tc = 0.0;
+    for (int k = 0; k < BT; ++k) neumaier_add(ts, tc, vals[k]);
+    tot = ts + tc;
+  }
+  __syncthreads();
+  return tot;
+}
+
+__global__ __launch_bounds__(BT) void k_finalize_sum(double *out, const double *partial, int nblk) {
+  const int r = blockIdx.x;
+  const double s = sum_partials(partial + (size_t)r * nblk, nblk);
+  if (threadIdx.x == 0) out[r] = s;
+}
+
+hipError_t launch_finalize_sum(double *out, const double *partial, int nblk, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_sum, dim3(nrhs), dim3(BT), 0, st, out, partial, nblk);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- streaming
+template <typename T>
+__global__ __launch_bounds__(BT) void k_lincomb(void *out, double a, const void *x, double b, const void *y,
+                                                FieldShape f) {
+  const int i = blockIdx.x * BT + threadIdx.x;
+  if (i >= f.Vh) return;
+  const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  for (int c = 0; c < f.ncomp; ++c) {
+    const size_t o = base + (size_t)c * f.stride;
+    cplx<double> v = up(ld<T>(x, o));
+    v = a * v;
+    if (y) {
+      const cplx<double> w = up(ld<T>(y, o));
+      v.re = fma(b, w.re, v.re);
+      v.im = fma(b, w.im, v.im);
+    }
+    st<T>(out, o, v);
+  }
+}
+
+hipError_t launch_lincomb(void *out, double a, const void *x, double b, const void *y, const FieldShape &f, int prec,
+                          hipStream_t st) {
+  dim3 grid(blas_nblocks(f), f.nrhs);
+  if (prec == 0) hipLaunchKernelGGL(k_lincomb<double>, grid, dim3(BT), 0, st, out, a, x, b, y, f);
+  else hipLaunchKernelGGL(k_lincomb<float>, grid, dim3(BT), 0, st, out, a, x, b, y, f);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(BT) void k_norm2_partial(double *partial, const void *v, FieldShape f) {
+  __shared__ double sh[BT / 64];
+  const int i = blockIdx.x * BT + threadIdx.x;
+  double s = 0.0;
+  if (i < f.Vh) {
+    const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+    for (int c = 0; c < f.ncomp; ++c) {
+      const cplx<T> w = ld<T>(v, base + (size_t)c * f.stride);
+      s += (double)w.re * w.re + (double)w.im * w.im;
+    }
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+}
+
+hipError_t launch_norm2_partial(double *partial, const void *v, const FieldShape &f, int prec, hipStream_t st) {
+  dim3 grid(blas_nblocks(f), f.nrhs);
+  if (prec == 0) hipLaunchKernelGGL(k_norm2_partial<double>, grid, dim3(BT), 0, st, partial, v, f);
+  else hipLaunchKernelGGL(k_norm2_partial<float>, grid, dim3(BT), 0, st, partial, v, f);
+  return hipGetLastError();
+}
+
+template <typename TO, typename TI>
+__global__ __launch_bounds__(BT) void k_convert(void *out, const void *in, FieldShape f) {
+  const int i = blockIdx.x * BT + threadIdx.x;
+  if (i >= f.Vh) return;
+  const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  for (int c = 0; c < f.ncomp; ++c) {
+    const size_t o = base + (size_t)c * f.stride;
+    st<TO>(out, o, up(ld<TI>(in, o)));
+  }
+}
+
+hipError_t launch_convert(void *out, int prec_out, const void *in, int prec_in, const FieldShape &f,
+                          hipStream_t st) {
+  dim3 grid(blas_nblocks(f), f.nrhs);
+  if (prec_out == 0 && prec_in == 1) hipLaunchKernelGGL((k_convert<double, float>), grid, dim3(BT), 0, st, out, in, f);
+  else if (prec_out == 1 && prec_in == 0) hipLaunchKernelGGL((k_convert<float, double>), grid, dim3(BT), 0, st, out, in, f);
+  else if (prec_out == 0) hipLaunchKernelGGL((k_convert<double, double>), grid, dim3(BT), 0, st, out, in, f);
+  else hipLaunchKernelGGL((k_convert<float, float>), grid, dim3(BT), 0, st, out, in, f);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- CG
+__global__ __launch_bounds__(BT) void k_cg_alpha(CgScalars *S, const double *partial, int nblk) {
+  const int r = blockIdx.x;
+  CgScalars &s = S[r];
+  if (!s.active) return;
+  const double pAp = sum_partials(partial + (size_t)r * nblk, nblk);
+  if (threadIdx.x == 0) {
+    s.pAp = pAp;
+    if (!(pAp > 0.0) || !isfinite(pAp) || !isfinite(s.rho)) {
+      s.status = -5;   // breakdown
+      s.active = 0;
+      s.alpha = 0.0;
+    } else {
+      s.alpha = s.rho / pAp;
+    }
+  }
+}
+
+hipError_t launch_cg_alpha(CgScalars *s, const double *pAp_partial, int nblk, int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(nrhs), dim3(BT), 0, st, s, pAp_partial, nblk);
+  return hipGetLastError();
+}
+
+template <typename T, typename TX>
+__global__ __launch_bounds__(BT) void k_cg_update_xr(void *x, void *r, const void *p, const void *q,
+                                                     const CgScalars *S, double *partial, FieldShape f) {
+  __shared__ double sh[BT / 64];
+  const CgScalars &s = S[blockIdx.y];
+  if (!s.active) return;
+  const double a = s.alpha;
+  const int i = blockIdx.x * BT + threadIdx.x;
+  double nrm = 0.0;
+  if (i < f.Vh) {
+    const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+    for (int c = 0; c < f.ncomp; ++c) {
+      const size_t o = base + (size_t)c * f.stride;
+      const cplx<double> pv = up(ld<T>(p, o)), qv = up(ld<T>(q, o));
+      cplx<double> xv = up(ld<TX>(x, o)), rv = up(ld<T>(r, o));
+      xv.re = fma(a, pv.re, xv.re);
+      xv.im = fma(a, pv.im, xv.im);
+      rv.re = fma(-a, qv.re, rv.re);
+      rv.im = fma(-a, qv.im, rv.im);
+      st<TX>(x, o, xv);
+      const cplx<T> rs = mk<T>((T)rv.re, (T)rv.im);   // the stored (rounded) residual
+      static_cast<cplx<T> *>(r)[o] = rs;
+      nrm += (double)rs.re * rs.re + (double)rs.im * rs.im;
+    }
+  }
+  nrm = block_sum(nrm, sh);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = nrm;
+}
+
+hipError_t launch_cg_update_xr(void *x, int prec_x, void *r, const void *p, const void *q, const CgScalars *s,
+                               double *partial, const FieldShape &f, int prec, hipStream_t st) {
+  dim3 grid(blas_nblocks(f), f.nrhs);
+  if (prec == 0 && prec_x == 0)
+    hipLaunchKernelGGL((k_cg_update_xr<double, double>), grid, dim3(BT), 0, st, x, r, p, q, s, partial, f);
+  else if (prec == 1 && prec_x == 1)
+    hipLaunchKernelGGL((k_cg_update_xr<float, float>), grid, dim3(BT), 0, st, x, r, p, q, s, partial, f);
+  else if (prec == 1 && prec_x == 0)
+    hipLaunchKernelGGL((k_cg_update_xr<float, double>), grid, dim3(BT), 0, st, x, r, p, q, s, partial, f);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// beta = rho'/rho; convergence and (mixed mode) reliable-update triggers.
+// The p update of an iteration is due exactly when this kernel ran for the rhs
+// (do_p), including the iteration that pauses it for a residual replacement:
+// the recurrence resumes afterwards from a consistent (r, p) pair.
+__global__ __launch_bounds__(BT) void k_cg_beta(CgScalars *S, const double *partial, int nblk, double delta) {
+  const int r = blockIdx.x;
+  CgScalars &s = S[r];
+  const int act = s.active;
+  __syncthreads();
+  if (threadIdx.x == 0) s.do_p = 0;
+  if (!act) return;
+  const double rr = sum_partials(partial + (size_t)r * nblk, nblk);
+  if (threadIdx.x == 0) {
+    s.iters += 1;
+    if (!isfinite(rr)) {
+      s.status = -5;
+      s.active = 0;
+      return;
+    }
+    s.beta = rr / s.rho;
+    s.rho = rr;
+    s.do_p = 1;
+    const double rn = sqrt(rr);
+    if (rn > s.rmax) s.rmax = rn;
+    if (rr <= s.stop2) {
+      s.active = 0;          // recursive residual converged: verify in FP64
+      s.need_update = 1;
+    } else if (delta > 0.0 && rn < delta * s.rmax) {
+      s.active = 0;          // mixed mode: pause for a reliable update
+      s.need_update = 1;
+    }
+  }
+}
+
+hipError_t launch_cg_beta(CgScalars *s, const double *rr_partial, int nblk, int nrhs, double delta,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_beta, dim3(nrhs), dim3(BT), 0, st, s, rr_partial, nblk, delta);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(BT) void k_cg_update_p(void *p, const void *r, const CgScalars *S, FieldShape f) {
+  const CgScalars &s = S[blockIdx.y];
+  if (!s.do_p) return;
+  const double b = s.beta;
+  const int i = blockIdx.x * BT + threadIdx.x;
+  if (i >= f.Vh) return;
+  const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  for (int c = 0; c < f.ncomp; ++c) {
+    const size_t o = base + (size_t)c * f.stride;
+    const cplx<double> rv = up(ld<T>(r, o));
+    cplx<double> pv = up(ld<T>(p, o));
+    pv.re = fma(b, pv.re, rv.re);
+    pv.im = fma(b, pv.im, rv.im);
+    st<T>(p, o, pv);
+  }
+}
+
+hipError_t launch_cg_update_p(void *p, const void *r, const CgScalars *s, const FieldShape &f, int prec,
+                              hipStream_t st) {
+  dim3 grid(blas_nblocks(f), f.nrhs);
+  if (prec == 0) hipLaunchKernelGGL(k_cg_update_p<double>, grid, dim3(BT), 0, st, p, r, s, f);
+  else hipLaunchKernelGGL(k_cg_update_p<float>, grid, dim3(BT), 0, st, p, r, s, f);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(BT) void k_residual(void *r, const void *b, const void *q, double *partial,
+                                                 FieldShape f) {
+  __shared__ double sh[BT / 64];
+  const int i = blockIdx.x * BT + threadIdx.x;
+  double nrm = 0.0;
+  if (i < f.Vh) {
+    const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+    for (int c = 0; c < f.ncomp; ++c) {
+      const size_t o = base + (size_t)c * f.stride;
+      const cplx<double> v = ld<double>(b, o) - ld<double>(q, o);
+      st<double>(r, o, v);
+      nrm += v.re * v.re + v.im * v.im;
+    }
+  }
+  nrm = block_sum(nrm, sh);
+  if (threadIdx.x == 0) partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = nrm;
+}
+
+hipError_t launch_residual(void *r, const void *b, const void *q, double *partial, const FieldShape &f,
+                           hipStream_t st) {
+  dim3 grid(blas_nblocks(f), f.nrhs);
+  hipLaunchKernelGGL(k_residual, grid, dim3(BT), 0, st, r, b, q, partial, f);
+  return hipGetLastError();
+}
+
+// After a (re)computation of r = b - A x in FP64: rho = ||r||^2.  With set_b2
+// the partial sums are those of b itself and only b2 / stop2 are set.
+// Otherwise rhs that are not finished are (re)activated: finished means
+// converged (rho <= stop2), broken down, or b = 0.  reset_p_mask != 0 marks
+// that p must be reset to r by the caller (first start).
+__global__ __launch_bounds__(BT) void k_cg_restart(CgScalars *S, const double *partial, int nblk, double tol,
+                                                   int set_b2, int first) {
+  const int r = blockIdx.x;
+  CgScalars &s = S[r];
+  const double v = sum_partials(partial + (size_t)r * nblk, nblk);
+  if (threadIdx.x != 0) return;
+  if (set_b2) {
+    s.b2 = v;
+    s.stop2 = tol * tol * v;
+    s.iters = 0;
+    s.status = 0;
+    s.active = 0;
+    s.need_update = 0;
+    s.do_p = 0;
+    s.rmax = 0.0;
+    return;
+  }
+  s.rho = v;
+  s.rho64 = v;
+  s.rmax = sqrt(v);
+  s.need_update = 0;
+  if (first) s.beta = 0.0;
+  if (s.status != 0) {
+    s.active = 0;
+    return;
+  }
+  if (!isfinite(v)) {
+    s.status = -5;
+    s.active = 0;
+    return;
+  }
+  s.active = (s.b2 > 0.0 && v > s.stop2) ? 1 : 0;
+}
+
+hipError_t launch_cg_restart(CgScalars *s, const double *partial, int nblk, int nrhs, double tol, int set_b2,
+                             int first, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_restart, dim3(nrhs), dim3(BT), 0, st, s, partial, nblk, tol, set_b2, first);
+  return hipGetLastError();
+}
+
+// x64 += x32 and x32 = 0 (mixed-mode accumulation of the inner solution).
+__global__ __launch_bounds__(BT) void k_accum_x(void *x64, void *x32, FieldShape f) {
+  const int i = blockIdx.x * BT + threadIdx.x;
+  if (i >= f.Vh) return;
+  const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  for (int c = 0; c < f.ncomp; ++c) {
+    const size_t o = base + (size_t)c * f.stride;
+    const cplx<double> v = ld<double>(x64, o) + up(ld<float>(x32, o));
+    st<double>(x64, o, v);
+    st<float>(x32, o, mk(0.0, 0.0));
+  }
+}
+
+hipError_t launch_accum_x(void *x64, void *x32, const FieldShape &f, hipStream_t st) {
+  dim3 grid(blas_nblocks(f), f.nrhs);
+  hipLaunchKernelGGL(k_accum_x, grid, dim3(BT), 0, st, x64, x32, f);
+  return hipGetLastError();
+}
+
+}  // namespace wd

@@ -1,0 +1,310 @@
+// Hopping term of the Wilson-Dirac operator on packed half spinors
+// (Sec. 2.3; even-odd blocks of Sec. 5.3.3):
+//   out(x) = alpha x_add(x) + beta * H in (x),
+//   H in (x) = -1/2 sum_mu [ (1 - g_mu) U_R(x,mu) in(x+mu) + (1 + g_mu) U_R(x-mu,mu)^+ in(x-mu) ],
+// for the sites x of one parity.  The dagger form swaps the two projectors.
+//
+// Two kernels compute the same thing:
+//  * k_hop_sp: one lane per output site; the whole spinor accumulator, the
+//    projected neighbour two-spinor and one link row live in registers.
+//    Good for small d_R.
+//  * k_hop_cs: one wavefront per colour row a of a tile of 64 consecutive
+//    sites (block = 64 * d_R lanes).  Lane (site, a) loads colour component a
+//    of the neighbour spinor, spin-projects it to two complex numbers and
+//    publishes them in LDS; after one barrier every lane reads the full
+//    projected two-spinor of its site and applies row a of U (or column a of
+//    U^+), which it loads itself -- each link entry is read exactly once, by
+//    one lane, coalesced across the 64 sites of the wavefront.  Register use
+//    no longer grows with d_R^2, which is what limits the site-parallel form
+//    for large representations.
+#include "wd_common.h"
+#include "wd_kernels.h"
+
+namespace wd {
+
+// ------------------------------------------------------------ tile mapping
+// Blocks are dispatched round-robin over the 8 XCDs of the chip.  With
+// remapping, XCD k receives a contiguous range of tiles, so the neighbours a
+// tile reads (mostly in nearby tiles) stay in that XCD's L2.
+__device__ __forceinline__ int tile_of_block(int b, int ntiles, int remap) {
+  if (!remap) return b;
+  const int q = ntiles >> 3, rmd = ntiles & 7;
+  const int x = b & 7, j = b >> 3;
+  return x * q + (x < rmd ? x : rmd) + j;
+}
+
+template <typename T, bool REAL>
+struct LinkT {
+  using type = cplx<T>;
+};
+template <typename T>
+struct LinkT<T, true> {
+  using type = T;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> link_mac(cplx<T> u, cplx<T> h, cplx<T> acc, bool conjugate) {
+  return conjugate ? cfma_conj(u, h, acc) : cfma(u, h, acc);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> link_mac(T u, cplx<T> h, cplx<T> acc, bool) {
+  return rfma(u, h, acc);
+}
+
+// ------------------------------------------------------- site-parallel form
+template <int D, bool REAL, typename T, int MU, int SIG, bool BWD>
+__device__ __forceinline__ void sp_dir(cplx<T> (&acc)[4][D], const cplx<T> *__restrict__ in, int stride, int nb,
+                                       const typename LinkT<T, REAL>::type *__restrict__ lk, int lsite) {
+  cplx<T> h[2][D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    cplx<T> p[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) p[s] = in[(size_t)(s * D + c) * stride + nb];
+    h[0][c] = p[0] + ipow<PROJ_PH(MU, SIG, 0)>(p[2 + ECOL(MU, 0)]);
+    h[1][c] = p[1] + ipow<PROJ_PH(MU, SIG, 1)>(p[2 + ECOL(MU, 1)]);
+  }
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    cplx<T> chi[2] = {mk<T>(0, 0), mk<T>(0, 0)};
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      // forward: U_ab;  backward: (U^+)_ab = conj(U_ba)
+      const auto u = lk[(size_t)(BWD ? b * D + a : a * D + b) * stride + lsite];
+      chi[0] = link_mac(u, h[0][b], chi[0], BWD);
+      chi[1] = link_mac(u, h[1][b], chi[1], BWD);
+    }
+    acc[0][a] = acc[0][a] + chi[0];
+    acc[1][a] = acc[1][a] + chi[1];
+    acc[2][a] = acc[2][a] + ipow<RECON_PH(MU, SIG, 0)>(chi[RECON_SRC(MU, 0)]);
+    acc[3][a] = acc[3][a] + ipow<RECON_PH(MU, SIG, 1)>(chi[RECON_SRC(MU, 1)]);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int D, bool REAL, typename T, bool DAG, int MU>
+__device__ __forceinline__ void sp_mu(cplx<T> (&acc)[4][D], const HopArgs &a, const cplx<T> *in, int i, int t,
+                                      int x, int y, int z) {
+  using L = typename LinkT<T, REAL>::type;
+  const L *links = static_cast<const L *>(a.links);
+  const size_t lstride = (size_t)D * D * a.g.stride;
+  constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
+  const int nbf = nb_index(a.g, t, x, y, z, MU, 1);
+  sp_dir<D, REAL, T, MU, SF, false>(acc, in, a.g.stride, nbf, links + (size_t)(a.parity * 4 + MU) * lstride, i);
+  const int nbb = nb_index(a.g, t, x, y, z, MU, 0);
+  sp_dir<D, REAL, T, MU, -SF, true>(acc, in, a.g.stride, nbb, links + (size_t)((1 - a.parity) * 4 + MU) * lstride,
+                                    nbb);
+}
+
+template <int D, bool REAL, typename T, bool DAG, int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_hop_sp(HopArgs a) {
+  const int ntiles = gridDim.x;
+  const int tile = tile_of_block(blockIdx.x, ntiles, a.xcd_remap);
+  const int i = tile * 256 + threadIdx.x;
+  const int r = blockIdx.y;
+  const size_t rstride = (size_t)4 * D * a.g.stride;
+  // Lanes past the last site recompute the last site and store into the row
+  // padding (stride is a multiple of 256), so that no branch separates the
+  // arithmetic from its stores.
+  const bool valid = i < a.g.Vh;
+  const int is = valid ? i : a.g.Vh - 1;
+  const cplx<T> *in = static_cast<const cplx<T> *>(a.in) + r * rstride;
+  int t, x, y, z;
+  cb_coords(a.g, is, a.parity, t, x, y, z);
+  cplx<T> acc[4][D];
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[s][c] = mk<T>(0, 0);
+  sp_mu<D, REAL, T, DAG, 0>(acc, a, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 1>(acc, a, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 2>(acc, a, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 3>(acc, a, in, is, t, x, y, z);
+  cplx<T> *out = static_cast<cplx<T> *>(a.out) + r * rstride;
+  const cplx<T> *xa = a.xadd ? static_cast<const cplx<T> *>(a.xadd) + r * rstride : nullptr;
+  const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
+  double nrm = 0.0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const size_t o = (size_t)(s * D + c) * a.g.stride + i;
+      cplx<T> v = cb * acc[s][c];
+      if (xa) {
+        const cplx<T> xv = xa[o];
+        v.re = fma(ca, xv.re, v.re);
+        v.im = fma(ca, xv.im, v.im);
+      }
+      out[o] = v;
+      nrm += (double)v.re * v.re + (double)v.im * v.im;
+    }
+  if (a.partial) {
+    __shared__ double sh[4];
+    const double s = block_sum(valid ? nrm : 0.0, sh);
+    if (threadIdx.x == 0) a.partial[(size_t)r * ntiles + tile] = s;
+  }
+}
+
+// ------------------------------------------------------ colour-split form
+template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, int NR>
+__device__ __forceinline__ void cs_dir(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[2][D][64], const HopArgs &a,
+                                       const cplx<T> *in0, size_t rstride, int nb, int lsite, int row,
+                                       int lane) {
+  using L = typename LinkT<T, REAL>::type;
+  const int stride = a.g.stride;
+  const int lpar = BWD ? 1 - a.parity : a.parity;
+  const L *lk = static_cast<const L *>(a.links) + (size_t)(lpar * 4 + MU) * D * D * stride;
+  // Link entries this lane needs: row `row` of U (forward) or column `row` of U (backward, for U^+).
+  L u[D];
+#pragma unroll
+  for (int b = 0; b < D; ++b) u[b] = lk[(size_t)(BWD ? b * D + row : row * D + b) * stride + lsite];
+  // Colour component `row` of the neighbour spinor, spin-projected.
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const cplx<T> *in = in0 + k * rstride;
+    cplx<T> p[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) p[s] = in[(size_t)(s * D + row) * stride + nb];
+    hs[k][0][row][lane] = p[0] + ipow<PROJ_PH(MU, SIG, 0)>(p[2 + ECOL(MU, 0)]);
+    hs[k][1][row][lane] = p[1] + ipow<PROJ_PH(MU, SIG, 1)>(p[2 + ECOL(MU, 1)]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    cplx<T> chi[2] = {mk<T>(0, 0), mk<T>(0, 0)};
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      chi[0] = link_mac(u[b], hs[k][0][b][lane], chi[0], BWD);
+      chi[1] = link_mac(u[b], hs[k][1][b][lane], chi[1], BWD);
+    }
+    acc[k][0] = acc[k][0] + chi[0];
+    acc[k][1] = acc[k][1] + chi[1];
+    acc[k][2] = acc[k][2] + ipow<RECON_PH(MU, SIG, 0)>(chi[RECON_SRC(MU, 0)]);
+    acc[k][3] = acc[k][3] + ipow<RECON_PH(MU, SIG, 1)>(chi[RECON_SRC(MU, 1)]);
+  }
+  // keep each direction's arithmetic next to its barrier
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int D, bool REAL, typename T, bool DAG, int NR, int W>
+__global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) void k_hop_cs(HopArgs a) {
+  __shared__ cplx<T> hs[2][NR][2][D][64];
+  __shared__ double sh[D];
+  const int ntiles = gridDim.x;
+  const int tile = tile_of_block(blockIdx.x, ntiles, a.xcd_remap);
+  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int i = tile * 64 + lane;
+  const bool valid = i < a.g.Vh;
+  const int is = valid ? i : a.g.Vh - 1;   // lanes past the end: see k_hop_sp
+  const int r0 = blockIdx.y * NR;
+  const size_t rstride = (size_t)4 * D * a.g.stride;
+  const cplx<T> *in0 = static_cast<const cplx<T> *>(a.in) + r0 * rstride;
+  int t, x, y, z;
+  cb_coords(a.g, is, a.parity, t, x, y, z);
+  cplx<T> acc[NR][4];
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[k][s] = mk<T>(0, 0);
+  constexpr int SF = DAG ? -1 : 1;
+#define WD_CS_MU(MU, BUF)                                                                                   \
+  cs_dir<D, REAL, T, MU, SF, false, NR>(acc, hs[0 + BUF], a, in0, rstride, nb_index(a.g, t, x, y, z, MU, 1), \
+                                        is, row, lane);                                                       \
+  {                                                                                                           \
+    const int nbb = nb_index(a.g, t, x, y, z, MU, 0);                                                         \
+    cs_dir<D, REAL, T, MU, -SF, true, NR>(acc, hs[1 - BUF], a, in0, rstride, nbb, nbb, row, lane);             \
+  }
+  WD_CS_MU(0, 0)
+  WD_CS_MU(1, 0)
+  WD_CS_MU(2, 0)
+  WD_CS_MU(3, 0)
+#undef WD_CS_MU
+  const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    double nrm = 0.0;
+    cplx<T> *out = static_cast<cplx<T> *>(a.out) + (r0 + k) * rstride;
+    const cplx<T> *xa = a.xadd ? static_cast<const cplx<T> *>(a.xadd) + (r0 + k) * rstride : nullptr;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const size_t o = (size_t)(s * D + row) * a.g.stride + i;   // i < stride always
+      cplx<T> v = cb * acc[k][s];
+      if (xa) {
+        const cplx<T> xv = xa[o];
+        v.re = fma(ca, xv.re, v.re);
+        v.im = fma(ca, xv.im, v.im);
+      }
+      out[o] = v;
+      nrm += (double)v.re * v.re + (double)v.im * v.im;
+    }
+    if (a.partial) {
+      const double s = block_sum(valid ? nrm : 0.0, sh);
+      if (threadIdx.x == 0) a.partial[(size_t)(r0 + k) * ntiles + tile] = s;
+    }
+  }
+}
+
+// -------------------------------------------------------------- dispatch
+// Waves per SIMD the register allocator is asked to allow (VGPR budget
+// 512 / W per lane), chosen per (d_R, precision) as the largest value that
+// compiles without spills for the colour-split kernel.
+constexpr int cs_waves(int D, bool dbl) {
+  return dbl ? (D <= 3 ? 4 : D <= 8 ? 3 : 2) : (D <= 4 ? 6 : D <= 6 ? 5 : D <= 10 ? 4 : 3);
+}
+constexpr int sp_waves(int D, bool dbl) { return dbl ? 2 : (D <= 2 ? 4 : 2); }
+template <int D, bool REAL, typename T, bool DAG>
+static hipError_t launch_typed(const HopArgs &a, int nrhs, int variant, hipStream_t st, int *nblk) {
+  if (variant == HOP_SITE) {
+    if constexpr (D <= 6) {
+      dim3 grid((a.g.Vh + 255) / 256, nrhs);
+      *nblk = grid.x;
+      hipLaunchKernelGGL((k_hop_sp<D, REAL, T, DAG, sp_waves(D, sizeof(T) == 8)>), grid, dim3(256), 0, st, a);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
+  dim3 grid((a.g.Vh + 63) / 64, nrhs);
+  *nblk = grid.x;
+  hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, 1, cs_waves(D, sizeof(T) == 8)>), grid, dim3(64 * D), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int D, bool REAL>
+static hipError_t launch_d(const HopArgs &a, int prec, int dagger, int nrhs, int variant, hipStream_t st,
+                           int *nblk) {
+  if (prec == 0)
+    return dagger ? launch_typed<D, REAL, double, true>(a, nrhs, variant, st, nblk)
+                  : launch_typed<D, REAL, double, false>(a, nrhs, variant, st, nblk);
+  return dagger ? launch_typed<D, REAL, float, true>(a, nrhs, variant, st, nblk)
+                : launch_typed<D, REAL, float, false>(a, nrhs, variant, st, nblk);
+}
+
+hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant,
+                      hipStream_t st, int *nblk) {
+  if (real) {
+    switch (d) {
+      case 3: return launch_d<3, true>(a, prec, dagger, nrhs, variant, st, nblk);
+      case 8: return launch_d<8, true>(a, prec, dagger, nrhs, variant, st, nblk);
+      case 15: return launch_d<15, true>(a, prec, dagger, nrhs, variant, st, nblk);
+    }
+  } else {
+    switch (d) {
+      case 2: return launch_d<2, false>(a, prec, dagger, nrhs, variant, st, nblk);
+      case 3: return launch_d<3, false>(a, prec, dagger, nrhs, variant, st, nblk);
+      case 4: return launch_d<4, false>(a, prec, dagger, nrhs, variant, st, nblk);
+      case 6: return launch_d<6, false>(a, prec, dagger, nrhs, variant, st, nblk);
+      case 10: return launch_d<10, false>(a, prec, dagger, nrhs, variant, st, nblk);
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+int hop_nblocks(int Vh, int d, int variant) {
+  (void)d;
+  return variant == HOP_SITE ? (Vh + 255) / 256 : (Vh + 63) / 64;
+}
+
+bool hop_variant_ok(int d, int variant) { return variant == HOP_COLOUR || d <= 6; }
+
+}  // namespace wd

@@ -1,0 +1,261 @@
+// Represented links U -> U_R (Sec. 2.3), the fermion boundary phase folded
+// into the links that cross the boundary (Sec. 6.3.1), and the packing of
+// fields between the caller's canonical layout and the structure-of-arrays
+// layout of the kernels.
+//
+// Bases (fixed conventions of this library):
+//  * fundamental generators T^a: for each pair j < k in lexicographic order
+//    (E_jk + E_kj)/2 then (-i E_jk + i E_kj)/2; then for k = 1..N-1
+//    diag(1,..,1,-k,0,..)/sqrt(2k(k+1));
+//  * ADJ: (U_R)_ab = 2 tr(T^a U T^b U^+), evaluated from the few non-zero
+//    entries of each generator;
+//  * SYM / 2AS: orthonormal basis of symmetric / antisymmetric matrices
+//    e_(ab) (a <= b / a < b, lexicographic), e_(aa) = E_aa, e_(ab) =
+//    (E_ab +- E_ba)/sqrt 2, acting as M -> U M U^T.  Expanding
+//    tr(e_(ab)^+ U e_(cd) U^T) gives the closed forms used below:
+//      SYM, a<b, c<d:   U_ac U_bd + U_ad U_bc
+//      SYM, a<b, c=d:   sqrt2 U_ac U_bc
+//      SYM, a=b, c<d:   sqrt2 U_ac U_ad
+//      SYM, a=b, c=d:   U_ac^2
+//      2AS, a<b, c<d:   U_ac U_bd - U_ad U_bc
+#include "wd_common.h"
+#include "wd_kernels.h"
+
+namespace wd {
+
+constexpr int rep_dim(int N, int rep) {
+  return rep == 0 ? N : rep == 1 ? N * N - 1 : rep == 2 ? N * (N + 1) / 2 : N * (N - 1) / 2;
+}
+
+// Non-zero entries of fundamental generator a: returns count, fills (row, col, value).
+template <int N>
+__device__ __forceinline__ int gen_nz(int a, int (&ri)[N], int (&ci)[N], cplx<double> (&v)[N]) {
+  constexpr int noff = N * (N - 1);
+  if (a < noff) {
+    int p = a >> 1, j = 0;
+    while (p >= N - 1 - j) {
+      p -= N - 1 - j;
+      ++j;
+    }
+    const int k = j + 1 + p;
+    ri[0] = j; ci[0] = k;
+    ri[1] = k; ci[1] = j;
+    if ((a & 1) == 0) {
+      v[0] = mk(0.5, 0.0);
+      v[1] = mk(0.5, 0.0);
+    } else {
+      v[0] = mk(0.0, -0.5);
+      v[1] = mk(0.0, 0.5);
+    }
+    return 2;
+  }
+  const int kk = a - noff + 1;
+  const double nrm = 1.0 / sqrt(2.0 * kk * (kk + 1));
+  for (int i = 0; i < kk; ++i) {
+    ri[i] = i; ci[i] = i;
+    v[i] = mk(nrm, 0.0);
+  }
+  ri[kk] = kk; ci[kk] = kk;
+  v[kk] = mk(-kk * nrm, 0.0);
+  return kk + 1;
+}
+
+// Index pair (a, b) of two-index basis element A (a <= b for SYM, a < b for 2AS).
+template <int N, bool SYM>
+__device__ __forceinline__ void pair_of(int A, int &a, int &b) {
+  a = 0;
+  int rem = A;
+  while (rem >= (SYM ? N - a : N - 1 - a)) {
+    rem -= SYM ? N - a : N - 1 - a;
+    ++a;
+  }
+  b = a + rem + (SYM ? 0 : 1);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_entry(void *base, size_t off, cplx<double> v, double sign, bool real) {
+  if (real) static_cast<T *>(base)[off] = (T)(sign * v.re);
+  else static_cast<cplx<T> *>(base)[off] = mk<T>((T)(sign * v.re), (T)(sign * v.im));
+}
+
+template <int N, int REP, typename T>
+__global__ __launch_bounds__(256) void k_rep_links(const cplx<double> *__restrict__ U, void *__restrict__ UR,
+                                                    Geom g) {
+  constexpr int D = rep_dim(N, REP);
+  const int V = 2 * g.Vh;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 4 * V) return;
+  const int lex = gid >> 2, mu = gid & 3;
+  int r = lex;
+  const int z = r % g.Z; r /= g.Z;
+  const int y = r % g.Y; r /= g.Y;
+  const int x = r % g.X;
+  const int t = r / g.X;
+  const int par = (t + x + y + z) & 1;
+  const int cb = lex >> 1;
+  const int c[4] = {t, x, y, z};
+  const int L[4] = {g.T, g.X, g.Y, g.Z};
+  const double sign = (c[mu] == L[mu] - 1) ? (double)g.bc[mu] : 1.0;
+  cplx<double> u[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) u[i][j] = U[(size_t)gid * N * N + i * N + j];
+  const size_t base = (size_t)(par * 4 + mu) * D * D * g.stride + cb;
+  const size_t es = g.stride;
+  if constexpr (REP == 0) {
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+      for (int b = 0; b < N; ++b) store_entry<T>(UR, base + (a * N + b) * es, u[a][b], sign, false);
+  } else if constexpr (REP == 1) {
+    int ra[N], ca[N], rb[N], cbi[N];
+    cplx<double> va[N], vb[N];
+    for (int A = 0; A < D; ++A) {
+      const int na = gen_nz<N>(A, ra, ca, va);
+      for (int B = 0; B < D; ++B) {
+        const int nb = gen_nz<N>(B, rb, cbi, vb);
+        // 2 tr(T^A U T^B U^+) = 2 sum T^A_ij U_jk T^B_kl conj(U_il)
+        cplx<double> s = mk(0.0, 0.0);
+        for (int p = 0; p < na; ++p)
+          for (int q = 0; q < nb; ++q) {
+            const cplx<double> w = cmul(cmul(va[p], vb[q]), u[ca[p]][rb[q]]);
+            s = cfma_conj(u[ra[p]][cbi[q]], w, s);
+          }
+        store_entry<T>(UR, base + (size_t)(A * D + B) * es, mk(2.0 * s.re, 0.0), sign, true);
+      }
+    }
+  } else {
+    constexpr bool SYM = REP == 2;
+    const double rt2 = 1.4142135623730951;
+    for (int A = 0; A < D; ++A) {
+      int a, b;
+      pair_of<N, SYM>(A, a, b);
+      for (int B = 0; B < D; ++B) {
+        int cc, dd;
+        pair_of<N, SYM>(B, cc, dd);
+        cplx<double> v;
+        if (!SYM) {
+          v = cmul(u[a][cc], u[b][dd]) - cmul(u[a][dd], u[b][cc]);
+        } else if (a < b && cc < dd) {
+          v = cmul(u[a][cc], u[b][dd]) + cmul(u[a][dd], u[b][cc]);
+        } else if (a < b) {
+          v = rt2 * cmul(u[a][cc], u[b][cc]);
+        } else if (cc < dd) {
+          v = rt2 * cmul(u[a][cc], u[a][dd]);
+        } else {
+          v = cmul(u[a][cc], u[a][cc]);
+        }
+        store_entry<T>(UR, base + (size_t)(A * D + B) * es, v, sign, false);
+      }
+    }
+  }
+}
+
+template <int N, int REP>
+static hipError_t rep_launch(const void *U, void *UR, const Geom &g, int prec, hipStream_t st) {
+  const int n = 8 * g.Vh;
+  dim3 grid((n + 255) / 256);
+  if (prec == 0)
+    hipLaunchKernelGGL((k_rep_links<N, REP, double>), grid, dim3(256), 0, st, (const cplx<double> *)U, UR, g);
+  else
+    hipLaunchKernelGGL((k_rep_links<N, REP, float>), grid, dim3(256), 0, st, (const cplx<double> *)U, UR, g);
+  return hipGetLastError();
+}
+
+template <int N>
+static hipError_t rep_launch_n(const void *U, void *UR, const Geom &g, int rep, int prec, hipStream_t st) {
+  switch (rep) {
+    case 0: return rep_launch<N, 0>(U, UR, g, prec, st);
+    case 1: return rep_launch<N, 1>(U, UR, g, prec, st);
+    case 2: return rep_launch<N, 2>(U, UR, g, prec, st);
+    case 3:
+      if constexpr (N > 2) return rep_launch<N, 3>(U, UR, g, prec, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rep_links(const void *U, void *UR, const Geom &g, int N, int rep, int prec, hipStream_t st) {
+  switch (N) {
+    case 2: return rep_launch_n<2>(U, UR, g, rep, prec, st);
+    case 3: return rep_launch_n<3>(U, UR, g, rep, prec, st);
+    case 4: return rep_launch_n<4>(U, UR, g, rep, prec, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+// ------------------------------------------------------------ link unpack
+template <typename T>
+__global__ __launch_bounds__(256) void k_unpack_links(double *__restrict__ out, const void *__restrict__ UR,
+                                                       Geom g, int d, int real) {
+  const int V = 2 * g.Vh;
+  const size_t n = (size_t)4 * V * d * d;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n) return;
+  const int e = gid % (d * d);
+  const size_t link = gid / (d * d);
+  const int lex = (int)(link >> 2), mu = (int)(link & 3);
+  int r = lex;
+  const int z = r % g.Z; r /= g.Z;
+  const int y = r % g.Y; r /= g.Y;
+  const int x = r % g.X;
+  const int t = r / g.X;
+  const int par = (t + x + y + z) & 1;
+  const size_t src = ((size_t)(par * 4 + mu) * d * d + e) * g.stride + (lex >> 1);
+  if (real) {
+    out[gid] = (double)static_cast<const T *>(UR)[src];
+  } else {
+    const cplx<T> v = static_cast<const cplx<T> *>(UR)[src];
+    out[2 * gid] = (double)v.re;
+    out[2 * gid + 1] = (double)v.im;
+  }
+}
+
+hipError_t launch_unpack_links(void *canon, const void *UR, const Geom &g, int d, int real, int prec,
+                               hipStream_t st) {
+  const size_t n = (size_t)8 * g.Vh * d * d;
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (prec == 0)
+    hipLaunchKernelGGL(k_unpack_links<double>, grid, dim3(256), 0, st, (double *)canon, UR, g, d, real);
+  else
+    hipLaunchKernelGGL(k_unpack_links<float>, grid, dim3(256), 0, st, (double *)canon, UR, g, d, real);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- spinor packing
+// Thread per (rhs, site of the parity, component); the packed side is the
+// coalesced one.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_spinor(cplx<T> *__restrict__ packed, cplx<T> *__restrict__ canon,
+                                                      Geom g, int d, int parity, int nrhs, int unpack) {
+  const int ncomp = 4 * d;
+  const size_t n = (size_t)nrhs * ncomp * g.Vh;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n) return;
+  const int i = (int)(gid % g.Vh);
+  const size_t rc = gid / g.Vh;
+  const int comp = (int)(rc % ncomp);
+  const int r = (int)(rc / ncomp);
+  int t, x, y, z;
+  cb_coords(g, i, parity, t, x, y, z);
+  const size_t lex = (((size_t)t * g.X + x) * g.Y + y) * g.Z + z;
+  const size_t co = ((size_t)r * 2 * g.Vh + lex) * ncomp + comp;
+  const size_t po = ((size_t)r * ncomp + comp) * g.stride + i;
+  if (unpack) canon[co] = packed[po];
+  else packed[po] = canon[co];
+}
+
+hipError_t launch_pack_spinor(void *packed, const void *canon, const Geom &g, int d, int parity, int nrhs,
+                              int prec, int unpack, hipStream_t st) {
+  const size_t n = (size_t)nrhs * 4 * d * g.Vh;
+  dim3 grid((unsigned)((n + 255) / 256));
+  if (prec == 0)
+    hipLaunchKernelGGL(k_pack_spinor<double>, grid, dim3(256), 0, st, (cplx<double> *)packed,
+                       (cplx<double> *)canon, g, d, parity, nrhs, unpack);
+  else
+    hipLaunchKernelGGL(k_pack_spinor<float>, grid, dim3(256), 0, st, (cplx<float> *)packed,
+                       (cplx<float> *)canon, g, d, parity, nrhs, unpack);
+  return hipGetLastError();
+}
+
+}  // namespace wd

@@ -1,0 +1,245 @@
+"""ctypes binding of libwdirac.so.
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  PyTorch supplies device memory (tensors) and the current HIP
+stream.  Function names are those of the C ABI without the ``wdirac_``
+prefix; see include/wdirac.h for the meaning of every argument.
+
+Importing this module raises ImportError if libwdirac.so has not been built
+(``__graft_entry__.build()`` or ``python -m paper_2503_06721_amd.build``).
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libwdirac.so')
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f'{LIB_PATH} is not built; run python -m paper_2503_06721_amd.build')
+_lib = ctypes.CDLL(LIB_PATH)
+
+# enums of include/wdirac.h
+OK, EINVAL, EUNSUPPORTED, EHIP, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5
+FUND, ADJ, SYM, ASYM = 0, 1, 2, 3
+F64, F32 = 0, 1
+CG_F64, CG_MIXED = 0, 1
+FIELD_HALF_SPINOR, FIELD_LINKS = 0, 1
+OP_DHAT, OP_CG, OP_FORCE, OP_NORM = 0, 1, 2, 3
+OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA = 0, 1, 2, 3, 4
+HOP_SITE, HOP_COLOUR = 0, 1
+REP_CODES = {'FUND': FUND, 'ADJ': ADJ, 'SYM': SYM, '2AS': ASYM}
+STATUS_NAMES = {OK: 'OK', EINVAL: 'EINVAL', EUNSUPPORTED: 'EUNSUPPORTED', EHIP: 'EHIP',
+                ENOCONV: 'ENOCONV', EBREAKDOWN: 'EBREAKDOWN'}
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [('dims', ctypes.c_int32 * 4), ('bc', ctypes.c_int32 * 4)]
+
+
+class CgStats(ctypes.Structure):
+    _fields_ = [('iters', ctypes.c_int32), ('reliable_updates', ctypes.c_int32), ('hops', ctypes.c_int32),
+                ('status', ctypes.c_int32), ('true_rel_resid', ctypes.c_double), ('seconds', ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_SIGS = {
+    'wdirac_create': (_I, [ctypes.POINTER(_P), _I, _I, ctypes.POINTER(Geom)]),
+    'wdirac_destroy': (_I, [_P]),
+    'wdirac_set_option': (_I, [_P, _I, _D]),
+    'wdirac_rep_info': (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    'wdirac_field_bytes': (ctypes.c_size_t, [_P, _I, _I, _I]),
+    'wdirac_workspace_bytes': (ctypes.c_size_t, [_P, _I, _I, _I]),
+    'wdirac_pack_spinor': (_I, [_P, _P, _P, _I, _I, _I, _P]),
+    'wdirac_unpack_spinor': (_I, [_P, _P, _P, _I, _I, _I, _P]),
+    'wdirac_rep_links': (_I, [_P, _P, _P, _I, _P]),
+    'wdirac_unpack_links': (_I, [_P, _P, _P, _I, _P]),
+    'wdirac_dslash_eo': (_I, [_P, _P, _P, _P, _I, _I, _I, _D, _P, _D, _I, _P]),
+    'wdirac_apply_Mee': (_I, [_P, _P, _P, _D, _I, _I, _I, _P]),
+    'wdirac_apply_Moo': (_I, [_P, _P, _P, _D, _I, _I, _I, _P]),
+    'wdirac_apply_dhat': (_I, [_P, _P, _P, _P, _D, _I, _I, _I, _P, _P]),
+    'wdirac_eo_source': (_I, [_P, _P, _P, _P, _P, _D, _I, _P]),
+    'wdirac_eo_reconstruct': (_I, [_P, _P, _P, _P, _P, _D, _I, _P]),
+    'wdirac_norm2': (_I, [_P, ctypes.POINTER(_D), _P, _I, _I, _P, _P]),
+    'wdirac_cg_eo': (_I, [_P, _P, _P, _P, _P, _D, _D, _I, _I, _I, _P, ctypes.POINTER(CgStats), _P]),
+    'wdirac_force_eo': (_I, [_P, _P, _P, _P, _D, _D, _I, _P, _P]),
+    'wdirac_last_error': (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class WdiracError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = _lib.wdirac_last_error().decode()
+        super().__init__(f'{where}: {STATUS_NAMES.get(code, code)}: {msg}')
+
+
+def last_error():
+    return _lib.wdirac_last_error().decode()
+
+
+def _check(code, where, allow=()):
+    if code != OK and code not in allow:
+        raise WdiracError(code, where)
+    return code
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError('libwdirac fields must be GPU tensors')
+    if not t.is_contiguous():
+        raise ValueError('libwdirac fields must be contiguous')
+    return t.data_ptr()
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+class Lattice:
+    """A libwdirac context: SU(N) fermions in representation `rep` on `dims`.
+
+    dims = (T, X, Y, Z), bc = per-direction fermion boundary phase (+1/-1)."""
+
+    def __init__(self, N, rep, dims, bc=(-1, 1, 1, 1)):
+        self.N = int(N)
+        self.rep_name = rep if isinstance(rep, str) else {v: k for k, v in REP_CODES.items()}[rep]
+        self.rep = REP_CODES[self.rep_name] if isinstance(rep, str) else int(rep)
+        self.dims = tuple(int(x) for x in dims)
+        self.bc = tuple(int(x) for x in bc)
+        g = Geom((ctypes.c_int32 * 4)(*self.dims), (ctypes.c_int32 * 4)(*self.bc))
+        h = _P()
+        _check(_lib.wdirac_create(ctypes.byref(h), self.N, self.rep, ctypes.byref(g)), 'create')
+        self._h = h
+        d, real = _I(), _I()
+        _check(_lib.wdirac_rep_info(h, ctypes.byref(d), ctypes.byref(real)), 'rep_info')
+        self.d, self.real = d.value, bool(real.value)
+        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.Vh = self.V // 2
+
+    def __del__(self):
+        h = getattr(self, '_h', None)
+        if h:
+            _lib.wdirac_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------ sizes
+    def field_bytes(self, kind, nrhs=1, prec=F64):
+        return _lib.wdirac_field_bytes(self._h, kind, nrhs, prec)
+
+    def workspace_bytes(self, op, nrhs=1, prec=F64):
+        return _lib.wdirac_workspace_bytes(self._h, op, nrhs, prec)
+
+    def set_option(self, option, value):
+        _check(_lib.wdirac_set_option(self._h, option, float(value)), 'set_option')
+
+    def new_half(self, nrhs=1, prec=F64, zero=True):
+        n = self.field_bytes(FIELD_HALF_SPINOR, nrhs, prec)
+        f = torch.zeros if zero else torch.empty
+        return f(n, dtype=torch.uint8, device='cuda')
+
+    def new_links(self, prec=F64):
+        return torch.empty(self.field_bytes(FIELD_LINKS, 1, prec), dtype=torch.uint8, device='cuda')
+
+    def new_workspace(self, op, nrhs=1, prec=F64):
+        return torch.empty(self.workspace_bytes(op, nrhs, prec), dtype=torch.uint8, device='cuda')
+
+    # ---------------------------------------------------------- layouts
+    def pack_spinor(self, packed, canon, parity, nrhs=1, prec=F64, stream=None):
+        _check(_lib.wdirac_pack_spinor(self._h, _ptr(packed), _ptr(canon), parity, nrhs, prec, _stream(stream)),
+               'pack_spinor')
+
+    def unpack_spinor(self, canon, packed, parity, nrhs=1, prec=F64, stream=None):
+        _check(_lib.wdirac_unpack_spinor(self._h, _ptr(canon), _ptr(packed), parity, nrhs, prec, _stream(stream)),
+               'unpack_spinor')
+
+    def rep_links(self, UR, U, prec=F64, stream=None):
+        _check(_lib.wdirac_rep_links(self._h, _ptr(UR), _ptr(U), prec, _stream(stream)), 'rep_links')
+
+    def unpack_links(self, UR_canon, UR, prec=F64, stream=None):
+        _check(_lib.wdirac_unpack_links(self._h, _ptr(UR_canon), _ptr(UR), prec, _stream(stream)), 'unpack_links')
+
+    # --------------------------------------------------------- operators
+    def dslash_eo(self, out, inp, UR, out_parity, dagger=0, nrhs=1, alpha=0.0, x_add=None, beta=1.0, prec=F64,
+                  stream=None):
+        _check(_lib.wdirac_dslash_eo(self._h, _ptr(out), _ptr(inp), _ptr(UR), out_parity, dagger, nrhs,
+                                     float(alpha), _ptr(x_add), float(beta), prec, _stream(stream)), 'dslash_eo')
+
+    def apply_Mee(self, out, inp, m0, inverse=0, nrhs=1, prec=F64, stream=None):
+        _check(_lib.wdirac_apply_Mee(self._h, _ptr(out), _ptr(inp), float(m0), inverse, nrhs, prec,
+                                     _stream(stream)), 'apply_Mee')
+
+    def apply_Moo(self, out, inp, m0, inverse=0, nrhs=1, prec=F64, stream=None):
+        _check(_lib.wdirac_apply_Moo(self._h, _ptr(out), _ptr(inp), float(m0), inverse, nrhs, prec,
+                                     _stream(stream)), 'apply_Moo')
+
+    def apply_dhat(self, out, inp, UR, m0, dagger=0, nrhs=1, prec=F64, workspace=None, stream=None):
+        ws = workspace if workspace is not None else self.new_workspace(OP_DHAT, nrhs, prec)
+        _check(_lib.wdirac_apply_dhat(self._h, _ptr(out), _ptr(inp), _ptr(UR), float(m0), dagger, nrhs, prec,
+                                      _ptr(ws), _stream(stream)), 'apply_dhat')
+
+    def eo_source(self, b_e, eta_e, eta_o, UR, m0, nrhs=1, stream=None):
+        _check(_lib.wdirac_eo_source(self._h, _ptr(b_e), _ptr(eta_e), _ptr(eta_o), _ptr(UR), float(m0), nrhs,
+                                     _stream(stream)), 'eo_source')
+
+    def eo_reconstruct(self, psi_o, psi_e, eta_o, UR, m0, nrhs=1, stream=None):
+        _check(_lib.wdirac_eo_reconstruct(self._h, _ptr(psi_o), _ptr(psi_e), _ptr(eta_o), _ptr(UR), float(m0),
+                                          nrhs, _stream(stream)), 'eo_reconstruct')
+
+    def norm2(self, v, nrhs=1, prec=F64, workspace=None, stream=None):
+        ws = workspace if workspace is not None else self.new_workspace(OP_NORM, nrhs, prec)
+        out = (_D * nrhs)()
+        _check(_lib.wdirac_norm2(self._h, out, _ptr(v), nrhs, prec, _ptr(ws), _stream(stream)), 'norm2')
+        return list(out)
+
+    def cg_eo(self, x, b, UR64, m0, tol=1e-10, maxit=10000, nrhs=1, mode=CG_F64, UR32=None, workspace=None,
+              stream=None, allow=(ENOCONV, EBREAKDOWN)):
+        """Returns (status, [stats dict per rhs])."""
+        ws = workspace if workspace is not None else self.new_workspace(OP_CG, nrhs, mode)
+        stats = (CgStats * nrhs)()
+        rc = _lib.wdirac_cg_eo(self._h, _ptr(x), _ptr(b), _ptr(UR64), _ptr(UR32), float(m0), float(tol),
+                               int(maxit), nrhs, mode, _ptr(ws), stats, _stream(stream))
+        _check(rc, 'cg_eo', allow)
+        return rc, [s.as_dict() for s in stats]
+
+    def force_eo(self, P, x_e, UR64, m0, scale=1.0, accumulate=0, workspace=None, stream=None):
+        ws = workspace if workspace is not None else self.new_workspace(OP_FORCE, 1, F64)
+        _check(_lib.wdirac_force_eo(self._h, _ptr(P), _ptr(x_e), _ptr(UR64), float(m0), float(scale), accumulate,
+                                    _ptr(ws), _stream(stream)), 'force_eo')
+
+    # ------------------------------------------------------- conveniences
+    def spinor_dtype(self, prec):
+        return torch.complex128 if prec == F64 else torch.complex64
+
+    def pack_half(self, canon_full, parity, nrhs=1, prec=F64):
+        """New packed half field holding the `parity` sites of a canonical full spinor tensor."""
+        out = self.new_half(nrhs, prec)
+        self.pack_spinor(out, canon_full.contiguous(), parity, nrhs, prec)
+        return out
+
+    def unpack_half(self, packed, parity, nrhs=1, prec=F64, into=None):
+        """Canonical full spinor tensor (zeros on the other parity) from a packed half field."""
+        shape = (nrhs,) + self.dims + (4, self.d)
+        canon = into if into is not None else torch.zeros(shape, dtype=self.spinor_dtype(prec), device='cuda')
+        self.unpack_spinor(canon, packed, parity, nrhs, prec)
+        return canon
+
+    def links_canonical(self, UR, prec=F64):
+        dt = torch.float64 if self.real else torch.complex128
+        out = torch.empty(self.dims + (4, self.d, self.d), dtype=dt, device='cuda')
+        self.unpack_links(out, UR, prec)
+        return out

@@ -1,0 +1,115 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/wdirac.h declares, and rejects bad arguments on the host before any
+device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, 'include', 'wdirac.h')
+LIB = os.path.join(ROOT, 'paper_2503_06721_amd', 'libwdirac.so')
+
+
+@pytest.fixture(scope='module')
+def W():
+    if not os.path.exists(LIB):
+        from paper_2503_06721_amd import build
+        build.build()
+    from paper_2503_06721_amd import wdirac
+    return wdirac
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r'/\*.*?\*/', '', text, flags=re.S)
+    return sorted(set(re.findall(r'\b(wdirac_\w+)\s*\(', text)))
+
+
+def test_every_declared_symbol_is_exported(W):
+    names = declared_functions()
+    assert len(names) >= 18
+    lib = ctypes.CDLL(W.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def geom(W, dims=(4, 4, 4, 4), bc=(-1, 1, 1, 1)):
+    return W.Geom((ctypes.c_int32 * 4)(*dims), (ctypes.c_int32 * 4)(*bc))
+
+
+def create(W, N, rep, dims=(4, 4, 4, 4), bc=(-1, 1, 1, 1)):
+    h = ctypes.c_void_p()
+    g = geom(W, dims, bc)
+    rc = W._lib.wdirac_create(ctypes.byref(h), N, rep, ctypes.byref(g))
+    return rc, h
+
+
+@pytest.mark.parametrize('N,rep,d,real', [(2, 0, 2, 0), (2, 1, 3, 1), (2, 2, 3, 0), (3, 0, 3, 0), (3, 1, 8, 1),
+                                          (3, 2, 6, 0), (3, 3, 3, 0), (4, 0, 4, 0), (4, 1, 15, 1), (4, 2, 10, 0),
+                                          (4, 3, 6, 0)])
+def test_create_and_rep_info(W, N, rep, d, real):
+    rc, h = create(W, N, rep)
+    assert rc == W.OK
+    dd, rr = ctypes.c_int(), ctypes.c_int()
+    assert W._lib.wdirac_rep_info(h, ctypes.byref(dd), ctypes.byref(rr)) == W.OK
+    assert (dd.value, rr.value) == (d, real)
+    Vh, stride = 128, 256
+    assert W._lib.wdirac_field_bytes(h, W.FIELD_HALF_SPINOR, 1, W.F64) == 4 * d * stride * 16
+    assert W._lib.wdirac_field_bytes(h, W.FIELD_HALF_SPINOR, 3, W.F32) == 3 * 4 * d * stride * 8
+    assert W._lib.wdirac_field_bytes(h, W.FIELD_LINKS, 1, W.F64) == 8 * d * d * stride * 8 * (1 if real else 2)
+    assert W._lib.wdirac_workspace_bytes(h, W.OP_CG, 2, W.CG_MIXED) > W._lib.wdirac_workspace_bytes(h, W.OP_CG, 2,
+                                                                                                     W.CG_F64)
+    assert Vh * 2 == 256
+    assert W._lib.wdirac_destroy(h) == W.OK
+
+
+@pytest.mark.parametrize('N,rep,dims,bc,code', [
+    (2, 3, (4, 4, 4, 4), (1, 1, 1, 1), -2),     # SU(2) 2AS: d_R = 1
+    (5, 0, (4, 4, 4, 4), (1, 1, 1, 1), -2),     # N not built
+    (3, 7, (4, 4, 4, 4), (1, 1, 1, 1), -1),     # unknown rep
+    (3, 0, (4, 3, 4, 4), (1, 1, 1, 1), -1),     # odd extent
+    (3, 0, (0, 4, 4, 4), (1, 1, 1, 1), -1),     # empty lattice
+    (3, 0, (4, 4, 4, 4), (1, 0, 1, 1), -1),     # bc not +-1
+])
+def test_create_rejects(W, N, rep, dims, bc, code):
+    rc, h = create(W, N, rep, dims, bc)
+    assert rc == code
+    assert not h.value
+    assert len(W.last_error()) > 0
+
+
+def test_null_and_range_checks(W):
+    rc, h = create(W, 3, 0)
+    assert rc == W.OK
+    L = W._lib
+    dummy = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+    assert L.wdirac_dslash_eo(h, None, dummy, dummy, 0, 0, 1, 0.0, None, 1.0, 0, None) == W.EINVAL
+    assert L.wdirac_dslash_eo(h, dummy, dummy, dummy, 2, 0, 1, 0.0, None, 1.0, 0, None) == W.EINVAL
+    assert L.wdirac_dslash_eo(h, dummy, dummy, dummy, 0, 0, 13, 0.0, None, 1.0, 0, None) == W.EINVAL
+    assert L.wdirac_dslash_eo(h, dummy, dummy, dummy, 0, 0, 0, 0.0, None, 1.0, 0, None) == W.EINVAL
+    assert L.wdirac_dslash_eo(h, dummy, dummy, dummy, 0, 2, 1, 0.0, None, 1.0, 0, None) == W.EINVAL
+    assert L.wdirac_dslash_eo(h, dummy, dummy, dummy, 0, 0, 1, 0.0, None, 1.0, 5, None) == W.EINVAL
+    assert L.wdirac_dslash_eo(h, dummy, dummy, dummy, 0, 0, 1, 0.0, None, 1.0, 0, None) == W.EINVAL  # in == out
+    assert L.wdirac_dslash_eo(None, dummy, dummy, dummy, 0, 0, 1, 0.0, None, 1.0, 0, None) == W.EINVAL
+    assert L.wdirac_apply_Mee(h, dummy, dummy, -4.0, 1, 1, 0, None) == W.EINVAL
+    assert L.wdirac_eo_reconstruct(h, dummy, ctypes.c_void_p(0x2000), dummy, dummy, -4.0, 1, None) == W.EINVAL
+    st = (W.CgStats * 1)()
+    assert L.wdirac_cg_eo(h, dummy, dummy, dummy, None, -0.2, 0.0, 10, 1, 0, dummy, st, None) == W.EINVAL
+    assert L.wdirac_cg_eo(h, dummy, dummy, dummy, None, -0.2, 1e-10, 10, 1, 1, dummy, st, None) == W.EINVAL
+    assert L.wdirac_cg_eo(h, dummy, dummy, dummy, None, -0.2, 1e-10, 10, 1, 7, dummy, st, None) == W.EINVAL
+    assert L.wdirac_set_option(h, W.OPT_CG_CHECK_EVERY, 0.0) == W.EINVAL
+    assert L.wdirac_set_option(h, W.OPT_MIXED_DELTA, 1.5) == W.EINVAL
+    assert L.wdirac_set_option(h, 99, 1.0) == W.EINVAL
+    assert L.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_SITE) == W.OK
+    assert L.wdirac_field_bytes(h, 9, 1, 0) == 0
+    assert L.wdirac_workspace_bytes(h, 9, 1, 0) == 0
+    assert L.wdirac_destroy(h) == W.OK
+
+
+def test_site_variant_unavailable_for_large_rep(W):
+    rc, h = create(W, 4, 1)   # SU(4) ADJ, d = 15
+    assert rc == W.OK
+    assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_SITE) == W.EUNSUPPORTED
+    W._lib.wdirac_destroy(h)

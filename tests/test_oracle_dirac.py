@@ -143,6 +143,9 @@ def test_bc_as_link_sign():
     URs = UR.copy()
     URs[-1, :, :, :, 0] *= -1.0
     assert rel(D.hopping(psi, URs, PBC), D.hopping(psi, UR, APBC)) < 1e-15
+    assert np.array_equal(D.links_with_boundary_phase(UR, APBC), URs)
+    bc2 = (1, -1, 1, -1)
+    assert rel(D.hopping(psi, D.links_with_boundary_phase(UR, bc2), PBC), D.hopping(psi, UR, bc2)) < 1e-15
 
 
 @pytest.mark.parametrize('N,rep', [(2, 'FUND'), (2, 'ADJ')])
