@@ -128,6 +128,11 @@ def main():
     stream = torch.cuda.current_stream()
 
     bytes_per_launch = hop_bytes_per_site(d, lat.real, 8) * lat.Vh
+    # the library's autotuner picks the hop launch shape for both precisions
+    tuned = {'f64': lat.autotune(UR64, W.F64, 1), 'f32': lat.autotune(UR32, W.F32, 1)}
+    log(f'[bench] autotuned hop shapes: {tuned}')
+    variant_name = {W.HOP_SITE: 'k_hop_sp (lane per site)', W.HOP_COLOUR: 'k_hop_cs (colour-split)',
+                    W.HOP_COLOUR_PAIR: 'k_hop_cs (colour-split, paired directions)'}
 
     def step(record):
         lat.rep_links(UR64, Ug, W.F64)
@@ -188,7 +193,8 @@ def main():
         'roofline': {'bound': 'hbm', 'achieved': round(gbs, 2), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
                      'frac': round(gbs / HBM_PEAK_GBS, 4),
                      'traffic': traffic,
-                     'kernel': 'k_hop_cs<3,complex,double> (colour-split hop)',
+                     'kernel': variant_name[tuned['f64']['variant']] + f' d=3 complex FP64, '
+                               f'xcd_remap={tuned["f64"]["xcd_remap"]}',
                      'bytes_per_launch': bytes_per_launch, 'us_per_launch': round(hop_ms * 1e3, 3)},
     }
     if not args.no_cg:

@@ -61,7 +61,14 @@ typedef enum { WDIRAC_CG_F64 = 0, WDIRAC_CG_MIXED = 1 } wdirac_cg_mode;
 /* Kinds of packed objects, for wdirac_field_bytes(). */
 typedef enum { WDIRAC_FIELD_HALF_SPINOR = 0, WDIRAC_FIELD_LINKS = 1 } wdirac_field_kind;
 /* Operations that need scratch memory, for wdirac_workspace_bytes(). */
-typedef enum { WDIRAC_OP_DHAT = 0, WDIRAC_OP_CG = 1, WDIRAC_OP_FORCE = 2, WDIRAC_OP_NORM = 3 } wdirac_op;
+typedef enum {
+  WDIRAC_OP_DHAT = 0,
+  WDIRAC_OP_CG = 1,
+  WDIRAC_OP_FORCE = 2,
+  WDIRAC_OP_NORM = 3,
+  WDIRAC_OP_DOT = 4,
+  WDIRAC_OP_TUNE = 5
+} wdirac_op;
 
 typedef struct {
   int32_t dims[4]; /* T, X, Y, Z: even, >= 2                                */
@@ -92,22 +99,52 @@ int wdirac_destroy(wdirac_ctx *ctx);
  * rounding):
  *   WDIRAC_OPT_HOP_VARIANT_F64 / _F32  0 = one lane per site (d_R <= 6 only),
  *                                      1 = one wavefront per colour row of a
- *                                          64-site tile (default)
+ *                                          64-site tile (default),
+ *                                      2 = as 1 with the forward and backward
+ *                                          hop of each direction staged
+ *                                          together (half the barriers)
  *   WDIRAC_OPT_XCD_REMAP               1 (default) = give each XCD a
  *                                      contiguous range of site tiles
  *   WDIRAC_OPT_CG_CHECK_EVERY          CG iterations between host checks of
  *                                      convergence (default 4, 1..1000)
  *   WDIRAC_OPT_MIXED_DELTA             reliable-update trigger of mixed CG,
  *                                      ||r|| < delta max ||r|| (default 0.1)
- * Errors: EINVAL (unknown option or value), EUNSUPPORTED. */
+ *   WDIRAC_OPT_HOP_NR_F64 / _F32       right-hand sides sharing each link load
+ *                                      in the colour-split form (1..4; the
+ *                                      largest divisor of nrhs not above it
+ *                                      whose LDS staging fits is used)
+ * Options set here apply to every nrhs except those that wdirac_autotune()
+ * has tuned.  Errors: EINVAL (unknown option or value), EUNSUPPORTED. */
 typedef enum {
   WDIRAC_OPT_HOP_VARIANT_F64 = 0,
   WDIRAC_OPT_HOP_VARIANT_F32 = 1,
   WDIRAC_OPT_XCD_REMAP = 2,
   WDIRAC_OPT_CG_CHECK_EVERY = 3,
-  WDIRAC_OPT_MIXED_DELTA = 4
+  WDIRAC_OPT_MIXED_DELTA = 4,
+  WDIRAC_OPT_HOP_NR_F64 = 5,
+  WDIRAC_OPT_HOP_NR_F32 = 6
 } wdirac_option;
 int wdirac_set_option(wdirac_ctx *ctx, int option, double value);
+
+/* Launch shape of the hopping kernel chosen by wdirac_autotune(). */
+typedef struct {
+  int32_t variant;    /* 0 = one lane per site, 1 = colour-split, 2 = paired */
+  int32_t nr;         /* right-hand sides per block (colour-split form)  */
+  int32_t xcd_remap;  /* 1 = contiguous tile ranges per XCD               */
+  int32_t candidates; /* number of shapes timed                           */
+  double us;          /* mean time of one hop launch with that shape      */
+} wdirac_tuning;
+
+/* Autotuner: times every available launch shape of the hopping kernel
+ * (variant x right-hand sides per block x XCD tile mapping) for nrhs
+ * right-hand sides in precision prec on the links UR (HIP events, 3 warm-up
+ * and 10 timed launches each), and makes the fastest the one used for this
+ * (prec, nrhs) by every later call on ctx (CG included).  Results never change
+ * beyond rounding.  workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_TUNE,
+ * nrhs, prec) bytes (overwritten).  best (host, nullable) receives the choice.
+ * Synchronises.  Errors: EINVAL, EHIP. */
+int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *workspace, wdirac_tuning *best,
+                    void *stream);
 
 /* Representation dimension d_R and whether links are stored as real numbers
  * (ADJ; Sec. 4.1.2).  Host only. */
@@ -196,6 +233,15 @@ int wdirac_eo_reconstruct(const wdirac_ctx *ctx, void *psi_o, const void *psi_e,
 int wdirac_norm2(const wdirac_ctx *ctx, double *out, const void *v, int nrhs, int prec, void *workspace,
                  void *stream);
 
+/* Inner products <a_k, b_k> = sum over sites, spins and colours of
+ * conj(a) b (Sec. 4.2.2) for the nrhs packed half spinors a, b (precision
+ * prec), summed in FP64 with compensated accumulation of the block partial
+ * sums; written to the host array out[2 nrhs] as (re, im) pairs.
+ * Synchronises.  workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_DOT, nrhs,
+ * prec).  Errors: EINVAL, EHIP. */
+int wdirac_dot(const wdirac_ctx *ctx, double *out, const void *a, const void *b, int nrhs, int prec,
+               void *workspace, void *stream);
+
 /* Conjugate gradient (Sec. 5.1.2) on (D-hat^+ D-hat) x = b over the even sites,
  * independently for each of nrhs right-hand sides.  x (packed FP64, in: the
  * initial guess, out: the solution), b (packed FP64).  Stops when the FP64
@@ -216,12 +262,15 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
  *   P_mu(x) = sum_a (dS/dw^a_mu(x)) T^a_F,  dS/dw^a = Im tr[T^a_R U_R Sigma_mu],
  *   Sigma_mu(x) = tr_spin[(1 - g_mu) X(x+mu) Y(x)^+ + (1 + g_mu) Y(x+mu) X(x)^+],
  * X = (x, D_oe x), Y = (D-hat x, D_eo^+ D-hat x), for the variation
- * U -> exp(i w^a T^a_F) U.  P (canonical complex128 force layout) receives
- * scale * P (accumulate = 0) or P += scale * P (accumulate = 1).  workspace:
- * wdirac_workspace_bytes(ctx, WDIRAC_OP_FORCE, 1, WDIRAC_F64).  Errors:
- * EINVAL, EHIP. */
-int wdirac_force_eo(const wdirac_ctx *ctx, void *P, const void *x_e, const void *UR64, double m0,
-                    double scale, int accumulate, void *workspace, void *stream);
+ * U -> exp(i w^a T^a_F) U.  `out` (canonical complex128 [T][X][Y][Z][4][N][N])
+ * receives scale * F (accumulate = 0) or out += scale * F (accumulate = 1),
+ * where F = P when U is NULL, and F = G = 2i P U (U: the canonical
+ * fundamental links) otherwise: G is the gradient in the convention
+ * dS = Re tr(G^+ dU) for tangent variations dU = i w^a T^a U.  workspace:
+ * wdirac_workspace_bytes(ctx, WDIRAC_OP_FORCE, 1, WDIRAC_F64).  Synchronises.
+ * Errors: EINVAL, EHIP. */
+int wdirac_force_eo(const wdirac_ctx *ctx, void *out, const void *x_e, const void *UR64, const void *U,
+                    double m0, double scale, int accumulate, void *workspace, void *stream);
 
 /* Thread-local description of the last error (empty string if none). */
 const char *wdirac_last_error(void);

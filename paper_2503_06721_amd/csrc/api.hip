@@ -1,5 +1,6 @@
 // C ABI of libwdirac: argument checking, dispatch to the kernels, and the
 // host loop of the conjugate-gradient solver.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -12,10 +13,16 @@
 #include "wd_common.h"
 #include "wd_kernels.h"
 
+struct wdirac_tuned {
+  int valid, variant, nr, xcd_remap;
+};
+
 struct wdirac_ctx {
   int N, rep, d, real;
   wd::Geom g;
-  int hop_variant[2];   // per precision (F64, F32): wd::HOP_SITE or wd::HOP_COLOUR
+  int hop_variant[2];   // per precision (F64, F32): wd::HOP_SITE, HOP_COLOUR or HOP_COLOUR_PAIR
+  int hop_nr[2];        // preferred right-hand sides per colour-split block
+  wdirac_tuned tuned[2][13];   // autotuned shape per (precision, nrhs)
   int xcd_remap;
   int cg_check_every;   // CG iterations between host convergence checks
   double mixed_delta;   // reliable-update trigger ||r|| < delta max||r||
@@ -127,9 +134,25 @@ CgWork carve_cg(const wdirac_ctx *c, int nrhs, int mode, void *ws) {
   return w;
 }
 
+// Right-hand sides per colour-split block: the largest divisor of nrhs not
+// above the preference whose LDS staging fits.
+int effective_nr(const wdirac_ctx *c, int pref, int nrhs, int prec, int variant) {
+  if (variant == wd::HOP_SITE) return 1;
+  int nr = std::min(pref, wd::hop_max_nr(c->d, prec, variant));
+  while (nr > 1 && nrhs % nr) --nr;
+  return std::max(nr, 1);
+}
+
 // One hopping-term launch.
 int hop(const wdirac_ctx *c, void *out, const void *in, const void *UR, int out_parity, int dagger, int nrhs,
         double alpha, const void *xadd, double beta, int prec, double *partial, hipStream_t st, int *nblk = nullptr) {
+  int variant = c->hop_variant[prec], pref = c->hop_nr[prec], remap = c->xcd_remap;
+  const wdirac_tuned &tn = c->tuned[prec][nrhs];
+  if (tn.valid) {
+    variant = tn.variant;
+    pref = tn.nr;
+    remap = tn.xcd_remap;
+  }
   wd::HopArgs a;
   a.out = out;
   a.in = in;
@@ -137,12 +160,14 @@ int hop(const wdirac_ctx *c, void *out, const void *in, const void *UR, int out_
   a.xadd = xadd;
   a.g = c->g;
   a.parity = out_parity;
-  a.xcd_remap = c->xcd_remap;
+  a.xcd_remap = remap;
   a.alpha = alpha;
   a.beta = beta;
   a.partial = partial;
   int nb = 0;
-  WD_HIP(wd::launch_hop(a, c->d, c->real, prec, dagger, nrhs, c->hop_variant[prec], st, &nb));
+  a.ntiles = a.ngroups = 0;
+  WD_HIP(wd::launch_hop(a, c->d, c->real, prec, dagger, nrhs, variant, effective_nr(c, pref, nrhs, prec, variant),
+                        st, &nb));
   if (nblk) *nblk = nb;
   return WDIRAC_OK;
 }
@@ -192,6 +217,8 @@ int wdirac_create(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *geom) {
   for (int mu = 0; mu < 4; ++mu) c->g.bc[mu] = geom->bc[mu];
   c->hop_variant[0] = wd::HOP_COLOUR;
   c->hop_variant[1] = wd::HOP_COLOUR;
+  c->hop_nr[0] = c->hop_nr[1] = 4;
+  std::memset(c->tuned, 0, sizeof(c->tuned));
   c->xcd_remap = 1;
   c->cg_check_every = 4;
   c->mixed_delta = 0.1;
@@ -235,6 +262,11 @@ size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec)
       return 3 * align256(half_bytes(ctx, 1, WDIRAC_F64));
     case WDIRAC_OP_NORM:
       return align256(partial_doubles(ctx, nrhs) * sizeof(double)) + align256(nrhs * sizeof(double));
+    case WDIRAC_OP_DOT:
+      return align256(2 * partial_doubles(ctx, nrhs) * sizeof(double)) + align256(2 * nrhs * sizeof(double));
+    case WDIRAC_OP_TUNE:
+      if (prec != WDIRAC_F64 && prec != WDIRAC_F32) return 0;
+      return 2 * align256(half_bytes(ctx, nrhs, prec));
   }
   return 0;
 }
@@ -245,7 +277,7 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
     case WDIRAC_OPT_HOP_VARIANT_F64:
     case WDIRAC_OPT_HOP_VARIANT_F32: {
       const int v = (int)value;
-      if ((v != wd::HOP_SITE && v != wd::HOP_COLOUR) || !wd::hop_variant_ok(ctx->d, v))
+      if (v < wd::HOP_SITE || v > wd::HOP_COLOUR_PAIR || !wd::hop_variant_ok(ctx->d, v))
         return fail(WDIRAC_EUNSUPPORTED, "hop variant not available for this representation");
       ctx->hop_variant[option == WDIRAC_OPT_HOP_VARIANT_F64 ? 0 : 1] = v;
       return WDIRAC_OK;
@@ -261,8 +293,75 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
       if (!(value > 0.0 && value < 1.0)) return fail(WDIRAC_EINVAL, "delta must be in (0, 1)");
       ctx->mixed_delta = value;
       return WDIRAC_OK;
+    case WDIRAC_OPT_HOP_NR_F64:
+    case WDIRAC_OPT_HOP_NR_F32:
+      if (!(value >= 1 && value <= 4)) return fail(WDIRAC_EINVAL, "right-hand sides per block must be in [1, 4]");
+      ctx->hop_nr[option == WDIRAC_OPT_HOP_NR_F64 ? 0 : 1] = (int)value;
+      return WDIRAC_OK;
   }
   return fail(WDIRAC_EINVAL, "unknown option");
+}
+
+int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *workspace, wdirac_tuning *best,
+                    void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  WD_TRY(check_prec(prec));
+  WD_TRY(check_nrhs(nrhs));
+  const hipStream_t st = S(stream);
+  Carver cv{static_cast<char *>(workspace)};
+  const size_t hb = half_bytes(ctx, nrhs, prec);
+  void *in = cv.take(hb), *out = cv.take(hb);
+  WD_HIP(hipMemsetAsync(in, 0, hb, st));
+  struct Cand {
+    int variant, nr, remap;
+  };
+  std::vector<Cand> cands;
+  for (int remap = 0; remap < 2; ++remap) {
+    for (int v = wd::HOP_COLOUR; v <= wd::HOP_COLOUR_PAIR; ++v)
+      for (int nr = 1; nr <= 4; ++nr)
+        if (effective_nr(ctx, nr, nrhs, prec, v) == nr) cands.push_back({v, nr, remap});
+    if (wd::hop_variant_ok(ctx->d, wd::HOP_SITE)) cands.push_back({wd::HOP_SITE, 1, remap});
+  }
+  hipEvent_t e0, e1;
+  WD_HIP(hipEventCreate(&e0));
+  WD_HIP(hipEventCreate(&e1));
+  wdirac_tuned &slot = ctx->tuned[prec][nrhs];
+  float best_ms = 1e30f;
+  Cand pick = cands.front();
+  int rc = WDIRAC_OK;
+  for (const Cand &cd : cands) {
+    slot = wdirac_tuned{1, cd.variant, cd.nr, cd.remap};
+    for (int k = 0; k < 3 && rc == WDIRAC_OK; ++k) rc = hop(ctx, out, in, UR, 0, 0, nrhs, 0.0, nullptr, 1.0, prec, nullptr, st);
+    if (rc == WDIRAC_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventRecord");
+    for (int k = 0; k < 10 && rc == WDIRAC_OK; ++k)
+      rc = hop(ctx, out, in, UR, k & 1, 0, nrhs, 0.0, nullptr, 1.0, prec, nullptr, st);
+    if (rc == WDIRAC_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventRecord");
+    if (rc == WDIRAC_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventSynchronize");
+    float ms = 0.0f;
+    if (rc == WDIRAC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventElapsedTime");
+    if (rc != WDIRAC_OK) break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      pick = cd;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != WDIRAC_OK) {
+    slot.valid = 0;
+    return rc;
+  }
+  slot = wdirac_tuned{1, pick.variant, pick.nr, pick.remap};
+  if (best) {
+    best->variant = pick.variant;
+    best->nr = pick.nr;
+    best->xcd_remap = pick.remap;
+    best->candidates = (int)cands.size();
+    best->us = best_ms * 1e3 / 10.0;
+  }
+  return WDIRAC_OK;
 }
 
 int wdirac_pack_spinor(const wdirac_ctx *ctx, void *packed, const void *canon, int parity, int nrhs, int prec,
@@ -401,6 +500,31 @@ int wdirac_norm2(const wdirac_ctx *ctx, double *out, const void *v, int nrhs, in
   WD_HIP(wd::launch_finalize_sum(dout, part, wd::blas_nblocks(f), nrhs, S(stream)));
   WD_HIP(hipMemcpyAsync(out, dout, nrhs * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
   WD_HIP(hipStreamSynchronize(S(stream)));
+  return WDIRAC_OK;
+}
+
+int wdirac_dot(const wdirac_ctx *ctx, double *out, const void *a, const void *b, int nrhs, int prec, void *workspace,
+               void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(a, "a"));
+  WD_TRY(check_ptr(b, "b"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_prec(prec));
+  Carver cv{static_cast<char *>(workspace)};
+  double *part = static_cast<double *>(cv.take(2 * partial_doubles(ctx, nrhs) * sizeof(double)));
+  double *dout = static_cast<double *>(cv.take(2 * nrhs * sizeof(double)));
+  const wd::FieldShape f = shape(ctx, nrhs);
+  WD_HIP(wd::launch_dot_partial(part, a, b, f, prec, S(stream)));
+  WD_HIP(wd::launch_finalize_sum(dout, part, wd::blas_nblocks(f), 2 * nrhs, S(stream)));
+  std::vector<double> tmp(2 * nrhs);
+  WD_HIP(hipMemcpyAsync(tmp.data(), dout, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
+  WD_HIP(hipStreamSynchronize(S(stream)));
+  for (int k = 0; k < nrhs; ++k) {
+    out[2 * k] = tmp[k];
+    out[2 * k + 1] = tmp[nrhs + k];
+  }
   return WDIRAC_OK;
 }
 
@@ -547,10 +671,10 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
   return worst;
 }
 
-int wdirac_force_eo(const wdirac_ctx *ctx, void *P, const void *x_e, const void *UR64, double m0, double scale,
-                    int accumulate, void *workspace, void *stream) {
+int wdirac_force_eo(const wdirac_ctx *ctx, void *P, const void *x_e, const void *UR64, const void *U, double m0,
+                    double scale, int accumulate, void *workspace, void *stream) {
   WD_TRY(check_ctx(ctx));
-  WD_TRY(check_ptr(P, "P"));
+  WD_TRY(check_ptr(P, "out"));
   WD_TRY(check_ptr(x_e, "x_e"));
   WD_TRY(check_ptr(UR64, "UR64"));
   WD_TRY(check_ptr(workspace, "workspace"));
@@ -562,7 +686,7 @@ int wdirac_force_eo(const wdirac_ctx *ctx, void *P, const void *x_e, const void 
   WD_TRY(hop(ctx, z_o, x_e, UR64, 1, 0, 1, 0.0, nullptr, 1.0, WDIRAC_F64, nullptr, st));
   WD_TRY(hop(ctx, y_e, z_o, UR64, 0, 0, 1, (4.0 + m0) * (4.0 + m0), x_e, -1.0, WDIRAC_F64, nullptr, st));
   WD_TRY(hop(ctx, w_o, y_e, UR64, 1, 1, 1, 0.0, nullptr, 1.0, WDIRAC_F64, nullptr, st));
-  WD_HIP(wd::launch_force_links(P, x_e, z_o, y_e, w_o, UR64, ctx->g, ctx->N, ctx->rep, scale, accumulate, st));
+  WD_HIP(wd::launch_force_links(P, x_e, z_o, y_e, w_o, UR64, U, ctx->g, ctx->N, ctx->rep, scale, accumulate, st));
   WD_HIP(hipStreamSynchronize(st));
   return WDIRAC_OK;
 }

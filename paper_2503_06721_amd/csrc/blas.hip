@@ -33,17 +33,46 @@ __device__ __forceinline__ void neumaier_add(double &s, double &c, double v) {
   s = t;
 }
 
-// One block per rhs: out = compensated sum of partial[r][0..nblk).
+// Error-free transformation: s + e == a + b exactly (Knuth's TwoSum, no
+// ordering requirement on |a|, |b|).
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// One block per rhs: compensated sum of partial[0..nblk).  Each thread keeps a
+// Neumaier (sum, compensation) pair over a strided subset; pairs are merged
+// by a butterfly over the wavefront with TwoSum on the sums, then the four
+// wavefronts are merged in a fixed order.  Deterministic: the result depends
+// only on nblk and the values, not on timing.
 __device__ double sum_partials(const double *partial, int nblk) {
-  __shared__ double vals[BT];
+  __shared__ double ws[BT / 64], wc[BT / 64];
   double s = 0.0, c = 0.0;
   for (int k = threadIdx.x; k < nblk; k += BT) neumaier_add(s, c, partial[k]);
-  vals[threadIdx.x] = s + c;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double so = __shfl_xor(s, off, 64), co = __shfl_xor(c, off, 64);
+    double t, e;
+    two_sum(s, so, t, e);
+    s = t;
+    c = (c + co) + e;
+  }
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    ws[threadIdx.x >> 6] = s;
+    wc[threadIdx.x >> 6] = c;
+  }
   __syncthreads();
   double tot = 0.0;
   if (threadIdx.x == 0) {
-    double ts = 0.0, tc = 0.0;
-    for (int k = 0; k < BT; ++k) neumaier_add(ts, tc, vals[k]);
+    double ts = ws[0], tc = wc[0];
+    for (int w = 1; w < BT / 64; ++w) {
+      double t, e;
+      two_sum(ts, ws[w], t, e);
+      ts = t;
+      tc = (tc + wc[w]) + e;
+    }
     tot = ts + tc;
   }
   __syncthreads();
@@ -109,6 +138,38 @@ hipError_t launch_norm2_partial(double *partial, const void *v, const FieldShape
   dim3 grid(blas_nblocks(f), f.nrhs);
   if (prec == 0) hipLaunchKernelGGL(k_norm2_partial<double>, grid, dim3(BT), 0, st, partial, v, f);
   else hipLaunchKernelGGL(k_norm2_partial<float>, grid, dim3(BT), 0, st, partial, v, f);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(BT) void k_dot_partial(double *partial, const void *a, const void *b, FieldShape f) {
+  __shared__ double sh[BT / 64];
+  const int i = blockIdx.x * BT + threadIdx.x;
+  double re = 0.0, im = 0.0;
+  if (i < f.Vh) {
+    const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+    for (int c = 0; c < f.ncomp; ++c) {
+      const size_t o = base + (size_t)c * f.stride;
+      const cplx<double> x = up(ld<T>(a, o)), y = up(ld<T>(b, o));
+      re = fma(x.re, y.re, re);
+      re = fma(x.im, y.im, re);
+      im = fma(x.re, y.im, im);
+      im = fma(-x.im, y.re, im);
+    }
+  }
+  re = block_sum(re, sh);
+  im = block_sum(im, sh);
+  if (threadIdx.x == 0) {
+    partial[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = re;
+    partial[(size_t)(gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = im;
+  }
+}
+
+hipError_t launch_dot_partial(double *partial, const void *a, const void *b, const FieldShape &f, int prec,
+                              hipStream_t st) {
+  dim3 grid(blas_nblocks(f), f.nrhs);
+  if (prec == 0) hipLaunchKernelGGL(k_dot_partial<double>, grid, dim3(BT), 0, st, partial, a, b, f);
+  else hipLaunchKernelGGL(k_dot_partial<float>, grid, dim3(BT), 0, st, partial, a, b, f);
   return hipGetLastError();
 }
 

@@ -88,7 +88,8 @@ __device__ __forceinline__ void project(const cplx<double> *__restrict__ f, int 
 
 template <int N, int REP, int MU>
 __device__ void force_link(double *__restrict__ P, const cplx<double> *Xe, const cplx<double> *Xo,
-                           const cplx<double> *Ye, const cplx<double> *Yo, const void *UR, const Geom &g, int lex,
+                           const cplx<double> *Ye, const cplx<double> *Yo, const void *UR,
+                           const cplx<double> *__restrict__ U, const Geom &g, int lex,
                            int par, int cb, int t, int x, int y, int z, double scale, int accumulate) {
   constexpr int D = frep_dim(N, REP);
   constexpr bool REAL = REP == 1;
@@ -195,15 +196,36 @@ __device__ void force_link(double *__restrict__ P, const cplx<double> *Xe, const
     }
 #pragma unroll
   for (int i = 0; i < N; ++i) trA += Am[i][i].re;
+  cplx<double> F[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+      F[i][j] = mk(scale * (0.5 * Am[i][j].re - (i == j ? 0.5 * trA / N : 0.0)), scale * 0.5 * Am[i][j].im);
+  if (U) {
+    // G = 2i P U, the gradient for dS = Re tr(G^+ dU) along dU = i w T U
+    const cplx<double> *u = U + ((size_t)lex * 4 + MU) * N * N;
+    cplx<double> G[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        cplx<double> g = mk(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < N; ++k) g = cfma(F[i][k], u[k * N + j], g);
+        G[i][j] = mk(-2.0 * g.im, 2.0 * g.re);
+      }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) F[i][j] = G[i][j];
+  }
   double *out = P + ((size_t)lex * 4 + MU) * N * N * 2;
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      double re = 0.5 * Am[i][j].re - (i == j ? 0.5 * trA / N : 0.0);
-      double im = 0.5 * Am[i][j].im;
-      re *= scale;
-      im *= scale;
+      double re = F[i][j].re, im = F[i][j].im;
       if (accumulate) {
         re += out[2 * (i * N + j)];
         im += out[2 * (i * N + j) + 1];
@@ -215,8 +237,8 @@ __device__ void force_link(double *__restrict__ P, const cplx<double> *Xe, const
 
 template <int N, int REP>
 __global__ __launch_bounds__(256) void k_force(double *P, const cplx<double> *Xe, const cplx<double> *Xo,
-                                               const cplx<double> *Ye, const cplx<double> *Yo, const void *UR, Geom g,
-                                               double scale, int accumulate) {
+                                               const cplx<double> *Ye, const cplx<double> *Yo, const void *UR,
+                                               const cplx<double> *U, Geom g, double scale, int accumulate) {
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= 8 * g.Vh) return;
   const int lex = gid >> 2, mu = gid & 3;
@@ -227,43 +249,43 @@ __global__ __launch_bounds__(256) void k_force(double *P, const cplx<double> *Xe
   const int t = r / g.X;
   const int par = (t + x + y + z) & 1, cb = lex >> 1;
   switch (mu) {
-    case 0: force_link<N, REP, 0>(P, Xe, Xo, Ye, Yo, UR, g, lex, par, cb, t, x, y, z, scale, accumulate); break;
-    case 1: force_link<N, REP, 1>(P, Xe, Xo, Ye, Yo, UR, g, lex, par, cb, t, x, y, z, scale, accumulate); break;
-    case 2: force_link<N, REP, 2>(P, Xe, Xo, Ye, Yo, UR, g, lex, par, cb, t, x, y, z, scale, accumulate); break;
-    default: force_link<N, REP, 3>(P, Xe, Xo, Ye, Yo, UR, g, lex, par, cb, t, x, y, z, scale, accumulate); break;
+    case 0: force_link<N, REP, 0>(P, Xe, Xo, Ye, Yo, UR, U, g, lex, par, cb, t, x, y, z, scale, accumulate); break;
+    case 1: force_link<N, REP, 1>(P, Xe, Xo, Ye, Yo, UR, U, g, lex, par, cb, t, x, y, z, scale, accumulate); break;
+    case 2: force_link<N, REP, 2>(P, Xe, Xo, Ye, Yo, UR, U, g, lex, par, cb, t, x, y, z, scale, accumulate); break;
+    default: force_link<N, REP, 3>(P, Xe, Xo, Ye, Yo, UR, U, g, lex, par, cb, t, x, y, z, scale, accumulate); break;
   }
 }
 
 template <int N, int REP>
 static hipError_t force_launch(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo, const void *UR,
-                               const Geom &g, double scale, int accumulate, hipStream_t st) {
+                               const void *U, const Geom &g, double scale, int accumulate, hipStream_t st) {
   const int n = 8 * g.Vh;
   hipLaunchKernelGGL((k_force<N, REP>), dim3((n + 255) / 256), dim3(256), 0, st, (double *)P,
                      (const cplx<double> *)Xe, (const cplx<double> *)Xo, (const cplx<double> *)Ye,
-                     (const cplx<double> *)Yo, UR, g, scale, accumulate);
+                     (const cplx<double> *)Yo, UR, (const cplx<double> *)U, g, scale, accumulate);
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t force_n(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo, const void *UR,
-                          const Geom &g, int rep, double scale, int accumulate, hipStream_t st) {
+                          const void *U, const Geom &g, int rep, double scale, int accumulate, hipStream_t st) {
   switch (rep) {
-    case 0: return force_launch<N, 0>(P, Xe, Xo, Ye, Yo, UR, g, scale, accumulate, st);
-    case 1: return force_launch<N, 1>(P, Xe, Xo, Ye, Yo, UR, g, scale, accumulate, st);
-    case 2: return force_launch<N, 2>(P, Xe, Xo, Ye, Yo, UR, g, scale, accumulate, st);
+    case 0: return force_launch<N, 0>(P, Xe, Xo, Ye, Yo, UR, U, g, scale, accumulate, st);
+    case 1: return force_launch<N, 1>(P, Xe, Xo, Ye, Yo, UR, U, g, scale, accumulate, st);
+    case 2: return force_launch<N, 2>(P, Xe, Xo, Ye, Yo, UR, U, g, scale, accumulate, st);
     case 3:
-      if constexpr (N > 2) return force_launch<N, 3>(P, Xe, Xo, Ye, Yo, UR, g, scale, accumulate, st);
+      if constexpr (N > 2) return force_launch<N, 3>(P, Xe, Xo, Ye, Yo, UR, U, g, scale, accumulate, st);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_force_links(void *P, const void *X_e, const void *X_o, const void *Y_e, const void *Y_o,
-                              const void *UR, const Geom &g, int N, int rep, double scale, int accumulate,
-                              hipStream_t st) {
+                              const void *UR, const void *U, const Geom &g, int N, int rep, double scale,
+                              int accumulate, hipStream_t st) {
   switch (N) {
-    case 2: return force_n<2>(P, X_e, X_o, Y_e, Y_o, UR, g, rep, scale, accumulate, st);
-    case 3: return force_n<3>(P, X_e, X_o, Y_e, Y_o, UR, g, rep, scale, accumulate, st);
-    case 4: return force_n<4>(P, X_e, X_o, Y_e, Y_o, UR, g, rep, scale, accumulate, st);
+    case 2: return force_n<2>(P, X_e, X_o, Y_e, Y_o, UR, U, g, rep, scale, accumulate, st);
+    case 3: return force_n<3>(P, X_e, X_o, Y_e, Y_o, UR, U, g, rep, scale, accumulate, st);
+    case 4: return force_n<4>(P, X_e, X_o, Y_e, Y_o, UR, U, g, rep, scale, accumulate, st);
   }
   return hipErrorInvalidValue;
 }

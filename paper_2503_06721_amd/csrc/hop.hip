@@ -121,23 +121,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
   sp_mu<D, REAL, T, DAG, 2>(acc, a, in, is, t, x, y, z);
   sp_mu<D, REAL, T, DAG, 3>(acc, a, in, is, t, x, y, z);
   cplx<T> *out = static_cast<cplx<T> *>(a.out) + r * rstride;
-  const cplx<T> *xa = a.xadd ? static_cast<const cplx<T> *>(a.xadd) + r * rstride : nullptr;
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
   double nrm = 0.0;
+  // two straight-line epilogues: every accumulator is used on both paths
+  if (a.xadd) {
+    const cplx<T> *xa = static_cast<const cplx<T> *>(a.xadd) + r * rstride;
 #pragma unroll
-  for (int s = 0; s < 4; ++s)
+    for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int c = 0; c < D; ++c) {
-      const size_t o = (size_t)(s * D + c) * a.g.stride + i;
-      cplx<T> v = cb * acc[s][c];
-      if (xa) {
+      for (int c = 0; c < D; ++c) {
+        const size_t o = (size_t)(s * D + c) * a.g.stride + i;
+        cplx<T> v = cb * acc[s][c];
         const cplx<T> xv = xa[o];
         v.re = fma(ca, xv.re, v.re);
         v.im = fma(ca, xv.im, v.im);
+        out[o] = v;
+        nrm += (double)v.re * v.re + (double)v.im * v.im;
       }
-      out[o] = v;
-      nrm += (double)v.re * v.re + (double)v.im * v.im;
-    }
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const size_t o = (size_t)(s * D + c) * a.g.stride + i;
+        const cplx<T> v = cb * acc[s][c];
+        out[o] = v;
+        nrm += (double)v.re * v.re + (double)v.im * v.im;
+      }
+  }
   if (a.partial) {
     __shared__ double sh[4];
     const double s = block_sum(valid ? nrm : 0.0, sh);
@@ -146,19 +157,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
 }
 
 // ------------------------------------------------------ colour-split form
+// Stage: this lane's link entries (row `row` of U for a forward hop, column
+// `row` of U for a backward hop, whose U^+ row is the conjugated column) and
+// colour component `row` of the neighbour spinor, spin-projected into LDS.
 template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, int NR>
-__device__ __forceinline__ void cs_dir(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[2][D][64], const HopArgs &a,
-                                       const cplx<T> *in0, size_t rstride, int nb, int lsite, int row,
-                                       int lane) {
+__device__ __forceinline__ void cs_stage(typename LinkT<T, REAL>::type (&u)[D], cplx<T> (*hs)[2][D][64],
+                                         const HopArgs &a, const cplx<T> *in0, size_t rstride, int nb, int lsite,
+                                         int row, int lane) {
   using L = typename LinkT<T, REAL>::type;
   const int stride = a.g.stride;
   const int lpar = BWD ? 1 - a.parity : a.parity;
   const L *lk = static_cast<const L *>(a.links) + (size_t)(lpar * 4 + MU) * D * D * stride;
-  // Link entries this lane needs: row `row` of U (forward) or column `row` of U (backward, for U^+).
-  L u[D];
 #pragma unroll
   for (int b = 0; b < D; ++b) u[b] = lk[(size_t)(BWD ? b * D + row : row * D + b) * stride + lsite];
-  // Colour component `row` of the neighbour spinor, spin-projected.
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     const cplx<T> *in = in0 + k * rstride;
@@ -168,7 +179,13 @@ __device__ __forceinline__ void cs_dir(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[2][D
     hs[k][0][row][lane] = p[0] + ipow<PROJ_PH(MU, SIG, 0)>(p[2 + ECOL(MU, 0)]);
     hs[k][1][row][lane] = p[1] + ipow<PROJ_PH(MU, SIG, 1)>(p[2 + ECOL(MU, 1)]);
   }
-  __syncthreads();
+}
+
+// Compute: after the barrier, the full projected two-spinor of this lane's
+// site is in LDS; apply the link row and reconstruct the lower spin half.
+template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, int NR>
+__device__ __forceinline__ void cs_compute(cplx<T> (&acc)[NR][4], const typename LinkT<T, REAL>::type (&u)[D],
+                                           cplx<T> (*hs)[2][D][64], int lane) {
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     cplx<T> chi[2] = {mk<T>(0, 0), mk<T>(0, 0)};
@@ -182,21 +199,56 @@ __device__ __forceinline__ void cs_dir(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[2][D
     acc[k][2] = acc[k][2] + ipow<RECON_PH(MU, SIG, 0)>(chi[RECON_SRC(MU, 0)]);
     acc[k][3] = acc[k][3] + ipow<RECON_PH(MU, SIG, 1)>(chi[RECON_SRC(MU, 1)]);
   }
-  // keep each direction's arithmetic next to its barrier
+  // keep each phase's arithmetic next to its barrier
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int D, bool REAL, typename T, bool DAG, int NR, int W>
+// One direction mu.  PAIR = false: forward and backward hops are two barrier
+// phases (LDS buffers 0 and 1).  PAIR = true: both are staged before a single
+// barrier (LDS buffers 2*(MU&1) and 2*(MU&1)+1), which halves the barriers and
+// doubles the loads in flight per phase at the cost of twice the LDS.
+template <int D, bool REAL, typename T, int MU, int SF, int NR, bool PAIR, int NB>
+__device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64], const HopArgs &a,
+                                      const cplx<T> *in0, size_t rstride, int t, int x, int y, int z, int is,
+                                      int row, int lane) {
+  using L = typename LinkT<T, REAL>::type;
+  const int nbf = nb_index(a.g, t, x, y, z, MU, 1);
+  const int nbb = nb_index(a.g, t, x, y, z, MU, 0);
+  L uf[D], ub[D];
+  if constexpr (PAIR) {
+    constexpr int B0 = 2 * (MU & 1);
+    cs_stage<D, REAL, T, MU, SF, false, NR>(uf, hs[B0], a, in0, rstride, nbf, is, row, lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR>(ub, hs[B0 + 1], a, in0, rstride, nbb, nbb, row, lane);
+    __syncthreads();
+    cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[B0], lane);
+    cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[B0 + 1], lane);
+  } else {
+    cs_stage<D, REAL, T, MU, SF, false, NR>(uf, hs[0], a, in0, rstride, nbf, is, row, lane);
+    __syncthreads();
+    cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[0], lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR>(ub, hs[1], a, in0, rstride, nbb, nbb, row, lane);
+    __syncthreads();
+    cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[1], lane);
+  }
+}
+
+template <int D, bool REAL, typename T, bool DAG, int NR, bool PAIR, int W>
 __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) void k_hop_cs(HopArgs a) {
-  __shared__ cplx<T> hs[2][NR][2][D][64];
+  constexpr int NB = PAIR ? 4 : 2;   // LDS buffers
+  __shared__ cplx<T> hs[NB][NR][2][D][64];
   __shared__ double sh[D];
-  const int ntiles = gridDim.x;
-  const int tile = tile_of_block(blockIdx.x, ntiles, a.xcd_remap);
+  // Work item = (tile, group of NR right-hand sides), group fastest, so the
+  // groups of one tile are consecutive and (after the XCD remap) run on the
+  // same XCD at nearly the same time: each link entry comes from HBM once
+  // and from that XCD's L2 for the other groups.
+  const int ngroups = a.ngroups, ntiles = a.ntiles;
+  const int w = tile_of_block(blockIdx.x, ntiles * ngroups, a.xcd_remap);
+  const int tile = w / ngroups, grp = w - tile * ngroups;
   const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
   const int i = tile * 64 + lane;
   const bool valid = i < a.g.Vh;
   const int is = valid ? i : a.g.Vh - 1;   // lanes past the end: see k_hop_sp
-  const int r0 = blockIdx.y * NR;
+  const int r0 = grp * NR;
   const size_t rstride = (size_t)4 * D * a.g.stride;
   const cplx<T> *in0 = static_cast<const cplx<T> *>(a.in) + r0 * rstride;
   int t, x, y, z;
@@ -206,39 +258,50 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
   for (int k = 0; k < NR; ++k)
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[k][s] = mk<T>(0, 0);
-  constexpr int SF = DAG ? -1 : 1;
-#define WD_CS_MU(MU, BUF)                                                                                   \
-  cs_dir<D, REAL, T, MU, SF, false, NR>(acc, hs[0 + BUF], a, in0, rstride, nb_index(a.g, t, x, y, z, MU, 1), \
-                                        is, row, lane);                                                       \
-  {                                                                                                           \
-    const int nbb = nb_index(a.g, t, x, y, z, MU, 0);                                                         \
-    cs_dir<D, REAL, T, MU, -SF, true, NR>(acc, hs[1 - BUF], a, in0, rstride, nbb, nbb, row, lane);             \
-  }
-  WD_CS_MU(0, 0)
-  WD_CS_MU(1, 0)
-  WD_CS_MU(2, 0)
-  WD_CS_MU(3, 0)
-#undef WD_CS_MU
+  constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
+  cs_mu<D, REAL, T, 0, SF, NR, PAIR, NB>(acc, hs, a, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 1, SF, NR, PAIR, NB>(acc, hs, a, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 2, SF, NR, PAIR, NB>(acc, hs, a, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 3, SF, NR, PAIR, NB>(acc, hs, a, in0, rstride, t, x, y, z, is, row, lane);
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
+  // Two straight-line epilogues (with and without x_add): every accumulator
+  // is used on both paths, so no arithmetic is sunk behind a branch.
+  double nrm[NR];
+  if (a.xadd) {
 #pragma unroll
-  for (int k = 0; k < NR; ++k) {
-    double nrm = 0.0;
-    cplx<T> *out = static_cast<cplx<T> *>(a.out) + (r0 + k) * rstride;
-    const cplx<T> *xa = a.xadd ? static_cast<const cplx<T> *>(a.xadd) + (r0 + k) * rstride : nullptr;
+    for (int k = 0; k < NR; ++k) {
+      nrm[k] = 0.0;
+      cplx<T> *out = static_cast<cplx<T> *>(a.out) + (r0 + k) * rstride;
+      const cplx<T> *xa = static_cast<const cplx<T> *>(a.xadd) + (r0 + k) * rstride;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const size_t o = (size_t)(s * D + row) * a.g.stride + i;   // i < stride always
-      cplx<T> v = cb * acc[k][s];
-      if (xa) {
+      for (int s = 0; s < 4; ++s) {
+        const size_t o = (size_t)(s * D + row) * a.g.stride + i;   // i < stride always
+        cplx<T> v = cb * acc[k][s];
         const cplx<T> xv = xa[o];
         v.re = fma(ca, xv.re, v.re);
         v.im = fma(ca, xv.im, v.im);
+        out[o] = v;
+        nrm[k] += (double)v.re * v.re + (double)v.im * v.im;
       }
-      out[o] = v;
-      nrm += (double)v.re * v.re + (double)v.im * v.im;
     }
-    if (a.partial) {
-      const double s = block_sum(valid ? nrm : 0.0, sh);
+  } else {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      nrm[k] = 0.0;
+      cplx<T> *out = static_cast<cplx<T> *>(a.out) + (r0 + k) * rstride;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const size_t o = (size_t)(s * D + row) * a.g.stride + i;
+        const cplx<T> v = cb * acc[k][s];
+        out[o] = v;
+        nrm[k] += (double)v.re * v.re + (double)v.im * v.im;
+      }
+    }
+  }
+  if (a.partial) {
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+      const double s = block_sum(valid ? nrm[k] : 0.0, sh);
       if (threadIdx.x == 0) a.partial[(size_t)(r0 + k) * ntiles + tile] = s;
     }
   }
@@ -252,8 +315,33 @@ constexpr int cs_waves(int D, bool dbl) {
   return dbl ? (D <= 3 ? 4 : D <= 8 ? 3 : 2) : (D <= 4 ? 6 : D <= 6 ? 5 : D <= 10 ? 4 : 3);
 }
 constexpr int sp_waves(int D, bool dbl) { return dbl ? 2 : (D <= 2 ? 4 : 2); }
+// LDS of one colour-split block, hs[NB][NR][2][D][64], must fit 64 KB.
+template <int D, typename T, int NR, bool PAIR>
+constexpr bool cs_fits() {
+  return (PAIR ? 4 : 2) * NR * 2 * D * 64 * (int)sizeof(cplx<T>) <= 65536;
+}
+
+template <int D, bool REAL, typename T, bool DAG, int NR>
+static hipError_t launch_cs(HopArgs a, int nrhs, int pair, hipStream_t st, int *nblk) {
+  a.ntiles = (a.g.Vh + 63) / 64;
+  a.ngroups = nrhs / NR;
+  *nblk = a.ntiles;
+  dim3 grid(a.ntiles * a.ngroups);
+  if constexpr (cs_fits<D, T, NR, true>()) {
+    if (pair) {
+      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, true, cs_waves(D, sizeof(T) == 8)>), grid, dim3(64 * D), 0,
+                         st, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, false, cs_waves(D, sizeof(T) == 8)>), grid, dim3(64 * D), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
 template <int D, bool REAL, typename T, bool DAG>
-static hipError_t launch_typed(const HopArgs &a, int nrhs, int variant, hipStream_t st, int *nblk) {
+static hipError_t launch_typed(const HopArgs &a, int nrhs, int variant, int nr, hipStream_t st, int *nblk) {
+  const int pair = variant == HOP_COLOUR_PAIR;
   if (variant == HOP_SITE) {
     if constexpr (D <= 6) {
       dim3 grid((a.g.Vh + 255) / 256, nrhs);
@@ -264,40 +352,54 @@ static hipError_t launch_typed(const HopArgs &a, int nrhs, int variant, hipStrea
       return hipErrorInvalidValue;
     }
   }
-  dim3 grid((a.g.Vh + 63) / 64, nrhs);
-  *nblk = grid.x;
-  hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, 1, cs_waves(D, sizeof(T) == 8)>), grid, dim3(64 * D), 0, st, a);
-  return hipGetLastError();
+  if (nr == 4 && nrhs % 4 == 0) {
+    if constexpr (cs_fits<D, T, 4, false>()) return launch_cs<D, REAL, T, DAG, 4>(a, nrhs, pair, st, nblk);
+  }
+  if (nr == 3 && nrhs % 3 == 0) {
+    if constexpr (cs_fits<D, T, 3, false>()) return launch_cs<D, REAL, T, DAG, 3>(a, nrhs, pair, st, nblk);
+  }
+  if (nr == 2 && nrhs % 2 == 0) {
+    if constexpr (cs_fits<D, T, 2, false>()) return launch_cs<D, REAL, T, DAG, 2>(a, nrhs, pair, st, nblk);
+  }
+  return launch_cs<D, REAL, T, DAG, 1>(a, nrhs, pair, st, nblk);
 }
 
 template <int D, bool REAL>
-static hipError_t launch_d(const HopArgs &a, int prec, int dagger, int nrhs, int variant, hipStream_t st,
+static hipError_t launch_d(const HopArgs &a, int prec, int dagger, int nrhs, int variant, int nr, hipStream_t st,
                            int *nblk) {
   if (prec == 0)
-    return dagger ? launch_typed<D, REAL, double, true>(a, nrhs, variant, st, nblk)
-                  : launch_typed<D, REAL, double, false>(a, nrhs, variant, st, nblk);
-  return dagger ? launch_typed<D, REAL, float, true>(a, nrhs, variant, st, nblk)
-                : launch_typed<D, REAL, float, false>(a, nrhs, variant, st, nblk);
+    return dagger ? launch_typed<D, REAL, double, true>(a, nrhs, variant, nr, st, nblk)
+                  : launch_typed<D, REAL, double, false>(a, nrhs, variant, nr, st, nblk);
+  return dagger ? launch_typed<D, REAL, float, true>(a, nrhs, variant, nr, st, nblk)
+                : launch_typed<D, REAL, float, false>(a, nrhs, variant, nr, st, nblk);
 }
 
-hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant,
+hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant, int nr,
                       hipStream_t st, int *nblk) {
   if (real) {
     switch (d) {
-      case 3: return launch_d<3, true>(a, prec, dagger, nrhs, variant, st, nblk);
-      case 8: return launch_d<8, true>(a, prec, dagger, nrhs, variant, st, nblk);
-      case 15: return launch_d<15, true>(a, prec, dagger, nrhs, variant, st, nblk);
+      case 3: return launch_d<3, true>(a, prec, dagger, nrhs, variant, nr, st, nblk);
+      case 8: return launch_d<8, true>(a, prec, dagger, nrhs, variant, nr, st, nblk);
+      case 15: return launch_d<15, true>(a, prec, dagger, nrhs, variant, nr, st, nblk);
     }
   } else {
     switch (d) {
-      case 2: return launch_d<2, false>(a, prec, dagger, nrhs, variant, st, nblk);
-      case 3: return launch_d<3, false>(a, prec, dagger, nrhs, variant, st, nblk);
-      case 4: return launch_d<4, false>(a, prec, dagger, nrhs, variant, st, nblk);
-      case 6: return launch_d<6, false>(a, prec, dagger, nrhs, variant, st, nblk);
-      case 10: return launch_d<10, false>(a, prec, dagger, nrhs, variant, st, nblk);
+      case 2: return launch_d<2, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
+      case 3: return launch_d<3, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
+      case 4: return launch_d<4, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
+      case 6: return launch_d<6, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
+      case 10: return launch_d<10, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
     }
   }
   return hipErrorInvalidValue;
+}
+
+int hop_max_nr(int d, int prec, int variant) {
+  // largest NR in {1..4} whose LDS staging fits, as in cs_fits
+  const int cb = prec == 0 ? 16 : 8, nbuf = variant == HOP_COLOUR_PAIR ? 4 : 2;
+  int nr = 4;
+  while (nr > 1 && nbuf * nr * 2 * d * 64 * cb > 65536) --nr;
+  return nr;
 }
 
 int hop_nblocks(int Vh, int d, int variant) {
@@ -305,6 +407,9 @@ int hop_nblocks(int Vh, int d, int variant) {
   return variant == HOP_SITE ? (Vh + 255) / 256 : (Vh + 63) / 64;
 }
 
-bool hop_variant_ok(int d, int variant) { return variant == HOP_COLOUR || d <= 6; }
+bool hop_variant_ok(int d, int variant) {
+  if (variant == HOP_SITE) return d <= 6;
+  return variant == HOP_COLOUR || variant == HOP_COLOUR_PAIR;
+}
 
 }  // namespace wd

@@ -7,7 +7,7 @@
 
 namespace wd {
 
-enum { HOP_SITE = 0, HOP_COLOUR = 1 };
+enum { HOP_SITE = 0, HOP_COLOUR = 1, HOP_COLOUR_PAIR = 2 };
 
 // Arguments of one hopping-term launch.  Pointers are device memory; fields
 // are packed half spinors, links the packed represented field.
@@ -20,11 +20,16 @@ struct HopArgs {
   int parity;         // parity of the output sites
   int xcd_remap;      // map consecutive tiles to one XCD
   double alpha, beta; // out = alpha * xadd + beta * H in
-  double *partial;    // nullable: per-block partial sums of |out|^2, [rhs][block]
+  double *partial;    // nullable: per-block partial sums of |out|^2, [rhs][tile]
+  int ntiles, ngroups;  // set by the launcher (colour-split form)
 };
 
-hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant,
+// nr: right-hand sides per block of the colour-split form (1..4; reduced to
+// one that divides nrhs and fits LDS).  *nblk receives the number of tiles,
+// the row length of `partial`.
+hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant, int nr,
                       hipStream_t st, int *nblk);
+int hop_max_nr(int d, int prec, int variant);
 int hop_nblocks(int Vh, int d, int variant);
 bool hop_variant_ok(int d, int variant);
 
@@ -48,6 +53,9 @@ hipError_t launch_lincomb(void *out, double a, const void *x, double b, const vo
 hipError_t launch_norm2_partial(double *partial, const void *v, const FieldShape &f, int prec, hipStream_t st);
 // out[r] = compensated sum of partial[r][0..nblk)
 hipError_t launch_finalize_sum(double *out, const double *partial, int nblk, int nrhs, hipStream_t st);
+// partial[r][blk] = Re sum conj(a) b, partial[nrhs + r][blk] = Im sum conj(a) b
+hipError_t launch_dot_partial(double *partial, const void *a, const void *b, const FieldShape &f, int prec,
+                              hipStream_t st);
 // convert between precisions: out (prec_out) = in (prec_in)
 hipError_t launch_convert(void *out, int prec_out, const void *in, int prec_in, const FieldShape &f,
                           hipStream_t st);
@@ -88,8 +96,9 @@ hipError_t launch_cg_restart(CgScalars *s, const double *partial, int nblk, int 
 hipError_t launch_accum_x(void *x64, void *x32, const FieldShape &f, hipStream_t st);
 
 // force.hip
+// U nullable: if given, the output is 2i P U instead of P
 hipError_t launch_force_links(void *P, const void *X_e, const void *X_o, const void *Y_e, const void *Y_o,
-                              const void *UR, const Geom &g, int N, int rep, double scale, int accumulate,
-                              hipStream_t st);
+                              const void *UR, const void *U, const Geom &g, int N, int rep, double scale,
+                              int accumulate, hipStream_t st);
 
 }  // namespace wd

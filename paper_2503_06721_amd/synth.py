@@ -82,6 +82,26 @@ def expH_links(dims, N, eps, seed):
     return expH_su_n(V * 4, N, eps, rng).reshape(tuple(dims) + (4, N, N))
 
 
+def expH_links_torch(dims, N, eps, seed, device='cuda'):
+    """The exp(i eps H) recipe drawn with torch's seeded generator on `device`
+    (for lattices whose links are too many for a host-side eigendecomposition):
+    same distribution of H, exponential by torch.linalg.matrix_exp."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    shape = tuple(dims) + (4, N, N)
+    re = torch.randn(shape, dtype=torch.float64, device=device, generator=g) * 0.5
+    im = torch.randn(shape, dtype=torch.float64, device=device, generator=g) * 0.5
+    A = torch.complex(re, im)
+    upper = torch.triu(A, diagonal=1)
+    H = upper + upper.conj().transpose(-1, -2)
+    diag = torch.randn(tuple(dims) + (4, N), dtype=torch.float64, device=device, generator=g) * (0.5 ** 0.5)
+    diag = diag - diag.mean(dim=-1, keepdim=True)
+    H = H + torch.diag_embed(diag.to(torch.complex128))
+    del A, upper, re, im
+    return torch.linalg.matrix_exp(1j * eps * H)
+
+
 def unit_links(dims, N):
     U = np.zeros(tuple(dims) + (4, N, N), dtype=np.complex128)
     idx = np.arange(N)

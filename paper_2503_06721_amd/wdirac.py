@@ -25,9 +25,10 @@ FUND, ADJ, SYM, ASYM = 0, 1, 2, 3
 F64, F32 = 0, 1
 CG_F64, CG_MIXED = 0, 1
 FIELD_HALF_SPINOR, FIELD_LINKS = 0, 1
-OP_DHAT, OP_CG, OP_FORCE, OP_NORM = 0, 1, 2, 3
-OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA = 0, 1, 2, 3, 4
-HOP_SITE, HOP_COLOUR = 0, 1
+OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE = 0, 1, 2, 3, 4, 5
+(OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
+ OPT_HOP_NR_F32) = 0, 1, 2, 3, 4, 5, 6
+HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR = 0, 1, 2
 REP_CODES = {'FUND': FUND, 'ADJ': ADJ, 'SYM': SYM, '2AS': ASYM}
 STATUS_NAMES = {OK: 'OK', EINVAL: 'EINVAL', EUNSUPPORTED: 'EUNSUPPORTED', EHIP: 'EHIP',
                 ENOCONV: 'ENOCONV', EBREAKDOWN: 'EBREAKDOWN'}
@@ -35,6 +36,14 @@ STATUS_NAMES = {OK: 'OK', EINVAL: 'EINVAL', EUNSUPPORTED: 'EUNSUPPORTED', EHIP: 
 
 class Geom(ctypes.Structure):
     _fields_ = [('dims', ctypes.c_int32 * 4), ('bc', ctypes.c_int32 * 4)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [('variant', ctypes.c_int32), ('nr', ctypes.c_int32), ('xcd_remap', ctypes.c_int32),
+                ('candidates', ctypes.c_int32), ('us', ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class CgStats(ctypes.Structure):
@@ -67,7 +76,9 @@ _SIGS = {
     'wdirac_eo_reconstruct': (_I, [_P, _P, _P, _P, _P, _D, _I, _P]),
     'wdirac_norm2': (_I, [_P, ctypes.POINTER(_D), _P, _I, _I, _P, _P]),
     'wdirac_cg_eo': (_I, [_P, _P, _P, _P, _P, _D, _D, _I, _I, _I, _P, ctypes.POINTER(CgStats), _P]),
-    'wdirac_force_eo': (_I, [_P, _P, _P, _P, _D, _D, _I, _P, _P]),
+    'wdirac_dot': (_I, [_P, ctypes.POINTER(_D), _P, _P, _I, _I, _P, _P]),
+    'wdirac_force_eo': (_I, [_P, _P, _P, _P, _P, _D, _D, _I, _P, _P]),
+    'wdirac_autotune': (_I, [_P, _P, _I, _I, _P, ctypes.POINTER(Tuning), _P]),
     'wdirac_last_error': (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -158,6 +169,14 @@ class Lattice:
     def new_workspace(self, op, nrhs=1, prec=F64):
         return torch.empty(self.workspace_bytes(op, nrhs, prec), dtype=torch.uint8, device='cuda')
 
+    def autotune(self, UR, prec=F64, nrhs=1, workspace=None, stream=None):
+        """Time the hop launch shapes for (prec, nrhs) and keep the fastest; returns it."""
+        ws = workspace if workspace is not None else self.new_workspace(OP_TUNE, nrhs, prec)
+        best = Tuning()
+        _check(_lib.wdirac_autotune(self._h, _ptr(UR), prec, nrhs, _ptr(ws), ctypes.byref(best), _stream(stream)),
+               'autotune')
+        return best.as_dict()
+
     # ---------------------------------------------------------- layouts
     def pack_spinor(self, packed, canon, parity, nrhs=1, prec=F64, stream=None):
         _check(_lib.wdirac_pack_spinor(self._h, _ptr(packed), _ptr(canon), parity, nrhs, prec, _stream(stream)),
@@ -206,6 +225,13 @@ class Lattice:
         _check(_lib.wdirac_norm2(self._h, out, _ptr(v), nrhs, prec, _ptr(ws), _stream(stream)), 'norm2')
         return list(out)
 
+    def dot(self, a, b, nrhs=1, prec=F64, workspace=None, stream=None):
+        """[<a_k, b_k>] as Python complex numbers."""
+        ws = workspace if workspace is not None else self.new_workspace(OP_DOT, nrhs, prec)
+        out = (_D * (2 * nrhs))()
+        _check(_lib.wdirac_dot(self._h, out, _ptr(a), _ptr(b), nrhs, prec, _ptr(ws), _stream(stream)), 'dot')
+        return [complex(out[2 * k], out[2 * k + 1]) for k in range(nrhs)]
+
     def cg_eo(self, x, b, UR64, m0, tol=1e-10, maxit=10000, nrhs=1, mode=CG_F64, UR32=None, workspace=None,
               stream=None, allow=(ENOCONV, EBREAKDOWN)):
         """Returns (status, [stats dict per rhs])."""
@@ -216,10 +242,11 @@ class Lattice:
         _check(rc, 'cg_eo', allow)
         return rc, [s.as_dict() for s in stats]
 
-    def force_eo(self, P, x_e, UR64, m0, scale=1.0, accumulate=0, workspace=None, stream=None):
+    def force_eo(self, out, x_e, UR64, m0, U=None, scale=1.0, accumulate=0, workspace=None, stream=None):
+        """out = scale * P (U None) or scale * 2i P U (U given), see include/wdirac.h."""
         ws = workspace if workspace is not None else self.new_workspace(OP_FORCE, 1, F64)
-        _check(_lib.wdirac_force_eo(self._h, _ptr(P), _ptr(x_e), _ptr(UR64), float(m0), float(scale), accumulate,
-                                    _ptr(ws), _stream(stream)), 'force_eo')
+        _check(_lib.wdirac_force_eo(self._h, _ptr(out), _ptr(x_e), _ptr(UR64), _ptr(U), float(m0), float(scale),
+                                    accumulate, _ptr(ws), _stream(stream)), 'force_eo')
 
     # ------------------------------------------------------- conveniences
     def spinor_dtype(self, prec):

@@ -1,0 +1,147 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times.  The oracle cannot hold these lattices, so it computes sampled
+output sites one by one from their gathered neighbourhoods (links and spinors
+copied back from the device inputs), and whole-lattice properties (true
+residuals, agreement of solver modes) are checked where sampling cannot reach.
+
+Sizes: SU(3) FUND 32^4, SU(4) 2AS 96x48^3, SU(3) SYM 48x24^3 (12 right-hand
+sides), SU(2) ADJ 32x16^3."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import TOL, log, rel, wdirac
+from oracle import dirac as D
+from oracle import lattice as L
+from oracle import reps as R
+from paper_2503_06721_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+NSAMPLE = 192
+
+
+@pytest.fixture(scope='module')
+def W():
+    assert torch.cuda.is_available(), 'GPU tests need a GPU'
+    return wdirac()
+
+
+def gen_links(cfg):
+    """Device links for a configuration (host recipe where it is fast, the
+    torch recipe for the 42M-link SU(4) lattice)."""
+    if np.prod(cfg['dims']) * 4 * cfg['N'] ** 2 > 60_000_000:
+        return synth.expH_links_torch(cfg['dims'], cfg['N'], cfg['eps'], cfg['seed'])
+    return torch.from_numpy(synth.links_for(cfg)).cuda()
+
+
+def sample_sites(dims, parity, n, seed):
+    """n sites of the given parity: corners, the last site, and random ones."""
+    rng = np.random.default_rng(seed)
+    T, X, Y, Z = dims
+    cands = [(0, 0, 0, 0), (T - 1, X - 1, Y - 1, Z - 1), (T - 1, 0, 0, 0), (0, X - 1, Y - 1, 0),
+             (T - 1, X - 1, Y - 1, Z - 2)]
+    out = []
+    for c in cands:
+        c = list(c)
+        if sum(c) % 2 != parity:
+            c[3] = (c[3] + 1) % Z
+        out.append(c)
+    while len(out) < n:
+        c = [int(rng.integers(L_)) for L_ in dims]
+        if sum(c) % 2 == parity:
+            out.append(c)
+    return np.array(out)
+
+
+def gather(t, coords):
+    """t[coords] for a device tensor with leading (T, X, Y, Z) axes, to host."""
+    idx = torch.from_numpy(coords.T.copy()).to(t.device)
+    return t[idx[0], idx[1], idx[2], idx[3]].cpu().numpy()
+
+
+def oracle_hop_sampled(U, psi, coords, rep, bc, dims, dagger=False):
+    """Oracle (H psi)(x) at the sampled sites from gathered neighbourhoods."""
+    n = len(coords)
+    cb = [L.neighbour(coords, mu, -1, dims) for mu in range(4)]
+    cf = [L.neighbour(coords, mu, +1, dims) for mu in range(4)]
+    Ux = gather(U, coords)                                   # (n, 4, N, N)
+    UR_f = R.represent(Ux, rep)
+    UR_b = np.stack([R.represent(gather(U, cb[mu][0])[:, mu], rep) for mu in range(4)], axis=1)
+    pf = np.stack([gather(psi, cf[mu][0]) for mu in range(4)], axis=1)
+    pb = np.stack([gather(psi, cb[mu][0]) for mu in range(4)], axis=1)
+    wf = np.stack([cf[mu][1] for mu in range(4)], axis=1)
+    wb = np.stack([cb[mu][1] for mu in range(4)], axis=1)
+    assert pf.shape[:2] == (n, 4)
+    return D.hop_at_sites(coords, UR_f, UR_b, pf.astype(np.complex128), pb.astype(np.complex128), wf, wb, bc,
+                          dagger=dagger)
+
+
+CASES = [('su3_fund_32x32x32x32', 0, 1), ('su3_fund_32x32x32x32', 1, 1), ('su4_2as_96x48x48x48', 0, 1),
+         ('su4_2as_96x48x48x48', 1, 1), ('su3_sym_48x24x24x24', 0, 12), ('su3_sym_48x24x24x24', 1, 12),
+         ('su2_adj_32x16x16x16', 0, 1)]
+
+
+@pytest.mark.parametrize('name,prec,nrhs', CASES)
+def test_dslash_full_size_sampled(W, name, prec, nrhs):
+    cfg = synth.CONFIGS[name]
+    dims, N, rep, bc = cfg['dims'], cfg['N'], cfg['rep'], cfg['bc']
+    log(f'full-size dslash {name} prec={prec} nrhs={nrhs}: generating inputs')
+    U = gen_links(cfg)
+    lat = W.Lattice(N, rep, dims, bc)
+    UR = lat.new_links(prec)
+    lat.rep_links(UR, U, prec)
+    g = torch.Generator(device='cuda')
+    g.manual_seed(cfg['seed'] + 7)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    psi = torch.randn((nrhs,) + tuple(dims) + (4, lat.d), dtype=dt, device='cuda', generator=g)
+    for p, dagger in ((0, 0), (1, 1)):
+        log(f'  parity {p} dagger {dagger}')
+        inp = lat.pack_half(psi, 1 - p, nrhs, prec)
+        out = lat.new_half(nrhs, prec)
+        lat.dslash_eo(out, inp, UR, p, dagger, nrhs, 0.0, None, 1.0, prec)
+        res = lat.unpack_half(out, p, nrhs, prec)
+        coords = sample_sites(dims, p, NSAMPLE, cfg['seed'] + p)
+        for r in range(0, nrhs, max(1, nrhs // 3)):
+            exp = oracle_hop_sampled(U, psi[r], coords, rep, bc, dims, dagger=bool(dagger))
+            got = gather(res[r], coords).astype(np.complex128)
+            err = rel(got, exp)
+            log(f'    rhs {r}: sampled relative error {err:.2e}')
+            assert err < TOL[prec], err
+        del inp, out, res
+    del U, UR, psi
+    torch.cuda.empty_cache()
+
+
+def test_cg_su4_2as_mixed_vs_f64(W):
+    """SU(4) 2AS 96x48^3: FP64 CG and mixed CG both reach the FP64 true
+    residual 1e-10 (recomputed by the library's FP64 operator) and agree."""
+    cfg = synth.CONFIGS['su4_2as_96x48x48x48']
+    log('full-size CG su4 2as: generating inputs')
+    U = gen_links(cfg)
+    lat = W.Lattice(cfg['N'], cfg['rep'], cfg['dims'], cfg['bc'])
+    UR64, UR32 = lat.new_links(W.F64), lat.new_links(W.F32)
+    lat.rep_links(UR64, U, W.F64)
+    lat.rep_links(UR32, U, W.F32)
+    del U
+    g = torch.Generator(device='cuda')
+    g.manual_seed(cfg['seed'] + 11)
+    eta = torch.randn((1,) + tuple(cfg['dims']) + (4, lat.d), dtype=torch.complex128, device='cuda', generator=g)
+    eta_e = lat.pack_half(eta, 0)
+    del eta
+    b = lat.new_half()
+    lat.apply_dhat(b, eta_e, UR64, cfg['m0'], dagger=1)
+    ws = lat.new_workspace(W.OP_CG, 1, W.CG_MIXED)
+    out = {}
+    for mode in (W.CG_F64, W.CG_MIXED):
+        x = lat.new_half()
+        rc, st = lat.cg_eo(x, b, UR64, cfg['m0'], tol=1e-10, maxit=20000, mode=mode, UR32=UR32, workspace=ws)
+        log(f'  mode {mode}: {st[0]}')
+        assert rc == W.OK and st[0]['true_rel_resid'] <= 1e-10
+        out[mode] = (x, st[0])
+    diff = out[W.CG_MIXED][0].view(torch.complex128) - out[W.CG_F64][0].view(torch.complex128)
+    rdiff = (torch.linalg.vector_norm(diff) / torch.linalg.vector_norm(out[W.CG_F64][0].view(torch.complex128))).item()
+    log(f'  ||x_mixed - x_f64|| / ||x_f64|| = {rdiff:.2e}; speedup '
+        f'{out[W.CG_F64][1]["seconds"] / out[W.CG_MIXED][1]["seconds"]:.2f}x')
+    # both solve to 1e-10; their difference is bounded by cond(A) * 2e-10
+    assert rdiff < 1e-4

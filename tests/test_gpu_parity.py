@@ -93,6 +93,40 @@ def test_dslash_eo(W, N, rep, dims):
                         assert err < TOL[prec], (variant, prec, p, dagger, alpha, err)
 
 
+@pytest.mark.parametrize('N,rep', [(3, 'FUND'), (3, 'SYM'), (2, 'ADJ'), (4, 'FUND')])
+def test_dslash_rhs_groups(W, N, rep):
+    """Several right-hand sides sharing each link load (1..4 per block), with a
+    ragged tile tail; every rhs must equal its own single-rhs hop."""
+    s = Setup(N, rep, (4, 6, 4, 6), seed=250 + N)
+    for nrhs in (4, 6, 12):
+        psi = s.spinor(251 + nrhs, nrhs)
+        for prec in (0, 1):
+            for nr in (1, 2, 3, 4):
+                s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, nr)
+                log(f'rhs groups N={N} rep={rep} nrhs={nrhs} prec={prec} nr={nr}')
+                for p, dagger in ((0, 0), (1, 1)):
+                    inp = s.to_gpu_half(psi, 1 - p, prec)
+                    out = s.lat.new_half(nrhs, prec)
+                    s.lat.dslash_eo(out, inp, s.URg[prec], p, dagger, nrhs, 0.0, None, 1.0, prec)
+                    got = s.from_gpu_half(out, p, nrhs, prec)
+                    exp = hop_expect(s, psi, p, dagger, 0.0, 1.0, None)
+                    assert rel(got, exp) < TOL[prec], (nrhs, prec, nr, p)
+
+
+def test_autotune_keeps_results(W):
+    s = Setup(3, 'SYM', (4, 6, 4, 6), seed=260)
+    for prec in (0, 1):
+        for nrhs in (1, 4):
+            best = s.lat.autotune(s.URg[prec], prec, nrhs)
+            log(f'autotune prec={prec} nrhs={nrhs}: {best}')
+            assert best['candidates'] >= 2 and best['us'] > 0
+            psi = s.spinor(261, nrhs)
+            inp = s.to_gpu_half(psi, 1, prec)
+            out = s.lat.new_half(nrhs, prec)
+            s.lat.dslash_eo(out, inp, s.URg[prec], 0, 0, nrhs, 0.0, None, 1.0, prec)
+            assert rel(s.from_gpu_half(out, 0, nrhs, prec), hop_expect(s, psi, 0, 0, 0.0, 1.0, None)) < TOL[prec]
+
+
 def test_dslash_in_place_xadd(W):
     """x_add may alias out (documented)."""
     s = Setup(3, 'FUND', (4, 6, 4, 6), seed=300, precs=(0,))
@@ -147,6 +181,22 @@ def test_norm2(W):
     got = s.lat.norm2(g, nrhs=3)
     exp = [norm2(h) for h in s.half(psi, 1)]
     assert np.allclose(got, exp, rtol=1e-14, atol=0)
+
+
+def test_dot(W):
+    from oracle.reductions import inner
+    s = Setup(2, 'SYM', (4, 6, 4, 6), seed=510, precs=(0,))
+    a, b = s.spinor(511, nrhs=2), s.spinor(512, nrhs=2)
+    ga, gb = s.to_gpu_half(a, 0), s.to_gpu_half(b, 0)
+    got = s.lat.dot(ga, gb, nrhs=2)
+    for k in range(2):
+        exp = inner(s.half(a, 0)[k], s.half(b, 0)[k])
+        assert abs(got[k] - exp) <= 1e-14 * abs(exp)
+    # norms of FP32 fields are accumulated in FP64
+    g32 = s.to_gpu_half(a, 0, prec=1)
+    n32 = s.lat.norm2(g32, nrhs=2, prec=1)
+    exp32 = [norm2(h) for h in s.half(a.astype(np.complex64).astype(np.complex128), 0)]
+    assert np.allclose(n32, exp32, rtol=1e-13, atol=0)
 
 
 def solve_problem(s, m, seed):
@@ -239,3 +289,8 @@ def test_force(W, N, rep, m):
     assert rel(got, exp) < TOL[0], rel(got, exp)
     s.lat.force_eo(P, xg, s.URg[0], m, scale=-0.5, accumulate=1)
     assert rel(P.cpu().numpy(), 0.5 * exp) < TOL[0]
+    # gradient form G = 2i P U (dS = Re tr(G^+ dU) for dU = i w T U)
+    G = torch.zeros_like(P)
+    s.lat.force_eo(G, xg, s.URg[0], m, U=s.Ug, scale=1.0)
+    expG = 2j * np.einsum('...ij,...jk->...ik', exp, s.U)
+    assert rel(G.cpu().numpy(), expG) < TOL[0]
