@@ -45,6 +45,30 @@ def hop_bytes_per_site(d, real, prec_bytes):
     return 8 * link + 2 * spinor
 
 
+def effective_bytes_per_site(d, real, prec_bytes):
+    """The paper's "effective" byte count per output site: 8 links, 8
+    neighbour spinors and the output spinor, as if nothing were cached."""
+    link = d * d * prec_bytes * (1 if real else 2)
+    spinor = 4 * d * 2 * prec_bytes
+    return 8 * link + 9 * spinor
+
+
+def device_copy_gbps(torch, n=1 << 28, reps=3):
+    """Read + write bandwidth of a 2 GiB device-to-device copy (HIP events)."""
+    a = torch.ones(n, dtype=torch.float64, device='cuda')
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return ms, 2 * n * 8 / ms / 1e6
+
+
 def measured_traffic(launch_bytes):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None if the hop kernel source changed since the counters were taken."""
@@ -85,6 +109,58 @@ def cpu_baseline(cfg, U, psi, seconds_target=15.0):
             'seconds_per_hop': t_hop / n}
 
 
+def multi_rhs_cg(W, torch, synth, name='su3_sym_48x24x24x24'):
+    """Time-to-1e-10 of the even-odd CG for 12 point sources on one gauge
+    field: all 12 in one batched solve (every hop streams each link once for
+    the 12 sources) against 12 single-source solves, in FP64 and in mixed
+    precision.  Run once, after the timed steps."""
+    cfg = synth.CONFIGS[name]
+    dims, m0, nrhs = cfg['dims'], cfg['m0'], cfg['nrhs']
+    log(f'[bench] multi-rhs CG on {name}: generating inputs')
+    lat = W.Lattice(cfg['N'], cfg['rep'], dims, cfg['bc'])
+    Ug = torch.from_numpy(synth.links_for(cfg)).cuda()
+    UR64, UR32 = lat.new_links(W.F64), lat.new_links(W.F32)
+    lat.rep_links(UR64, Ug, W.F64)
+    lat.rep_links(UR32, Ug, W.F32)
+    del Ug
+    src = torch.from_numpy(synth.point_sources(dims, lat.d, nrhs)).cuda()
+    eta_e, eta_o = lat.pack_half(src, 0, nrhs), lat.pack_half(src, 1, nrhs)
+    del src
+    bp, b = lat.new_half(nrhs), lat.new_half(nrhs)
+    lat.eo_source(bp, eta_e, eta_o, UR64, m0, nrhs)
+    lat.apply_dhat(b, bp, UR64, m0, dagger=1, nrhs=nrhs)
+    del bp, eta_e, eta_o
+    for prec, UR in ((W.F64, UR64), (W.F32, UR32)):
+        lat.autotune(UR, prec, nrhs)
+        lat.autotune(UR, prec, 1)
+    ws = lat.new_workspace(W.OP_CG, nrhs, W.CG_MIXED)
+    x = lat.new_half(nrhs)
+    per = x.numel() // nrhs
+    out = {'workload': name, 'sources': f'{nrhs} point sources (spin k%4, colour k//4) at the origin'}
+    for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
+        x.zero_()
+        rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, nrhs=nrhs, mode=mode, UR32=UR32, workspace=ws)
+        batched = st[0]['seconds']
+        worst = max(s['true_rel_resid'] for s in st)
+        log(f'[bench]   batched {key}: {batched:.3f} s, iters {[s["iters"] for s in st]}, worst residual {worst:.2e}')
+        seq, its = 0.0, []
+        for r in range(nrhs):
+            xr, br = x[r * per:(r + 1) * per], b[r * per:(r + 1) * per]
+            xr.zero_()
+            rc1, st1 = lat.cg_eo(xr, br, UR64, m0, tol=1e-10, maxit=20000, nrhs=1, mode=mode, UR32=UR32,
+                                 workspace=ws)
+            seq += st1[0]['seconds']
+            its.append(st1[0]['iters'])
+            worst = max(worst, st1[0]['true_rel_resid'])
+        log(f'[bench]   {nrhs} single solves {key}: {seq:.3f} s, iters {its}')
+        out[key] = {'batched_seconds': round(batched, 4), 'sequential_seconds': round(seq, 4),
+                    'batched_speedup': round(seq / batched, 3), 'max_iters': max(s['iters'] for s in st),
+                    'worst_true_rel_resid': worst, 'status': W.STATUS_NAMES.get(rc)}
+    out['mixed_batched_vs_f64_sequential'] = round(out['f64']['sequential_seconds'] / out['mixed']['batched_seconds'],
+                                                   3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -93,14 +169,25 @@ def main():
     ap.add_argument('--hops', type=int, default=50, help='dslash_eo launches timed per step')
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU-oracle baseline')
     ap.add_argument('--no-cg', action='store_true', help='profiling aid: hops and links only')
+    ap.add_argument('--no-multi', action='store_true', help='skip the 12-source batched-vs-single CG comparison')
+    ap.add_argument('--copy-calibration', action='store_true',
+                    help='run only a device copy of 2 GiB (x3), the known-size kernel that calibrates the '
+                         'FETCH_SIZE / WRITE_SIZE counters, and print its bandwidth')
     args = ap.parse_args()
     if args.gpus != 1:
         print(f'bench.py measures one GPU only; --gpus {args.gpus} is not supported '
-              f'(the multi-GPU decomposition is a design, not part of this build)', file=sys.stderr)
+              f'(how the path would shard over several GPUs is described in the design notes, not implemented)', file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = 1 << 28
+        ms, g = device_copy_gbps(torch, n)
+        print(json.dumps({'copy_bytes_read': n * 8, 'copy_bytes_written': n * 8, 'copies': 4,
+                          'ms_per_copy': round(ms, 4), 'GBps_read_plus_write': round(g, 1)}))
+        return
 
     from paper_2503_06721_amd import synth
     from paper_2503_06721_amd import wdirac as W
@@ -171,10 +258,11 @@ def main():
     wall = time.perf_counter() - t0
 
     hop_ms = float(np.mean([r['hop_ms'] for r in recs]))
+    copy_gbs = round(device_copy_gbps(torch)[1], 1)
     gbs = bytes_per_launch / (hop_ms * 1e-3) / 1e9
     traffic = measured_traffic(bytes_per_launch)
     out = {
-        'metric': 'dslash_eo bandwidth on compulsory bytes (FP64)',
+        'metric': 'Dslash GB/s & % HBM roofline; CG time-to-1e-10 (FP64 vs mixed/multi-RHS)',
         'value': round(gbs, 2),
         'unit': 'GB/s',
         'n_gpus': 1,
@@ -193,6 +281,12 @@ def main():
         'roofline': {'bound': 'hbm', 'achieved': round(gbs, 2), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
                      'frac': round(gbs / HBM_PEAK_GBS, 4),
                      'traffic': traffic,
+                     'traffic_unit': 'HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, calibrated '
+                                     'on a 2 GiB copy)',
+                     'traffic_GBps': None if traffic is None else round(traffic / (hop_ms * 1e-3) / 1e9, 2),
+                     'effective_GBps': round(effective_bytes_per_site(d, lat.real, 8) * lat.Vh / (hop_ms * 1e-3)
+                                             / 1e9, 2),
+                     'device_copy_GBps': copy_gbs,
                      'kernel': variant_name[tuned['f64']['variant']] + f' d=3 complex FP64, '
                                f'xcd_remap={tuned["f64"]["xcd_remap"]}',
                      'bytes_per_launch': bytes_per_launch, 'us_per_launch': round(hop_ms * 1e3, 3)},
@@ -206,6 +300,10 @@ def main():
         out['cg_time_to_1e-10'] = {'f64': agg('f64'), 'mixed': agg('mixed')}
         out['cg_time_to_1e-10']['mixed_speedup'] = round(
             out['cg_time_to_1e-10']['f64']['seconds'] / out['cg_time_to_1e-10']['mixed']['seconds'], 3)
+    if not args.no_cg and not args.no_multi:
+        del halves, x64, xmix, ws_cg, b, UR32
+        torch.cuda.empty_cache()
+        out['cg_multi_rhs_time_to_1e-10'] = multi_rhs_cg(W, torch, synth)
     if not args.no_cpu:
         log('[bench] timing the CPU oracle on a bounded sample')
         cb = cpu_baseline(cfg, U, psi[0])

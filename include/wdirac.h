@@ -92,6 +92,17 @@ typedef struct {
  * wdirac_destroy).  Errors: EINVAL, EUNSUPPORTED. */
 int wdirac_create(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *geom);
 
+/* Create a context for a batch of nlat (1..8) lattices of possibly different
+ * extents and boundary conditions, same Ng and representation: every call on
+ * the context processes all lattices at once (one launch per kernel).  Packed
+ * fields and links of a batch are the per-lattice objects one after the
+ * other, lattice by lattice; canonical batch layouts are the per-lattice
+ * canonical arrays one after the other ([lattice][T][X][Y][Z]...).  A batch
+ * carries one right-hand side per lattice (nrhs = 1 in every call); results
+ * that are per right-hand side (norms, dots, CG statistics) are per lattice.
+ * Same errors as wdirac_create; EINVAL also for nlat out of range. */
+int wdirac_create_batch(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *geoms, int nlat);
+
 /* Release a context (NULL is accepted). */
 int wdirac_destroy(wdirac_ctx *ctx);
 
@@ -109,6 +120,11 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                      convergence (default 4, 1..1000)
  *   WDIRAC_OPT_MIXED_DELTA             reliable-update trigger of mixed CG,
  *                                      ||r|| < delta max ||r|| (default 0.1)
+ *   WDIRAC_OPT_TILE_TBLOCK             0 (default) = site tiles in lexicographic
+ *                                      order; b > 0 = in t-blocks of b slices
+ *                                      (t-neighbours close in time; used when
+ *                                      b divides T and tiles do not straddle
+ *                                      (t, x) rows)
  *   WDIRAC_OPT_HOP_NR_F64 / _F32       right-hand sides sharing each link load
  *                                      in the colour-split form (1..4; the
  *                                      largest divisor of nrhs not above it
@@ -122,7 +138,8 @@ typedef enum {
   WDIRAC_OPT_CG_CHECK_EVERY = 3,
   WDIRAC_OPT_MIXED_DELTA = 4,
   WDIRAC_OPT_HOP_NR_F64 = 5,
-  WDIRAC_OPT_HOP_NR_F32 = 6
+  WDIRAC_OPT_HOP_NR_F32 = 6,
+  WDIRAC_OPT_TILE_TBLOCK = 7
 } wdirac_option;
 int wdirac_set_option(wdirac_ctx *ctx, int option, double value);
 
@@ -131,6 +148,7 @@ typedef struct {
   int32_t variant;    /* 0 = one lane per site, 1 = colour-split, 2 = paired */
   int32_t nr;         /* right-hand sides per block (colour-split form)  */
   int32_t xcd_remap;  /* 1 = contiguous tile ranges per XCD               */
+  int32_t tblock;     /* t-block of the tile order (0 = lexicographic)    */
   int32_t candidates; /* number of shapes timed                           */
   double us;          /* mean time of one hop launch with that shape      */
 } wdirac_tuning;
@@ -228,7 +246,8 @@ int wdirac_eo_reconstruct(const wdirac_ctx *ctx, void *psi_o, const void *psi_e,
 
 /* Squared norms ||v_k||^2 of the nrhs packed half spinors v (precision prec),
  * summed in FP64 with compensated (Neumaier, Sec. 5.1.1) accumulation of the
- * block partial sums; written to the host array out[nrhs].  Synchronises.
+ * block partial sums; written to the host array out[nsys] (nsys = nrhs, or
+ * the number of lattices of a batch).  Synchronises.
  * workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_NORM, nrhs, prec). */
 int wdirac_norm2(const wdirac_ctx *ctx, double *out, const void *v, int nrhs, int prec, void *workspace,
                  void *stream);
@@ -236,7 +255,8 @@ int wdirac_norm2(const wdirac_ctx *ctx, double *out, const void *v, int nrhs, in
 /* Inner products <a_k, b_k> = sum over sites, spins and colours of
  * conj(a) b (Sec. 4.2.2) for the nrhs packed half spinors a, b (precision
  * prec), summed in FP64 with compensated accumulation of the block partial
- * sums; written to the host array out[2 nrhs] as (re, im) pairs.
+ * sums; written to the host array out[2 nsys] as (re, im) pairs (nsys =
+ * nrhs, or the number of lattices of a batch).
  * Synchronises.  workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_DOT, nrhs,
  * prec).  Errors: EINVAL, EHIP. */
 int wdirac_dot(const wdirac_ctx *ctx, double *out, const void *a, const void *b, int nrhs, int prec,
@@ -249,7 +269,8 @@ int wdirac_dot(const wdirac_ctx *ctx, double *out, const void *a, const void *b,
  * mode WDIRAC_CG_F64: all in FP64, UR32 unused (may be NULL).  mode
  * WDIRAC_CG_MIXED: FP32 hops and vectors inside, FP64 solution, FP64
  * residual replacements ("reliable updates") and FP64 inner-product sums;
- * UR32 = the FP32 links.  stats: host array of nrhs records.  Returns OK,
+ * UR32 = the FP32 links.  stats: host array of nsys records (nsys = nrhs,
+ * or the number of lattices of a batch).  Returns OK,
  * ENOCONV (some rhs reached maxit), EBREAKDOWN, EINVAL or EHIP.  workspace:
  * wdirac_workspace_bytes(ctx, WDIRAC_OP_CG, nrhs, mode).  Synchronises. */
 int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32,

@@ -14,16 +14,20 @@
 #include "wd_kernels.h"
 
 struct wdirac_tuned {
-  int valid, variant, nr, xcd_remap;
+  int valid, variant, nr, xcd_remap, tblock;
 };
 
 struct wdirac_ctx {
   int N, rep, d, real;
-  wd::Geom g;
+  int nlat;                        // lattices of a batch (1 for a single lattice)
+  wd::Geom g[wd::MAXLAT];
+  long long spre[wd::MAXLAT + 1];  // prefix sums of the packed row strides (sites)
+  long long vpre[wd::MAXLAT + 1];  // prefix sums of the lattice volumes (canonical sites)
   int hop_variant[2];   // per precision (F64, F32): wd::HOP_SITE, HOP_COLOUR or HOP_COLOUR_PAIR
   int hop_nr[2];        // preferred right-hand sides per colour-split block
   wdirac_tuned tuned[2][13];   // autotuned shape per (precision, nrhs)
   int xcd_remap;
+  int tblock;           // t-blocked tile order (0 = lexicographic)
   int cg_check_every;   // CG iterations between host convergence checks
   double mixed_delta;   // reliable-update trigger ||r|| < delta max||r||
 };
@@ -62,10 +66,27 @@ int rep_dim(int N, int rep) {
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
 size_t half_bytes(const wdirac_ctx *c, int nrhs, int prec) {
-  return (size_t)nrhs * 4 * c->d * c->g.stride * (prec == WDIRAC_F64 ? 16 : 8);
+  return (size_t)nrhs * 4 * c->d * c->spre[c->nlat] * (prec == WDIRAC_F64 ? 16 : 8);
 }
 
-wd::FieldShape shape(const wdirac_ctx *c, int nrhs) { return wd::FieldShape{c->g.Vh, c->g.stride, 4 * c->d, nrhs}; }
+// Independent systems of a packed field: the right-hand sides of a single
+// lattice, or the lattices of a batch (one right-hand side each).
+int nsys_of(const wdirac_ctx *c, int nrhs) { return c->nlat == 1 ? nrhs : c->nlat; }
+
+wd::FieldShape shape(const wdirac_ctx *c, int nrhs) {
+  wd::FieldShape f{};
+  f.ncomp = 4 * c->d;
+  f.nsys = nsys_of(c, nrhs);
+  f.maxvh = 0;
+  for (int s = 0; s < f.nsys; ++s) {
+    const int l = c->nlat == 1 ? 0 : s;
+    f.vh[s] = c->g[l].Vh;
+    f.stride[s] = c->g[l].stride;
+    f.off[s] = c->nlat == 1 ? (long long)s * f.ncomp * c->g[0].stride : (long long)f.ncomp * c->spre[l];
+    f.maxvh = std::max(f.maxvh, f.vh[s]);
+  }
+  return f;
+}
 
 hipStream_t S(void *s) { return static_cast<hipStream_t>(s); }
 
@@ -79,6 +100,11 @@ int check_prec(int prec) {
 }
 int check_nrhs(int nrhs) {
   if (nrhs < 1 || nrhs > 12) return fail(WDIRAC_EINVAL, "nrhs must be in [1, 12]");
+  return WDIRAC_OK;
+}
+int check_nrhs(const wdirac_ctx *c, int nrhs) {
+  WD_TRY(check_nrhs(nrhs));
+  if (c->nlat > 1 && nrhs != 1) return fail(WDIRAC_EINVAL, "a batch of lattices carries one right-hand side");
   return WDIRAC_OK;
 }
 int check_parity(int p) {
@@ -102,11 +128,12 @@ struct Carver {
 };
 
 size_t partial_doubles(const wdirac_ctx *c, int nrhs) {
-  // enough for any producer of per-block partial sums
-  const int nb = std::max(wd::hop_nblocks(c->g.Vh, c->d, wd::HOP_COLOUR),
-                          std::max(wd::hop_nblocks(c->g.Vh, c->d, wd::HOP_SITE),
-                                   wd::blas_nblocks(shape(c, nrhs))));
-  return (size_t)nrhs * nb;
+  // rows (one per system, twice for the real and imaginary rows of a dot) of
+  // the longest per-tile row any producer writes: the smallest tiles are the
+  // 64-site tiles of the colour-split hop
+  int mx = 0;
+  for (int l = 0; l < c->nlat; ++l) mx = std::max(mx, (c->g[l].Vh + 63) / 64);
+  return (size_t)2 * nsys_of(c, nrhs) * mx;
 }
 
 struct CgWork {
@@ -129,7 +156,7 @@ CgWork carve_cg(const wdirac_ctx *c, int nrhs, int mode, void *ws) {
   }
   w.P1 = static_cast<double *>(cv.take(partial_doubles(c, nrhs) * sizeof(double)));
   w.P2 = static_cast<double *>(cv.take(partial_doubles(c, nrhs) * sizeof(double)));
-  w.sc = static_cast<wd::CgScalars *>(cv.take(nrhs * sizeof(wd::CgScalars)));
+  w.sc = static_cast<wd::CgScalars *>(cv.take(nsys_of(c, nrhs) * sizeof(wd::CgScalars)));
   w.bytes = cv.off;
   return w;
 }
@@ -143,41 +170,66 @@ int effective_nr(const wdirac_ctx *c, int pref, int nrhs, int prec, int variant)
   return std::max(nr, 1);
 }
 
-// One hopping-term launch.
+// One hopping-term launch over every lattice of the context.  counts/prow
+// (nullable) receive the layout of the per-tile partial sums.
 int hop(const wdirac_ctx *c, void *out, const void *in, const void *UR, int out_parity, int dagger, int nrhs,
-        double alpha, const void *xadd, double beta, int prec, double *partial, hipStream_t st, int *nblk = nullptr) {
-  int variant = c->hop_variant[prec], pref = c->hop_nr[prec], remap = c->xcd_remap;
+        double alpha, const void *xadd, double beta, int prec, double *partial, hipStream_t st,
+        wd::Counts *counts = nullptr, int *prow = nullptr) {
+  int variant = c->hop_variant[prec], pref = c->hop_nr[prec], remap = c->xcd_remap, tblock = c->tblock;
   const wdirac_tuned &tn = c->tuned[prec][nrhs];
   if (tn.valid) {
     variant = tn.variant;
     pref = tn.nr;
     remap = tn.xcd_remap;
+    tblock = tn.tblock;
   }
   wd::HopArgs a;
   a.out = out;
   a.in = in;
   a.links = UR;
   a.xadd = xadd;
-  a.g = c->g;
+  a.nlat = c->nlat;
+  for (int l = 0; l < c->nlat; ++l) {
+    a.lat[l].g = c->g[l];
+    a.lat[l].tile0 = a.lat[l].ntiles = 0;
+    a.lat[l].soff = c->nlat == 1 ? 0 : (long long)4 * c->d * c->spre[l];
+    a.lat[l].loff = (long long)8 * c->d * c->d * c->spre[l];
+  }
   a.parity = out_parity;
   a.xcd_remap = remap;
   a.alpha = alpha;
   a.beta = beta;
   a.partial = partial;
-  int nb = 0;
-  a.ntiles = a.ngroups = 0;
+  a.prow = a.ntiles = a.ngroups = 0;
+  a.tblock = c->nlat == 1 ? tblock : 0;
+  a.tiles_per_tx = 0;
+  wd::Counts cnt{};
+  int pr = 0;
   WD_HIP(wd::launch_hop(a, c->d, c->real, prec, dagger, nrhs, variant, effective_nr(c, pref, nrhs, prec, variant),
-                        st, &nb));
-  if (nblk) *nblk = nb;
+                        st, &cnt, &pr));
+  if (counts) *counts = cnt;
+  if (prow) *prow = pr;
   return WDIRAC_OK;
 }
 
 // out = D-hat in (dagger = 0) or D-hat^+ in (dagger = 1); tmp is an odd half field.
 int dhat(const wdirac_ctx *c, void *out, const void *in, const void *UR, double m0, int dagger, int nrhs, int prec,
-         void *tmp, double *partial, hipStream_t st, int *nblk = nullptr) {
+         void *tmp, double *partial, hipStream_t st, wd::Counts *counts = nullptr, int *prow = nullptr) {
   const double m4 = (4.0 + m0) * (4.0 + m0);
   WD_TRY(hop(c, tmp, in, UR, 1, dagger, nrhs, 0.0, nullptr, 1.0, prec, nullptr, st));
-  WD_TRY(hop(c, out, tmp, UR, 0, dagger, nrhs, m4, in, -1.0, prec, partial, st, nblk));
+  WD_TRY(hop(c, out, tmp, UR, 0, dagger, nrhs, m4, in, -1.0, prec, partial, st, counts, prow));
+  return WDIRAC_OK;
+}
+
+// Canonical <-> packed half spinors, lattice by lattice.  Canonical batch
+// layout: [lattice][T][X][Y][Z][4][d] (one right-hand side).
+int pack(const wdirac_ctx *c, void *packed, void *canon, int parity, int nrhs, int prec, int unpack, hipStream_t st) {
+  const size_t cb = prec == WDIRAC_F64 ? 16 : 8;
+  for (int l = 0; l < c->nlat; ++l) {
+    char *P = static_cast<char *>(packed) + (size_t)4 * c->d * c->spre[l] * cb;
+    char *C = static_cast<char *>(canon) + (size_t)4 * c->d * c->vpre[l] * cb;
+    WD_HIP(wd::launch_pack_spinor(P, C, c->g[l], c->d, parity, nrhs, prec, unpack, st));
+  }
   return WDIRAC_OK;
 }
 
@@ -187,43 +239,65 @@ extern "C" {
 
 const char *wdirac_last_error(void) { return g_err.c_str(); }
 
-int wdirac_create(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *geom) {
+int wdirac_create_batch(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *geoms, int nlat) {
   g_err.clear();
   if (!ctx) return fail(WDIRAC_EINVAL, "ctx is NULL");
   *ctx = nullptr;
-  if (!geom) return fail(WDIRAC_EINVAL, "geom is NULL");
+  if (!geoms) return fail(WDIRAC_EINVAL, "geom is NULL");
+  if (nlat < 1 || nlat > wd::MAXLAT) return fail(WDIRAC_EINVAL, "a batch holds 1 to 8 lattices");
   if (rep < WDIRAC_FUND || rep > WDIRAC_ASYM) return fail(WDIRAC_EINVAL, "unknown representation");
   if (Ng < 2 || Ng > 4) return fail(WDIRAC_EUNSUPPORTED, "Ng must be 2, 3 or 4");
   if (Ng == 2 && rep == WDIRAC_ASYM) return fail(WDIRAC_EUNSUPPORTED, "SU(2) 2AS is one-dimensional (d_R = 1)");
-  int64_t V = 1;
-  for (int mu = 0; mu < 4; ++mu) {
-    const int L = geom->dims[mu];
-    if (L < 2 || (L & 1)) return fail(WDIRAC_EINVAL, "every lattice extent must be even and >= 2");
-    if (geom->bc[mu] != 1 && geom->bc[mu] != -1) return fail(WDIRAC_EINVAL, "bc must be +1 or -1");
-    V *= L;
+  const int d = rep_dim(Ng, rep);
+  int64_t total = 0;
+  for (int l = 0; l < nlat; ++l) {
+    int64_t V = 1;
+    for (int mu = 0; mu < 4; ++mu) {
+      const int L = geoms[l].dims[mu];
+      if (L < 2 || (L & 1)) return fail(WDIRAC_EINVAL, "every lattice extent must be even and >= 2");
+      if (geoms[l].bc[mu] != 1 && geoms[l].bc[mu] != -1) return fail(WDIRAC_EINVAL, "bc must be +1 or -1");
+      V *= L;
+    }
+    if (V > (int64_t)1 << 30) return fail(WDIRAC_EINVAL, "lattice volume above 2^30 sites");
+    total += V;
   }
-  if (V > (int64_t)1 << 30) return fail(WDIRAC_EINVAL, "lattice volume above 2^30 sites");
+  // every packed offset must stay addressable by the kernels' 64-bit arithmetic
+  // and every per-lattice row index by 32-bit ints (checked per lattice above)
+  if (total * 12 * d * d > ((int64_t)1 << 45)) return fail(WDIRAC_EINVAL, "batch too large");
   wdirac_ctx *c = new wdirac_ctx();
   c->N = Ng;
   c->rep = rep;
-  c->d = rep_dim(Ng, rep);
+  c->d = d;
   c->real = rep == WDIRAC_ADJ;
-  c->g.T = geom->dims[0];
-  c->g.X = geom->dims[1];
-  c->g.Y = geom->dims[2];
-  c->g.Z = geom->dims[3];
-  c->g.Vh = (int)(V / 2);
-  c->g.stride = (c->g.Vh + 255) & ~255;   // whole 256-site tiles, see hop.hip
-  for (int mu = 0; mu < 4; ++mu) c->g.bc[mu] = geom->bc[mu];
+  c->nlat = nlat;
+  c->spre[0] = c->vpre[0] = 0;
+  for (int l = 0; l < nlat; ++l) {
+    wd::Geom &g = c->g[l];
+    g.T = geoms[l].dims[0];
+    g.X = geoms[l].dims[1];
+    g.Y = geoms[l].dims[2];
+    g.Z = geoms[l].dims[3];
+    const int64_t V = (int64_t)g.T * g.X * g.Y * g.Z;
+    g.Vh = (int)(V / 2);
+    g.stride = (g.Vh + 255) & ~255;   // whole 256-site tiles, see hop.hip
+    for (int mu = 0; mu < 4; ++mu) g.bc[mu] = geoms[l].bc[mu];
+    c->spre[l + 1] = c->spre[l] + g.stride;
+    c->vpre[l + 1] = c->vpre[l] + V;
+  }
   c->hop_variant[0] = wd::HOP_COLOUR;
   c->hop_variant[1] = wd::HOP_COLOUR;
   c->hop_nr[0] = c->hop_nr[1] = 4;
   std::memset(c->tuned, 0, sizeof(c->tuned));
   c->xcd_remap = 1;
+  c->tblock = 0;
   c->cg_check_every = 4;
   c->mixed_delta = 0.1;
   *ctx = c;
   return WDIRAC_OK;
+}
+
+int wdirac_create(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *geom) {
+  return wdirac_create_batch(ctx, Ng, rep, geom, 1);
 }
 
 int wdirac_destroy(wdirac_ctx *ctx) {
@@ -245,12 +319,12 @@ size_t wdirac_field_bytes(const wdirac_ctx *ctx, int kind, int nrhs, int prec) {
     if (nrhs < 1 || nrhs > 12) return 0;
     return half_bytes(ctx, nrhs, prec);
   }
-  if (kind == WDIRAC_FIELD_LINKS) return (size_t)8 * ctx->d * ctx->d * ctx->g.stride * el * (ctx->real ? 1 : 2);
+  if (kind == WDIRAC_FIELD_LINKS) return (size_t)8 * ctx->d * ctx->d * ctx->spre[ctx->nlat] * el * (ctx->real ? 1 : 2);
   return 0;
 }
 
 size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec) {
-  if (!ctx || nrhs < 1 || nrhs > 12) return 0;
+  if (!ctx || nrhs < 1 || nrhs > 12 || (ctx->nlat > 1 && nrhs != 1)) return 0;
   switch (op) {
     case WDIRAC_OP_DHAT:
       if (prec != WDIRAC_F64 && prec != WDIRAC_F32) return 0;
@@ -261,9 +335,8 @@ size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec)
     case WDIRAC_OP_FORCE:
       return 3 * align256(half_bytes(ctx, 1, WDIRAC_F64));
     case WDIRAC_OP_NORM:
-      return align256(partial_doubles(ctx, nrhs) * sizeof(double)) + align256(nrhs * sizeof(double));
     case WDIRAC_OP_DOT:
-      return align256(2 * partial_doubles(ctx, nrhs) * sizeof(double)) + align256(2 * nrhs * sizeof(double));
+      return align256(partial_doubles(ctx, nrhs) * sizeof(double)) + align256(2 * wd::MAXSYS * sizeof(double));
     case WDIRAC_OP_TUNE:
       if (prec != WDIRAC_F64 && prec != WDIRAC_F32) return 0;
       return 2 * align256(half_bytes(ctx, nrhs, prec));
@@ -293,6 +366,10 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
       if (!(value > 0.0 && value < 1.0)) return fail(WDIRAC_EINVAL, "delta must be in (0, 1)");
       ctx->mixed_delta = value;
       return WDIRAC_OK;
+    case WDIRAC_OPT_TILE_TBLOCK:
+      if (!(value >= 0 && value <= 64)) return fail(WDIRAC_EINVAL, "t-block must be in [0, 64]");
+      ctx->tblock = (int)value;
+      return WDIRAC_OK;
     case WDIRAC_OPT_HOP_NR_F64:
     case WDIRAC_OPT_HOP_NR_F32:
       if (!(value >= 1 && value <= 4)) return fail(WDIRAC_EINVAL, "right-hand sides per block must be in [1, 4]");
@@ -308,21 +385,25 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
   WD_TRY(check_ptr(UR, "UR"));
   WD_TRY(check_ptr(workspace, "workspace"));
   WD_TRY(check_prec(prec));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   const hipStream_t st = S(stream);
   Carver cv{static_cast<char *>(workspace)};
   const size_t hb = half_bytes(ctx, nrhs, prec);
   void *in = cv.take(hb), *out = cv.take(hb);
   WD_HIP(hipMemsetAsync(in, 0, hb, st));
   struct Cand {
-    int variant, nr, remap;
+    int variant, nr, remap, tblock;
   };
   std::vector<Cand> cands;
-  for (int remap = 0; remap < 2; ++remap) {
-    for (int v = wd::HOP_COLOUR; v <= wd::HOP_COLOUR_PAIR; ++v)
-      for (int nr = 1; nr <= 4; ++nr)
-        if (effective_nr(ctx, nr, nrhs, prec, v) == nr) cands.push_back({v, nr, remap});
-    if (wd::hop_variant_ok(ctx->d, wd::HOP_SITE)) cands.push_back({wd::HOP_SITE, 1, remap});
+  const int tbs[] = {0, 2, 4, 8};
+  for (int tb : tbs) {
+    if (tb && (ctx->nlat > 1 || ctx->g[0].T % tb)) continue;
+    for (int remap = 0; remap < 2; ++remap) {
+      for (int v = wd::HOP_COLOUR; v <= wd::HOP_COLOUR_PAIR; ++v)
+        for (int nr = 1; nr <= 4; ++nr)
+          if (effective_nr(ctx, nr, nrhs, prec, v) == nr) cands.push_back({v, nr, remap, tb});
+      if (wd::hop_variant_ok(ctx->d, wd::HOP_SITE)) cands.push_back({wd::HOP_SITE, 1, remap, tb});
+    }
   }
   hipEvent_t e0, e1;
   WD_HIP(hipEventCreate(&e0));
@@ -332,7 +413,7 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
   Cand pick = cands.front();
   int rc = WDIRAC_OK;
   for (const Cand &cd : cands) {
-    slot = wdirac_tuned{1, cd.variant, cd.nr, cd.remap};
+    slot = wdirac_tuned{1, cd.variant, cd.nr, cd.remap, cd.tblock};
     for (int k = 0; k < 3 && rc == WDIRAC_OK; ++k) rc = hop(ctx, out, in, UR, 0, 0, nrhs, 0.0, nullptr, 1.0, prec, nullptr, st);
     if (rc == WDIRAC_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventRecord");
     for (int k = 0; k < 10 && rc == WDIRAC_OK; ++k)
@@ -353,11 +434,12 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
     slot.valid = 0;
     return rc;
   }
-  slot = wdirac_tuned{1, pick.variant, pick.nr, pick.remap};
+  slot = wdirac_tuned{1, pick.variant, pick.nr, pick.remap, pick.tblock};
   if (best) {
     best->variant = pick.variant;
     best->nr = pick.nr;
     best->xcd_remap = pick.remap;
+    best->tblock = pick.tblock;
     best->candidates = (int)cands.size();
     best->us = best_ms * 1e3 / 10.0;
   }
@@ -370,10 +452,9 @@ int wdirac_pack_spinor(const wdirac_ctx *ctx, void *packed, const void *canon, i
   WD_TRY(check_ptr(packed, "packed"));
   WD_TRY(check_ptr(canon, "canon"));
   WD_TRY(check_parity(parity));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   WD_TRY(check_prec(prec));
-  WD_HIP(wd::launch_pack_spinor(packed, canon, ctx->g, ctx->d, parity, nrhs, prec, 0, S(stream)));
-  return WDIRAC_OK;
+  return pack(ctx, packed, const_cast<void *>(canon), parity, nrhs, prec, 0, S(stream));
 }
 
 int wdirac_unpack_spinor(const wdirac_ctx *ctx, void *canon, const void *packed, int parity, int nrhs, int prec,
@@ -382,11 +463,9 @@ int wdirac_unpack_spinor(const wdirac_ctx *ctx, void *canon, const void *packed,
   WD_TRY(check_ptr(packed, "packed"));
   WD_TRY(check_ptr(canon, "canon"));
   WD_TRY(check_parity(parity));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   WD_TRY(check_prec(prec));
-  WD_HIP(wd::launch_pack_spinor(const_cast<void *>(packed), canon, ctx->g, ctx->d, parity, nrhs, prec, 1,
-                                S(stream)));
-  return WDIRAC_OK;
+  return pack(ctx, const_cast<void *>(packed), canon, parity, nrhs, prec, 1, S(stream));
 }
 
 int wdirac_rep_links(const wdirac_ctx *ctx, void *UR, const void *U, int prec, void *stream) {
@@ -394,7 +473,12 @@ int wdirac_rep_links(const wdirac_ctx *ctx, void *UR, const void *U, int prec, v
   WD_TRY(check_ptr(UR, "UR"));
   WD_TRY(check_ptr(U, "U"));
   WD_TRY(check_prec(prec));
-  WD_HIP(wd::launch_rep_links(U, UR, ctx->g, ctx->N, ctx->rep, prec, S(stream)));
+  const size_t el = (prec == WDIRAC_F64 ? 8 : 4) * (ctx->real ? 1 : 2);
+  for (int l = 0; l < ctx->nlat; ++l) {
+    const char *Ul = static_cast<const char *>(U) + (size_t)ctx->vpre[l] * 4 * ctx->N * ctx->N * 16;
+    char *URl = static_cast<char *>(UR) + (size_t)8 * ctx->d * ctx->d * ctx->spre[l] * el;
+    WD_HIP(wd::launch_rep_links(Ul, URl, ctx->g[l], ctx->N, ctx->rep, prec, S(stream)));
+  }
   return WDIRAC_OK;
 }
 
@@ -403,7 +487,13 @@ int wdirac_unpack_links(const wdirac_ctx *ctx, void *UR_canon, const void *UR, i
   WD_TRY(check_ptr(UR, "UR"));
   WD_TRY(check_ptr(UR_canon, "UR_canon"));
   WD_TRY(check_prec(prec));
-  WD_HIP(wd::launch_unpack_links(UR_canon, UR, ctx->g, ctx->d, ctx->real, prec, S(stream)));
+  const size_t el = (prec == WDIRAC_F64 ? 8 : 4) * (ctx->real ? 1 : 2);
+  const size_t cel = ctx->real ? 8 : 16;
+  for (int l = 0; l < ctx->nlat; ++l) {
+    char *Cl = static_cast<char *>(UR_canon) + (size_t)ctx->vpre[l] * 4 * ctx->d * ctx->d * cel;
+    const char *URl = static_cast<const char *>(UR) + (size_t)8 * ctx->d * ctx->d * ctx->spre[l] * el;
+    WD_HIP(wd::launch_unpack_links(Cl, URl, ctx->g[l], ctx->d, ctx->real, prec, S(stream)));
+  }
   return WDIRAC_OK;
 }
 
@@ -414,7 +504,7 @@ int wdirac_dslash_eo(const wdirac_ctx *ctx, void *out, const void *in, const voi
   WD_TRY(check_ptr(in, "in"));
   WD_TRY(check_ptr(UR, "UR"));
   WD_TRY(check_parity(out_parity));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   WD_TRY(check_prec(prec));
   if (dagger != 0 && dagger != 1) return fail(WDIRAC_EINVAL, "dagger must be 0 or 1");
   if (in == out) return fail(WDIRAC_EINVAL, "in and out must not alias");
@@ -426,7 +516,7 @@ static int apply_M(const wdirac_ctx *ctx, void *out, const void *in, double m0, 
   WD_TRY(check_ctx(ctx));
   WD_TRY(check_ptr(out, "out"));
   WD_TRY(check_ptr(in, "in"));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   WD_TRY(check_prec(prec));
   if (inverse && 4.0 + m0 == 0.0) return fail(WDIRAC_EINVAL, "4 + m0 = 0 has no inverse");
   const double f = inverse ? 1.0 / (4.0 + m0) : 4.0 + m0;
@@ -451,7 +541,7 @@ int wdirac_apply_dhat(const wdirac_ctx *ctx, void *out, const void *in, const vo
   WD_TRY(check_ptr(in, "in"));
   WD_TRY(check_ptr(UR, "UR"));
   WD_TRY(check_ptr(workspace, "workspace"));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   WD_TRY(check_prec(prec));
   if (dagger != 0 && dagger != 1) return fail(WDIRAC_EINVAL, "dagger must be 0 or 1");
   if (in == out) return fail(WDIRAC_EINVAL, "in and out must not alias");
@@ -465,7 +555,7 @@ int wdirac_eo_source(const wdirac_ctx *ctx, void *b_e, const void *eta_e, const 
   WD_TRY(check_ptr(eta_e, "eta_e"));
   WD_TRY(check_ptr(eta_o, "eta_o"));
   WD_TRY(check_ptr(UR, "UR"));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   if (b_e == eta_o) return fail(WDIRAC_EINVAL, "b_e must not alias eta_o");
   return hop(ctx, b_e, eta_o, UR, 0, 0, nrhs, 4.0 + m0, eta_e, -1.0, WDIRAC_F64, nullptr, S(stream));
 }
@@ -477,7 +567,7 @@ int wdirac_eo_reconstruct(const wdirac_ctx *ctx, void *psi_o, const void *psi_e,
   WD_TRY(check_ptr(psi_e, "psi_e"));
   WD_TRY(check_ptr(eta_o, "eta_o"));
   WD_TRY(check_ptr(UR, "UR"));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   if (4.0 + m0 == 0.0) return fail(WDIRAC_EINVAL, "4 + m0 = 0 has no inverse");
   if (psi_o == psi_e) return fail(WDIRAC_EINVAL, "psi_o must not alias psi_e");
   const double f = 1.0 / (4.0 + m0);
@@ -490,15 +580,16 @@ int wdirac_norm2(const wdirac_ctx *ctx, double *out, const void *v, int nrhs, in
   WD_TRY(check_ptr(out, "out"));
   WD_TRY(check_ptr(v, "v"));
   WD_TRY(check_ptr(workspace, "workspace"));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   WD_TRY(check_prec(prec));
   Carver cv{static_cast<char *>(workspace)};
   double *part = static_cast<double *>(cv.take(partial_doubles(ctx, nrhs) * sizeof(double)));
-  double *dout = static_cast<double *>(cv.take(nrhs * sizeof(double)));
+  double *dout = static_cast<double *>(cv.take(2 * wd::MAXSYS * sizeof(double)));
   const wd::FieldShape f = shape(ctx, nrhs);
+  const int nb = wd::blas_nblocks(f);
   WD_HIP(wd::launch_norm2_partial(part, v, f, prec, S(stream)));
-  WD_HIP(wd::launch_finalize_sum(dout, part, wd::blas_nblocks(f), nrhs, S(stream)));
-  WD_HIP(hipMemcpyAsync(out, dout, nrhs * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
+  WD_HIP(wd::launch_finalize_sum(dout, part, nb, wd::uniform_counts(nb), f.nsys, f.nsys, S(stream)));
+  WD_HIP(hipMemcpyAsync(out, dout, f.nsys * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
   WD_HIP(hipStreamSynchronize(S(stream)));
   return WDIRAC_OK;
 }
@@ -510,20 +601,21 @@ int wdirac_dot(const wdirac_ctx *ctx, double *out, const void *a, const void *b,
   WD_TRY(check_ptr(a, "a"));
   WD_TRY(check_ptr(b, "b"));
   WD_TRY(check_ptr(workspace, "workspace"));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   WD_TRY(check_prec(prec));
   Carver cv{static_cast<char *>(workspace)};
-  double *part = static_cast<double *>(cv.take(2 * partial_doubles(ctx, nrhs) * sizeof(double)));
-  double *dout = static_cast<double *>(cv.take(2 * nrhs * sizeof(double)));
+  double *part = static_cast<double *>(cv.take(partial_doubles(ctx, nrhs) * sizeof(double)));
+  double *dout = static_cast<double *>(cv.take(2 * wd::MAXSYS * sizeof(double)));
   const wd::FieldShape f = shape(ctx, nrhs);
+  const int nb = wd::blas_nblocks(f), ns = f.nsys;
   WD_HIP(wd::launch_dot_partial(part, a, b, f, prec, S(stream)));
-  WD_HIP(wd::launch_finalize_sum(dout, part, wd::blas_nblocks(f), 2 * nrhs, S(stream)));
-  std::vector<double> tmp(2 * nrhs);
-  WD_HIP(hipMemcpyAsync(tmp.data(), dout, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
+  WD_HIP(wd::launch_finalize_sum(dout, part, nb, wd::uniform_counts(nb), 2 * ns, ns, S(stream)));
+  std::vector<double> tmp(2 * ns);
+  WD_HIP(hipMemcpyAsync(tmp.data(), dout, 2 * ns * sizeof(double), hipMemcpyDeviceToHost, S(stream)));
   WD_HIP(hipStreamSynchronize(S(stream)));
-  for (int k = 0; k < nrhs; ++k) {
+  for (int k = 0; k < ns; ++k) {
     out[2 * k] = tmp[k];
-    out[2 * k + 1] = tmp[nrhs + k];
+    out[2 * k + 1] = tmp[ns + k];
   }
   return WDIRAC_OK;
 }
@@ -551,7 +643,7 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
   WD_TRY(check_ptr(UR64, "UR64"));
   WD_TRY(check_ptr(workspace, "workspace"));
   WD_TRY(check_ptr(stats, "stats"));
-  WD_TRY(check_nrhs(nrhs));
+  WD_TRY(check_nrhs(ctx, nrhs));
   if (mode != WDIRAC_CG_F64 && mode != WDIRAC_CG_MIXED) return fail(WDIRAC_EINVAL, "unknown CG mode");
   if (mode == WDIRAC_CG_MIXED) WD_TRY(check_ptr(UR32, "UR32"));
   if (!(tol > 0.0) || maxit < 0) return fail(WDIRAC_EINVAL, "tol must be > 0 and maxit >= 0");
@@ -560,14 +652,14 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
   const bool mixed = mode == WDIRAC_CG_MIXED;
   CgWork w = carve_cg(ctx, nrhs, mode, workspace);
   const wd::FieldShape f = shape(ctx, nrhs);
-  const int nbb = wd::blas_nblocks(f);
-  std::vector<wd::CgScalars> hs(nrhs);
-  std::vector<int> hops(nrhs, 0), rel(nrhs, 0);
+  const int nbb = wd::blas_nblocks(f), ns = f.nsys;
+  std::vector<wd::CgScalars> hs(ns);
+  std::vector<int> rel(ns, 0);
   int hop_count = 0, updates = 0;
 
   // b2, stop2
   WD_HIP(wd::launch_norm2_partial(w.P2, b, f, WDIRAC_F64, st));
-  WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, nrhs, tol, 1, 1, st));
+  WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, ns, tol, 1, 1, st));
   // r = b - A x (FP64)
   auto true_residual = [&]() -> int {
     WD_TRY(dhat(ctx, w.u, x, UR64, m0, 0, nrhs, WDIRAC_F64, w.t, nullptr, st));
@@ -577,7 +669,7 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
     return WDIRAC_OK;
   };
   WD_TRY(true_residual());
-  WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, nrhs, tol, 0, 1, st));
+  WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, ns, tol, 0, 1, st));
   void *r = w.r, *p = w.p, *q = w.q, *t = w.t, *u = w.u, *v = w.v, *xi = x;
   const void *UR = UR64;
   int prec = WDIRAC_F64;
@@ -594,23 +686,23 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
   int rc = WDIRAC_OK;
   int launched = 0;   // iterations launched since start
   for (;;) {
-    WD_HIP(hipMemcpyAsync(hs.data(), w.sc, nrhs * sizeof(wd::CgScalars), hipMemcpyDeviceToHost, st));
+    WD_HIP(hipMemcpyAsync(hs.data(), w.sc, ns * sizeof(wd::CgScalars), hipMemcpyDeviceToHost, st));
     WD_HIP(hipStreamSynchronize(st));
     bool any_active = false, any_update = false;
-    for (int k = 0; k < nrhs; ++k) {
+    for (int k = 0; k < ns; ++k) {
       any_active |= hs[k].active != 0;
       any_update |= hs[k].need_update != 0;
     }
     int max_iters = 0;
-    for (int k = 0; k < nrhs; ++k) max_iters = std::max(max_iters, hs[k].iters);
+    for (int k = 0; k < ns; ++k) max_iters = std::max(max_iters, hs[k].iters);
     if (!any_active && any_update) {
       // residual replacement in FP64 (verifies convergence of the recursion)
       if (mixed) WD_HIP(wd::launch_accum_x(x, w.x32, f, st));
       WD_TRY(true_residual());
-      WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, nrhs, tol, 0, 0, st));
+      WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, ns, tol, 0, 0, st));
       if (mixed) WD_HIP(wd::launch_convert(w.r32, WDIRAC_F32, w.r, WDIRAC_F64, f, st));
       ++updates;
-      for (int k = 0; k < nrhs; ++k)
+      for (int k = 0; k < ns; ++k)
         if (hs[k].need_update) ++rel[k];
       continue;
     }
@@ -621,12 +713,13 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
     }
     const int nit = std::min(check, std::max(1, maxit - max_iters));
     for (int it = 0; it < nit; ++it) {
-      int nb2 = 0;
-      WD_TRY(dhat(ctx, u, p, UR, m0, 0, nrhs, prec, t, w.P1, st, &nb2));
-      WD_HIP(wd::launch_cg_alpha(w.sc, w.P1, nb2, nrhs, st));
+      wd::Counts cnt{};
+      int prow = 0;
+      WD_TRY(dhat(ctx, u, p, UR, m0, 0, nrhs, prec, t, w.P1, st, &cnt, &prow));
+      WD_HIP(wd::launch_cg_alpha(w.sc, w.P1, prow, cnt, ns, st));
       WD_TRY(dhat(ctx, q, u, UR, m0, 1, nrhs, prec, v, nullptr, st));
       WD_HIP(wd::launch_cg_update_xr(xi, prec, r, p, q, w.sc, w.P2, f, prec, st));
-      WD_HIP(wd::launch_cg_beta(w.sc, w.P2, nbb, nrhs, delta, st));
+      WD_HIP(wd::launch_cg_beta(w.sc, w.P2, nbb, ns, delta, st));
       WD_HIP(wd::launch_cg_update_p(p, r, w.sc, f, prec, st));
       hop_count += 4;
       ++launched;
@@ -635,22 +728,22 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
   if (mixed) WD_HIP(wd::launch_accum_x(x, w.x32, f, st));
   // final FP64 true residual of the returned x
   WD_TRY(true_residual());
-  WD_HIP(wd::launch_finalize_sum(w.P1, w.P2, nbb, nrhs, st));
-  std::vector<double> res2(nrhs);
-  WD_HIP(hipMemcpyAsync(res2.data(), w.P1, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-  WD_HIP(hipMemcpyAsync(hs.data(), w.sc, nrhs * sizeof(wd::CgScalars), hipMemcpyDeviceToHost, st));
+  WD_HIP(wd::launch_finalize_sum(w.P1, w.P2, nbb, wd::uniform_counts(nbb), ns, ns, st));
+  std::vector<double> res2(ns);
+  WD_HIP(hipMemcpyAsync(res2.data(), w.P1, ns * sizeof(double), hipMemcpyDeviceToHost, st));
+  WD_HIP(hipMemcpyAsync(hs.data(), w.sc, ns * sizeof(wd::CgScalars), hipMemcpyDeviceToHost, st));
   WD_HIP(hipStreamSynchronize(st));
   // b = 0: the solution is x = 0 whatever the initial guess
-  for (int k = 0; k < nrhs; ++k)
+  for (int k = 0; k < ns; ++k)
     if (!(hs[k].b2 > 0.0)) {
-      const size_t hb = half_bytes(ctx, 1, WDIRAC_F64);
-      WD_HIP(hipMemsetAsync(static_cast<char *>(x) + k * hb, 0, hb, st));
+      const size_t bytes = (size_t)f.ncomp * f.stride[k] * 16;
+      WD_HIP(hipMemsetAsync(static_cast<char *>(x) + (size_t)f.off[k] * 16, 0, bytes, st));
       res2[k] = 0.0;
     }
   WD_HIP(hipStreamSynchronize(st));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   int worst = WDIRAC_OK;
-  for (int k = 0; k < nrhs; ++k) {
+  for (int k = 0; k < ns; ++k) {
     wdirac_cg_stats &s = stats[k];
     s.iters = hs[k].iters;
     s.reliable_updates = rel[k];
@@ -686,7 +779,16 @@ int wdirac_force_eo(const wdirac_ctx *ctx, void *P, const void *x_e, const void 
   WD_TRY(hop(ctx, z_o, x_e, UR64, 1, 0, 1, 0.0, nullptr, 1.0, WDIRAC_F64, nullptr, st));
   WD_TRY(hop(ctx, y_e, z_o, UR64, 0, 0, 1, (4.0 + m0) * (4.0 + m0), x_e, -1.0, WDIRAC_F64, nullptr, st));
   WD_TRY(hop(ctx, w_o, y_e, UR64, 1, 1, 1, 0.0, nullptr, 1.0, WDIRAC_F64, nullptr, st));
-  WD_HIP(wd::launch_force_links(P, x_e, z_o, y_e, w_o, UR64, U, ctx->g, ctx->N, ctx->rep, scale, accumulate, st));
+  const size_t el = ctx->real ? 8 : 16;
+  for (int l = 0; l < ctx->nlat; ++l) {
+    const size_t so = (size_t)4 * ctx->d * ctx->spre[l] * 16;   // this lattice in the FP64 half fields
+    const size_t po = (size_t)ctx->vpre[l] * 4 * ctx->N * ctx->N * 16;
+    auto at = [so](const void *p) { return static_cast<const void *>(static_cast<const char *>(p) + so); };
+    WD_HIP(wd::launch_force_links(static_cast<char *>(P) + po, at(x_e), at(z_o), at(y_e), at(w_o),
+                                  static_cast<const char *>(UR64) + (size_t)8 * ctx->d * ctx->d * ctx->spre[l] * el,
+                                  U ? static_cast<const char *>(U) + po : nullptr, ctx->g[l], ctx->N, ctx->rep, scale,
+                                  accumulate, st));
+  }
   WD_HIP(hipStreamSynchronize(st));
   return WDIRAC_OK;
 }

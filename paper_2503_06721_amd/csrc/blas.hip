@@ -10,7 +10,16 @@ namespace wd {
 
 constexpr int BT = 256;   // threads per block of the streaming kernels
 
-int blas_nblocks(const FieldShape &f) { return (f.Vh + BT - 1) / BT; }
+int blas_nblocks(const FieldShape &f) { return (f.maxvh + BT - 1) / BT; }
+
+Counts uniform_counts(int n) {
+  Counts c;
+  for (int k = 0; k < MAXSYS; ++k) c.n[k] = n;
+  return c;
+}
+
+// Row addressing of system s: element (component c, site i) is at
+// f.off[s] + c * f.stride[s] + i.
 
 template <typename T>
 __device__ __forceinline__ cplx<T> ld(const void *p, size_t o) {
@@ -79,14 +88,18 @@ __device__ double sum_partials(const double *partial, int nblk) {
   return tot;
 }
 
-__global__ __launch_bounds__(BT) void k_finalize_sum(double *out, const double *partial, int nblk) {
+__global__ __launch_bounds__(BT) void k_finalize_sum(double *out, const double *partial, int prow, Counts cnt,
+                                                     int nsys) {
   const int r = blockIdx.x;
-  const double s = sum_partials(partial + (size_t)r * nblk, nblk);
+  const double s = sum_partials(partial + (size_t)r * prow, cnt.n[r % nsys]);
   if (threadIdx.x == 0) out[r] = s;
 }
 
-hipError_t launch_finalize_sum(double *out, const double *partial, int nblk, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize_sum, dim3(nrhs), dim3(BT), 0, st, out, partial, nblk);
+// One block per row; rows r >= nsys (the imaginary parts of dot products)
+// use the counts of system r - nsys.
+hipError_t launch_finalize_sum(double *out, const double *partial, int prow, const Counts &counts, int nrows,
+                               int nsys, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize_sum, dim3(nrows), dim3(BT), 0, st, out, partial, prow, counts, nsys);
   return hipGetLastError();
 }
 
@@ -94,11 +107,11 @@ hipError_t launch_finalize_sum(double *out, const double *partial, int nblk, int
 template <typename T>
 __global__ __launch_bounds__(BT) void k_lincomb(void *out, double a, const void *x, double b, const void *y,
                                                 FieldShape f) {
-  const int i = blockIdx.x * BT + threadIdx.x;
-  if (i >= f.Vh) return;
-  const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  const int i = blockIdx.x * BT + threadIdx.x, sy = blockIdx.y;
+  if (i >= f.vh[sy]) return;
+  const size_t base = (size_t)f.off[sy] + i;
   for (int c = 0; c < f.ncomp; ++c) {
-    const size_t o = base + (size_t)c * f.stride;
+    const size_t o = base + (size_t)c * f.stride[sy];
     cplx<double> v = up(ld<T>(x, o));
     v = a * v;
     if (y) {
@@ -112,7 +125,7 @@ __global__ __launch_bounds__(BT) void k_lincomb(void *out, double a, const void 
 
 hipError_t launch_lincomb(void *out, double a, const void *x, double b, const void *y, const FieldShape &f, int prec,
                           hipStream_t st) {
-  dim3 grid(blas_nblocks(f), f.nrhs);
+  dim3 grid(blas_nblocks(f), f.nsys);
   if (prec == 0) hipLaunchKernelGGL(k_lincomb<double>, grid, dim3(BT), 0, st, out, a, x, b, y, f);
   else hipLaunchKernelGGL(k_lincomb<float>, grid, dim3(BT), 0, st, out, a, x, b, y, f);
   return hipGetLastError();
@@ -121,12 +134,12 @@ hipError_t launch_lincomb(void *out, double a, const void *x, double b, const vo
 template <typename T>
 __global__ __launch_bounds__(BT) void k_norm2_partial(double *partial, const void *v, FieldShape f) {
   __shared__ double sh[BT / 64];
-  const int i = blockIdx.x * BT + threadIdx.x;
+  const int i = blockIdx.x * BT + threadIdx.x, sy = blockIdx.y;
   double s = 0.0;
-  if (i < f.Vh) {
-    const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  if (i < f.vh[sy]) {
+    const size_t base = (size_t)f.off[sy] + i;
     for (int c = 0; c < f.ncomp; ++c) {
-      const cplx<T> w = ld<T>(v, base + (size_t)c * f.stride);
+      const cplx<T> w = ld<T>(v, base + (size_t)c * f.stride[sy]);
       s += (double)w.re * w.re + (double)w.im * w.im;
     }
   }
@@ -135,7 +148,7 @@ __global__ __launch_bounds__(BT) void k_norm2_partial(double *partial, const voi
 }
 
 hipError_t launch_norm2_partial(double *partial, const void *v, const FieldShape &f, int prec, hipStream_t st) {
-  dim3 grid(blas_nblocks(f), f.nrhs);
+  dim3 grid(blas_nblocks(f), f.nsys);
   if (prec == 0) hipLaunchKernelGGL(k_norm2_partial<double>, grid, dim3(BT), 0, st, partial, v, f);
   else hipLaunchKernelGGL(k_norm2_partial<float>, grid, dim3(BT), 0, st, partial, v, f);
   return hipGetLastError();
@@ -144,12 +157,12 @@ hipError_t launch_norm2_partial(double *partial, const void *v, const FieldShape
 template <typename T>
 __global__ __launch_bounds__(BT) void k_dot_partial(double *partial, const void *a, const void *b, FieldShape f) {
   __shared__ double sh[BT / 64];
-  const int i = blockIdx.x * BT + threadIdx.x;
+  const int i = blockIdx.x * BT + threadIdx.x, sy = blockIdx.y;
   double re = 0.0, im = 0.0;
-  if (i < f.Vh) {
-    const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  if (i < f.vh[sy]) {
+    const size_t base = (size_t)f.off[sy] + i;
     for (int c = 0; c < f.ncomp; ++c) {
-      const size_t o = base + (size_t)c * f.stride;
+      const size_t o = base + (size_t)c * f.stride[sy];
       const cplx<double> x = up(ld<T>(a, o)), y = up(ld<T>(b, o));
       re = fma(x.re, y.re, re);
       re = fma(x.im, y.im, re);
@@ -167,7 +180,7 @@ __global__ __launch_bounds__(BT) void k_dot_partial(double *partial, const void 
 
 hipError_t launch_dot_partial(double *partial, const void *a, const void *b, const FieldShape &f, int prec,
                               hipStream_t st) {
-  dim3 grid(blas_nblocks(f), f.nrhs);
+  dim3 grid(blas_nblocks(f), f.nsys);
   if (prec == 0) hipLaunchKernelGGL(k_dot_partial<double>, grid, dim3(BT), 0, st, partial, a, b, f);
   else hipLaunchKernelGGL(k_dot_partial<float>, grid, dim3(BT), 0, st, partial, a, b, f);
   return hipGetLastError();
@@ -175,18 +188,18 @@ hipError_t launch_dot_partial(double *partial, const void *a, const void *b, con
 
 template <typename TO, typename TI>
 __global__ __launch_bounds__(BT) void k_convert(void *out, const void *in, FieldShape f) {
-  const int i = blockIdx.x * BT + threadIdx.x;
-  if (i >= f.Vh) return;
-  const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  const int i = blockIdx.x * BT + threadIdx.x, sy = blockIdx.y;
+  if (i >= f.vh[sy]) return;
+  const size_t base = (size_t)f.off[sy] + i;
   for (int c = 0; c < f.ncomp; ++c) {
-    const size_t o = base + (size_t)c * f.stride;
+    const size_t o = base + (size_t)c * f.stride[sy];
     st<TO>(out, o, up(ld<TI>(in, o)));
   }
 }
 
 hipError_t launch_convert(void *out, int prec_out, const void *in, int prec_in, const FieldShape &f,
                           hipStream_t st) {
-  dim3 grid(blas_nblocks(f), f.nrhs);
+  dim3 grid(blas_nblocks(f), f.nsys);
   if (prec_out == 0 && prec_in == 1) hipLaunchKernelGGL((k_convert<double, float>), grid, dim3(BT), 0, st, out, in, f);
   else if (prec_out == 1 && prec_in == 0) hipLaunchKernelGGL((k_convert<float, double>), grid, dim3(BT), 0, st, out, in, f);
   else if (prec_out == 0) hipLaunchKernelGGL((k_convert<double, double>), grid, dim3(BT), 0, st, out, in, f);
@@ -195,11 +208,11 @@ hipError_t launch_convert(void *out, int prec_out, const void *in, int prec_in, 
 }
 
 // ------------------------------------------------------------------- CG
-__global__ __launch_bounds__(BT) void k_cg_alpha(CgScalars *S, const double *partial, int nblk) {
+__global__ __launch_bounds__(BT) void k_cg_alpha(CgScalars *S, const double *partial, int prow, Counts cnt) {
   const int r = blockIdx.x;
   CgScalars &s = S[r];
   if (!s.active) return;
-  const double pAp = sum_partials(partial + (size_t)r * nblk, nblk);
+  const double pAp = sum_partials(partial + (size_t)r * prow, cnt.n[r]);
   if (threadIdx.x == 0) {
     s.pAp = pAp;
     if (!(pAp > 0.0) || !isfinite(pAp) || !isfinite(s.rho)) {
@@ -212,8 +225,9 @@ __global__ __launch_bounds__(BT) void k_cg_alpha(CgScalars *S, const double *par
   }
 }
 
-hipError_t launch_cg_alpha(CgScalars *s, const double *pAp_partial, int nblk, int nrhs, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_alpha, dim3(nrhs), dim3(BT), 0, st, s, pAp_partial, nblk);
+hipError_t launch_cg_alpha(CgScalars *s, const double *pAp_partial, int prow, const Counts &counts, int nsys,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_alpha, dim3(nsys), dim3(BT), 0, st, s, pAp_partial, prow, counts);
   return hipGetLastError();
 }
 
@@ -224,12 +238,12 @@ __global__ __launch_bounds__(BT) void k_cg_update_xr(void *x, void *r, const voi
   const CgScalars &s = S[blockIdx.y];
   if (!s.active) return;
   const double a = s.alpha;
-  const int i = blockIdx.x * BT + threadIdx.x;
+  const int i = blockIdx.x * BT + threadIdx.x, sy = blockIdx.y;
   double nrm = 0.0;
-  if (i < f.Vh) {
-    const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  if (i < f.vh[sy]) {
+    const size_t base = (size_t)f.off[sy] + i;
     for (int c = 0; c < f.ncomp; ++c) {
-      const size_t o = base + (size_t)c * f.stride;
+      const size_t o = base + (size_t)c * f.stride[sy];
       const cplx<double> pv = up(ld<T>(p, o)), qv = up(ld<T>(q, o));
       cplx<double> xv = up(ld<TX>(x, o)), rv = up(ld<T>(r, o));
       xv.re = fma(a, pv.re, xv.re);
@@ -248,7 +262,7 @@ __global__ __launch_bounds__(BT) void k_cg_update_xr(void *x, void *r, const voi
 
 hipError_t launch_cg_update_xr(void *x, int prec_x, void *r, const void *p, const void *q, const CgScalars *s,
                                double *partial, const FieldShape &f, int prec, hipStream_t st) {
-  dim3 grid(blas_nblocks(f), f.nrhs);
+  dim3 grid(blas_nblocks(f), f.nsys);
   if (prec == 0 && prec_x == 0)
     hipLaunchKernelGGL((k_cg_update_xr<double, double>), grid, dim3(BT), 0, st, x, r, p, q, s, partial, f);
   else if (prec == 1 && prec_x == 1)
@@ -305,11 +319,11 @@ __global__ __launch_bounds__(BT) void k_cg_update_p(void *p, const void *r, cons
   const CgScalars &s = S[blockIdx.y];
   if (!s.do_p) return;
   const double b = s.beta;
-  const int i = blockIdx.x * BT + threadIdx.x;
-  if (i >= f.Vh) return;
-  const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  const int i = blockIdx.x * BT + threadIdx.x, sy = blockIdx.y;
+  if (i >= f.vh[sy]) return;
+  const size_t base = (size_t)f.off[sy] + i;
   for (int c = 0; c < f.ncomp; ++c) {
-    const size_t o = base + (size_t)c * f.stride;
+    const size_t o = base + (size_t)c * f.stride[sy];
     const cplx<double> rv = up(ld<T>(r, o));
     cplx<double> pv = up(ld<T>(p, o));
     pv.re = fma(b, pv.re, rv.re);
@@ -320,7 +334,7 @@ __global__ __launch_bounds__(BT) void k_cg_update_p(void *p, const void *r, cons
 
 hipError_t launch_cg_update_p(void *p, const void *r, const CgScalars *s, const FieldShape &f, int prec,
                               hipStream_t st) {
-  dim3 grid(blas_nblocks(f), f.nrhs);
+  dim3 grid(blas_nblocks(f), f.nsys);
   if (prec == 0) hipLaunchKernelGGL(k_cg_update_p<double>, grid, dim3(BT), 0, st, p, r, s, f);
   else hipLaunchKernelGGL(k_cg_update_p<float>, grid, dim3(BT), 0, st, p, r, s, f);
   return hipGetLastError();
@@ -329,12 +343,12 @@ hipError_t launch_cg_update_p(void *p, const void *r, const CgScalars *s, const 
 __global__ __launch_bounds__(BT) void k_residual(void *r, const void *b, const void *q, double *partial,
                                                  FieldShape f) {
   __shared__ double sh[BT / 64];
-  const int i = blockIdx.x * BT + threadIdx.x;
+  const int i = blockIdx.x * BT + threadIdx.x, sy = blockIdx.y;
   double nrm = 0.0;
-  if (i < f.Vh) {
-    const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  if (i < f.vh[sy]) {
+    const size_t base = (size_t)f.off[sy] + i;
     for (int c = 0; c < f.ncomp; ++c) {
-      const size_t o = base + (size_t)c * f.stride;
+      const size_t o = base + (size_t)c * f.stride[sy];
       const cplx<double> v = ld<double>(b, o) - ld<double>(q, o);
       st<double>(r, o, v);
       nrm += v.re * v.re + v.im * v.im;
@@ -346,7 +360,7 @@ __global__ __launch_bounds__(BT) void k_residual(void *r, const void *b, const v
 
 hipError_t launch_residual(void *r, const void *b, const void *q, double *partial, const FieldShape &f,
                            hipStream_t st) {
-  dim3 grid(blas_nblocks(f), f.nrhs);
+  dim3 grid(blas_nblocks(f), f.nsys);
   hipLaunchKernelGGL(k_residual, grid, dim3(BT), 0, st, r, b, q, partial, f);
   return hipGetLastError();
 }
@@ -398,11 +412,11 @@ hipError_t launch_cg_restart(CgScalars *s, const double *partial, int nblk, int 
 
 // x64 += x32 and x32 = 0 (mixed-mode accumulation of the inner solution).
 __global__ __launch_bounds__(BT) void k_accum_x(void *x64, void *x32, FieldShape f) {
-  const int i = blockIdx.x * BT + threadIdx.x;
-  if (i >= f.Vh) return;
-  const size_t base = (size_t)blockIdx.y * f.ncomp * f.stride + i;
+  const int i = blockIdx.x * BT + threadIdx.x, sy = blockIdx.y;
+  if (i >= f.vh[sy]) return;
+  const size_t base = (size_t)f.off[sy] + i;
   for (int c = 0; c < f.ncomp; ++c) {
-    const size_t o = base + (size_t)c * f.stride;
+    const size_t o = base + (size_t)c * f.stride[sy];
     const cplx<double> v = ld<double>(x64, o) + up(ld<float>(x32, o));
     st<double>(x64, o, v);
     st<float>(x32, o, mk(0.0, 0.0));
@@ -410,7 +424,7 @@ __global__ __launch_bounds__(BT) void k_accum_x(void *x64, void *x32, FieldShape
 }
 
 hipError_t launch_accum_x(void *x64, void *x32, const FieldShape &f, hipStream_t st) {
-  dim3 grid(blas_nblocks(f), f.nrhs);
+  dim3 grid(blas_nblocks(f), f.nsys);
   hipLaunchKernelGGL(k_accum_x, grid, dim3(BT), 0, st, x64, x32, f);
   return hipGetLastError();
 }

@@ -33,6 +33,32 @@ __device__ __forceinline__ int tile_of_block(int b, int ntiles, int remap) {
   return x * q + (x < rmd ? x : rmd) + j;
 }
 
+// Processing order of tiles.  With tb > 0 the tiles (each tiles_per_tx
+// tiles cover one (t, x) row of Y*Z lexicographic sites) are visited in the
+// order (t-block of tb slices, x, t within the block, tile within the row):
+// t-neighbours are then tiles_per_tx tiles apart instead of a whole t-slice,
+// so they are still in L2 when read.  tb = 0: lexicographic order.
+__device__ __forceinline__ int tile_order(int q, const HopArgs &a) {
+  if (a.tblock == 0) return q;
+  const int nb = a.tiles_per_tx, tb = a.tblock, X = a.lat[0].g.X;
+  const int per_tb = X * tb * nb;
+  const int tbi = q / per_tb;
+  int r = q - tbi * per_tb;
+  const int x = r / (tb * nb);
+  r -= x * tb * nb;
+  const int tin = r / nb;
+  const int yb = r - tin * nb;
+  return ((tbi * tb + tin) * X + x) * nb + yb;
+}
+
+// Lattice of a global tile index (the launch covers the tiles of every
+// lattice of a batch back to back).
+__device__ __forceinline__ int lattice_of_tile(const HopArgs &a, int tile) {
+  int l = 0;
+  while (l + 1 < a.nlat && tile >= a.lat[l + 1].tile0) ++l;
+  return l;
+}
+
 template <typename T, bool REAL>
 struct LinkT {
   using type = cplx<T>;
@@ -83,54 +109,59 @@ __device__ __forceinline__ void sp_dir(cplx<T> (&acc)[4][D], const cplx<T> *__re
 }
 
 template <int D, bool REAL, typename T, bool DAG, int MU>
-__device__ __forceinline__ void sp_mu(cplx<T> (&acc)[4][D], const HopArgs &a, const cplx<T> *in, int i, int t,
+__device__ __forceinline__ void sp_mu(cplx<T> (&acc)[4][D], const Geom &g, int parity,
+                                      const typename LinkT<T, REAL>::type *links, const cplx<T> *in, int i, int t,
                                       int x, int y, int z) {
-  using L = typename LinkT<T, REAL>::type;
-  const L *links = static_cast<const L *>(a.links);
-  const size_t lstride = (size_t)D * D * a.g.stride;
+  const size_t lstride = (size_t)D * D * g.stride;
   constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
-  const int nbf = nb_index(a.g, t, x, y, z, MU, 1);
-  sp_dir<D, REAL, T, MU, SF, false>(acc, in, a.g.stride, nbf, links + (size_t)(a.parity * 4 + MU) * lstride, i);
-  const int nbb = nb_index(a.g, t, x, y, z, MU, 0);
-  sp_dir<D, REAL, T, MU, -SF, true>(acc, in, a.g.stride, nbb, links + (size_t)((1 - a.parity) * 4 + MU) * lstride,
+  const int nbf = nb_index(g, t, x, y, z, MU, 1);
+  sp_dir<D, REAL, T, MU, SF, false>(acc, in, g.stride, nbf, links + (size_t)(parity * 4 + MU) * lstride, i);
+  const int nbb = nb_index(g, t, x, y, z, MU, 0);
+  sp_dir<D, REAL, T, MU, -SF, true>(acc, in, g.stride, nbb, links + (size_t)((1 - parity) * 4 + MU) * lstride,
                                     nbb);
 }
 
 template <int D, bool REAL, typename T, bool DAG, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_hop_sp(HopArgs a) {
-  const int ntiles = gridDim.x;
-  const int tile = tile_of_block(blockIdx.x, ntiles, a.xcd_remap);
-  const int i = tile * 256 + threadIdx.x;
+  using L = typename LinkT<T, REAL>::type;
+  const int tile = tile_order(tile_of_block(blockIdx.x, a.ntiles, a.xcd_remap), a);
+  const int l = lattice_of_tile(a, tile);
+  const Geom g = a.lat[l].g;
+  const int tl = tile - a.lat[l].tile0;   // tile within its lattice
+  const int i = tl * 256 + threadIdx.x;
   const int r = blockIdx.y;
-  const size_t rstride = (size_t)4 * D * a.g.stride;
+  const int sys = l * gridDim.y + r;
+  const size_t rstride = (size_t)4 * D * g.stride;
+  const size_t fbase = (size_t)a.lat[l].soff + r * rstride;
+  const L *links = static_cast<const L *>(a.links) + a.lat[l].loff;
   // Lanes past the last site recompute the last site and store into the row
   // padding (stride is a multiple of 256), so that no branch separates the
   // arithmetic from its stores.
-  const bool valid = i < a.g.Vh;
-  const int is = valid ? i : a.g.Vh - 1;
-  const cplx<T> *in = static_cast<const cplx<T> *>(a.in) + r * rstride;
+  const bool valid = i < g.Vh;
+  const int is = valid ? i : g.Vh - 1;
+  const cplx<T> *in = static_cast<const cplx<T> *>(a.in) + fbase;
   int t, x, y, z;
-  cb_coords(a.g, is, a.parity, t, x, y, z);
+  cb_coords(g, is, a.parity, t, x, y, z);
   cplx<T> acc[4][D];
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[s][c] = mk<T>(0, 0);
-  sp_mu<D, REAL, T, DAG, 0>(acc, a, in, is, t, x, y, z);
-  sp_mu<D, REAL, T, DAG, 1>(acc, a, in, is, t, x, y, z);
-  sp_mu<D, REAL, T, DAG, 2>(acc, a, in, is, t, x, y, z);
-  sp_mu<D, REAL, T, DAG, 3>(acc, a, in, is, t, x, y, z);
-  cplx<T> *out = static_cast<cplx<T> *>(a.out) + r * rstride;
+  sp_mu<D, REAL, T, DAG, 0>(acc, g, a.parity, links, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 1>(acc, g, a.parity, links, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 2>(acc, g, a.parity, links, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 3>(acc, g, a.parity, links, in, is, t, x, y, z);
+  cplx<T> *out = static_cast<cplx<T> *>(a.out) + fbase;
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
   double nrm = 0.0;
   // two straight-line epilogues: every accumulator is used on both paths
   if (a.xadd) {
-    const cplx<T> *xa = static_cast<const cplx<T> *>(a.xadd) + r * rstride;
+    const cplx<T> *xa = static_cast<const cplx<T> *>(a.xadd) + fbase;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const size_t o = (size_t)(s * D + c) * a.g.stride + i;
+        const size_t o = (size_t)(s * D + c) * g.stride + i;
         cplx<T> v = cb * acc[s][c];
         const cplx<T> xv = xa[o];
         v.re = fma(ca, xv.re, v.re);
@@ -143,7 +174,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < D; ++c) {
-        const size_t o = (size_t)(s * D + c) * a.g.stride + i;
+        const size_t o = (size_t)(s * D + c) * g.stride + i;
         const cplx<T> v = cb * acc[s][c];
         out[o] = v;
         nrm += (double)v.re * v.re + (double)v.im * v.im;
@@ -152,7 +183,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
   if (a.partial) {
     __shared__ double sh[4];
     const double s = block_sum(valid ? nrm : 0.0, sh);
-    if (threadIdx.x == 0) a.partial[(size_t)r * ntiles + tile] = s;
+    if (threadIdx.x == 0) a.partial[(size_t)sys * a.prow + tl] = s;
   }
 }
 
@@ -162,12 +193,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
 // colour component `row` of the neighbour spinor, spin-projected into LDS.
 template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, int NR>
 __device__ __forceinline__ void cs_stage(typename LinkT<T, REAL>::type (&u)[D], cplx<T> (*hs)[2][D][64],
-                                         const HopArgs &a, const cplx<T> *in0, size_t rstride, int nb, int lsite,
-                                         int row, int lane) {
+                                         const Geom &g, int parity, const typename LinkT<T, REAL>::type *links,
+                                         const cplx<T> *in0, size_t rstride, int nb, int lsite, int row, int lane) {
   using L = typename LinkT<T, REAL>::type;
-  const int stride = a.g.stride;
-  const int lpar = BWD ? 1 - a.parity : a.parity;
-  const L *lk = static_cast<const L *>(a.links) + (size_t)(lpar * 4 + MU) * D * D * stride;
+  const int stride = g.stride;
+  const int lpar = BWD ? 1 - parity : parity;
+  const L *lk = links + (size_t)(lpar * 4 + MU) * D * D * stride;
 #pragma unroll
   for (int b = 0; b < D; ++b) u[b] = lk[(size_t)(BWD ? b * D + row : row * D + b) * stride + lsite];
 #pragma unroll
@@ -208,25 +239,25 @@ __device__ __forceinline__ void cs_compute(cplx<T> (&acc)[NR][4], const typename
 // barrier (LDS buffers 2*(MU&1) and 2*(MU&1)+1), which halves the barriers and
 // doubles the loads in flight per phase at the cost of twice the LDS.
 template <int D, bool REAL, typename T, int MU, int SF, int NR, bool PAIR, int NB>
-__device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64], const HopArgs &a,
-                                      const cplx<T> *in0, size_t rstride, int t, int x, int y, int z, int is,
-                                      int row, int lane) {
+__device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64], const Geom &g, int parity,
+                                      const typename LinkT<T, REAL>::type *links, const cplx<T> *in0, size_t rstride,
+                                      int t, int x, int y, int z, int is, int row, int lane) {
   using L = typename LinkT<T, REAL>::type;
-  const int nbf = nb_index(a.g, t, x, y, z, MU, 1);
-  const int nbb = nb_index(a.g, t, x, y, z, MU, 0);
+  const int nbf = nb_index(g, t, x, y, z, MU, 1);
+  const int nbb = nb_index(g, t, x, y, z, MU, 0);
   L uf[D], ub[D];
   if constexpr (PAIR) {
     constexpr int B0 = 2 * (MU & 1);
-    cs_stage<D, REAL, T, MU, SF, false, NR>(uf, hs[B0], a, in0, rstride, nbf, is, row, lane);
-    cs_stage<D, REAL, T, MU, -SF, true, NR>(ub, hs[B0 + 1], a, in0, rstride, nbb, nbb, row, lane);
+    cs_stage<D, REAL, T, MU, SF, false, NR>(uf, hs[B0], g, parity, links, in0, rstride, nbf, is, row, lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR>(ub, hs[B0 + 1], g, parity, links, in0, rstride, nbb, nbb, row, lane);
     __syncthreads();
     cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[B0], lane);
     cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[B0 + 1], lane);
   } else {
-    cs_stage<D, REAL, T, MU, SF, false, NR>(uf, hs[0], a, in0, rstride, nbf, is, row, lane);
+    cs_stage<D, REAL, T, MU, SF, false, NR>(uf, hs[0], g, parity, links, in0, rstride, nbf, is, row, lane);
     __syncthreads();
     cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[0], lane);
-    cs_stage<D, REAL, T, MU, -SF, true, NR>(ub, hs[1], a, in0, rstride, nbb, nbb, row, lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR>(ub, hs[1], g, parity, links, in0, rstride, nbb, nbb, row, lane);
     __syncthreads();
     cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[1], lane);
   }
@@ -241,28 +272,36 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
   // groups of one tile are consecutive and (after the XCD remap) run on the
   // same XCD at nearly the same time: each link entry comes from HBM once
   // and from that XCD's L2 for the other groups.
-  const int ngroups = a.ngroups, ntiles = a.ntiles;
-  const int w = tile_of_block(blockIdx.x, ntiles * ngroups, a.xcd_remap);
-  const int tile = w / ngroups, grp = w - tile * ngroups;
+  using L = typename LinkT<T, REAL>::type;
+  const int ngroups = a.ngroups;
+  const int w = tile_of_block(blockIdx.x, a.ntiles * ngroups, a.xcd_remap);
+  const int q = w / ngroups, grp = w - q * ngroups;
+  const int tile = tile_order(q, a);
+  const int l = lattice_of_tile(a, tile);
+  const Geom g = a.lat[l].g;
+  const int tl = tile - a.lat[l].tile0;   // tile within its lattice
   const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
-  const int i = tile * 64 + lane;
-  const bool valid = i < a.g.Vh;
-  const int is = valid ? i : a.g.Vh - 1;   // lanes past the end: see k_hop_sp
+  const int i = tl * 64 + lane;
+  const bool valid = i < g.Vh;
+  const int is = valid ? i : g.Vh - 1;   // lanes past the end: see k_hop_sp
   const int r0 = grp * NR;
-  const size_t rstride = (size_t)4 * D * a.g.stride;
-  const cplx<T> *in0 = static_cast<const cplx<T> *>(a.in) + r0 * rstride;
+  const int sys0 = l * ngroups * NR + r0;
+  const size_t rstride = (size_t)4 * D * g.stride;
+  const size_t fbase = (size_t)a.lat[l].soff + r0 * rstride;
+  const cplx<T> *in0 = static_cast<const cplx<T> *>(a.in) + fbase;
+  const L *links = static_cast<const L *>(a.links) + a.lat[l].loff;
   int t, x, y, z;
-  cb_coords(a.g, is, a.parity, t, x, y, z);
+  cb_coords(g, is, a.parity, t, x, y, z);
   cplx<T> acc[NR][4];
 #pragma unroll
   for (int k = 0; k < NR; ++k)
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[k][s] = mk<T>(0, 0);
   constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
-  cs_mu<D, REAL, T, 0, SF, NR, PAIR, NB>(acc, hs, a, in0, rstride, t, x, y, z, is, row, lane);
-  cs_mu<D, REAL, T, 1, SF, NR, PAIR, NB>(acc, hs, a, in0, rstride, t, x, y, z, is, row, lane);
-  cs_mu<D, REAL, T, 2, SF, NR, PAIR, NB>(acc, hs, a, in0, rstride, t, x, y, z, is, row, lane);
-  cs_mu<D, REAL, T, 3, SF, NR, PAIR, NB>(acc, hs, a, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 0, SF, NR, PAIR, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 1, SF, NR, PAIR, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 2, SF, NR, PAIR, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 3, SF, NR, PAIR, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
   // Two straight-line epilogues (with and without x_add): every accumulator
   // is used on both paths, so no arithmetic is sunk behind a branch.
@@ -271,11 +310,11 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       nrm[k] = 0.0;
-      cplx<T> *out = static_cast<cplx<T> *>(a.out) + (r0 + k) * rstride;
-      const cplx<T> *xa = static_cast<const cplx<T> *>(a.xadd) + (r0 + k) * rstride;
+      cplx<T> *out = static_cast<cplx<T> *>(a.out) + fbase + k * rstride;
+      const cplx<T> *xa = static_cast<const cplx<T> *>(a.xadd) + fbase + k * rstride;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const size_t o = (size_t)(s * D + row) * a.g.stride + i;   // i < stride always
+        const size_t o = (size_t)(s * D + row) * g.stride + i;   // i < stride always
         cplx<T> v = cb * acc[k][s];
         const cplx<T> xv = xa[o];
         v.re = fma(ca, xv.re, v.re);
@@ -288,10 +327,10 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       nrm[k] = 0.0;
-      cplx<T> *out = static_cast<cplx<T> *>(a.out) + (r0 + k) * rstride;
+      cplx<T> *out = static_cast<cplx<T> *>(a.out) + fbase + k * rstride;
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const size_t o = (size_t)(s * D + row) * a.g.stride + i;
+        const size_t o = (size_t)(s * D + row) * g.stride + i;
         const cplx<T> v = cb * acc[k][s];
         out[o] = v;
         nrm[k] += (double)v.re * v.re + (double)v.im * v.im;
@@ -302,7 +341,7 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
 #pragma unroll
     for (int k = 0; k < NR; ++k) {
       const double s = block_sum(valid ? nrm[k] : 0.0, sh);
-      if (threadIdx.x == 0) a.partial[(size_t)(r0 + k) * ntiles + tile] = s;
+      if (threadIdx.x == 0) a.partial[(size_t)(sys0 + k) * a.prow + tl] = s;
     }
   }
 }
@@ -321,11 +360,38 @@ constexpr bool cs_fits() {
   return (PAIR ? 4 : 2) * NR * 2 * D * 64 * (int)sizeof(cplx<T>) <= 65536;
 }
 
+// Tile bookkeeping of a launch with tiles of ts sites: per-lattice tile
+// ranges, the partial-sum row length and counts, and the t-blocked order
+// (single lattices only: tiles_per_tx is the number of tiles covering one
+// (t, x) row of Y*Z sites; the order falls back to lexicographic if tiles
+// straddle rows or tb does not divide T).
+static void set_tiles(HopArgs &a, int ts, int nrhs, Counts *counts, int *prow) {
+  int tot = 0, mx = 0;
+  for (int l = 0; l < a.nlat; ++l) {
+    const int n = (a.lat[l].g.Vh + ts - 1) / ts;
+    a.lat[l].tile0 = tot;
+    a.lat[l].ntiles = n;
+    tot += n;
+    mx = n > mx ? n : mx;
+    for (int r = 0; r < nrhs && l * nrhs + r < MAXSYS; ++r) counts->n[l * nrhs + r] = n;
+  }
+  a.ntiles = tot;
+  a.prow = mx;
+  *prow = mx;
+  const Geom &g = a.lat[0].g;
+  const int lex_per_tile = 2 * ts, rowl = g.Y * g.Z;
+  if (a.nlat == 1 && a.tblock > 0 && rowl % lex_per_tile == 0 && g.T % a.tblock == 0) {
+    a.tiles_per_tx = rowl / lex_per_tile;
+  } else {
+    a.tblock = 0;
+    a.tiles_per_tx = 0;
+  }
+}
+
 template <int D, bool REAL, typename T, bool DAG, int NR>
-static hipError_t launch_cs(HopArgs a, int nrhs, int pair, hipStream_t st, int *nblk) {
-  a.ntiles = (a.g.Vh + 63) / 64;
+static hipError_t launch_cs(HopArgs a, int nrhs, int pair, hipStream_t st, Counts *counts, int *prow) {
+  set_tiles(a, 64, nrhs, counts, prow);
   a.ngroups = nrhs / NR;
-  *nblk = a.ntiles;
   dim3 grid(a.ntiles * a.ngroups);
   if constexpr (cs_fits<D, T, NR, true>()) {
     if (pair) {
@@ -340,12 +406,14 @@ static hipError_t launch_cs(HopArgs a, int nrhs, int pair, hipStream_t st, int *
 }
 
 template <int D, bool REAL, typename T, bool DAG>
-static hipError_t launch_typed(const HopArgs &a, int nrhs, int variant, int nr, hipStream_t st, int *nblk) {
+static hipError_t launch_typed(const HopArgs &a0, int nrhs, int variant, int nr, hipStream_t st, Counts *counts,
+                               int *prow) {
   const int pair = variant == HOP_COLOUR_PAIR;
   if (variant == HOP_SITE) {
     if constexpr (D <= 6) {
-      dim3 grid((a.g.Vh + 255) / 256, nrhs);
-      *nblk = grid.x;
+      HopArgs a = a0;
+      set_tiles(a, 256, nrhs, counts, prow);
+      dim3 grid(a.ntiles, nrhs);
       hipLaunchKernelGGL((k_hop_sp<D, REAL, T, DAG, sp_waves(D, sizeof(T) == 8)>), grid, dim3(256), 0, st, a);
       return hipGetLastError();
     } else {
@@ -353,42 +421,42 @@ static hipError_t launch_typed(const HopArgs &a, int nrhs, int variant, int nr, 
     }
   }
   if (nr == 4 && nrhs % 4 == 0) {
-    if constexpr (cs_fits<D, T, 4, false>()) return launch_cs<D, REAL, T, DAG, 4>(a, nrhs, pair, st, nblk);
+    if constexpr (cs_fits<D, T, 4, false>()) return launch_cs<D, REAL, T, DAG, 4>(a0, nrhs, pair, st, counts, prow);
   }
   if (nr == 3 && nrhs % 3 == 0) {
-    if constexpr (cs_fits<D, T, 3, false>()) return launch_cs<D, REAL, T, DAG, 3>(a, nrhs, pair, st, nblk);
+    if constexpr (cs_fits<D, T, 3, false>()) return launch_cs<D, REAL, T, DAG, 3>(a0, nrhs, pair, st, counts, prow);
   }
   if (nr == 2 && nrhs % 2 == 0) {
-    if constexpr (cs_fits<D, T, 2, false>()) return launch_cs<D, REAL, T, DAG, 2>(a, nrhs, pair, st, nblk);
+    if constexpr (cs_fits<D, T, 2, false>()) return launch_cs<D, REAL, T, DAG, 2>(a0, nrhs, pair, st, counts, prow);
   }
-  return launch_cs<D, REAL, T, DAG, 1>(a, nrhs, pair, st, nblk);
+  return launch_cs<D, REAL, T, DAG, 1>(a0, nrhs, pair, st, counts, prow);
 }
 
 template <int D, bool REAL>
 static hipError_t launch_d(const HopArgs &a, int prec, int dagger, int nrhs, int variant, int nr, hipStream_t st,
-                           int *nblk) {
+                           Counts *c, int *prow) {
   if (prec == 0)
-    return dagger ? launch_typed<D, REAL, double, true>(a, nrhs, variant, nr, st, nblk)
-                  : launch_typed<D, REAL, double, false>(a, nrhs, variant, nr, st, nblk);
-  return dagger ? launch_typed<D, REAL, float, true>(a, nrhs, variant, nr, st, nblk)
-                : launch_typed<D, REAL, float, false>(a, nrhs, variant, nr, st, nblk);
+    return dagger ? launch_typed<D, REAL, double, true>(a, nrhs, variant, nr, st, c, prow)
+                  : launch_typed<D, REAL, double, false>(a, nrhs, variant, nr, st, c, prow);
+  return dagger ? launch_typed<D, REAL, float, true>(a, nrhs, variant, nr, st, c, prow)
+                : launch_typed<D, REAL, float, false>(a, nrhs, variant, nr, st, c, prow);
 }
 
 hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant, int nr,
-                      hipStream_t st, int *nblk) {
+                      hipStream_t st, Counts *counts, int *prow) {
   if (real) {
     switch (d) {
-      case 3: return launch_d<3, true>(a, prec, dagger, nrhs, variant, nr, st, nblk);
-      case 8: return launch_d<8, true>(a, prec, dagger, nrhs, variant, nr, st, nblk);
-      case 15: return launch_d<15, true>(a, prec, dagger, nrhs, variant, nr, st, nblk);
+      case 3: return launch_d<3, true>(a, prec, dagger, nrhs, variant, nr, st, counts, prow);
+      case 8: return launch_d<8, true>(a, prec, dagger, nrhs, variant, nr, st, counts, prow);
+      case 15: return launch_d<15, true>(a, prec, dagger, nrhs, variant, nr, st, counts, prow);
     }
   } else {
     switch (d) {
-      case 2: return launch_d<2, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
-      case 3: return launch_d<3, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
-      case 4: return launch_d<4, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
-      case 6: return launch_d<6, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
-      case 10: return launch_d<10, false>(a, prec, dagger, nrhs, variant, nr, st, nblk);
+      case 2: return launch_d<2, false>(a, prec, dagger, nrhs, variant, nr, st, counts, prow);
+      case 3: return launch_d<3, false>(a, prec, dagger, nrhs, variant, nr, st, counts, prow);
+      case 4: return launch_d<4, false>(a, prec, dagger, nrhs, variant, nr, st, counts, prow);
+      case 6: return launch_d<6, false>(a, prec, dagger, nrhs, variant, nr, st, counts, prow);
+      case 10: return launch_d<10, false>(a, prec, dagger, nrhs, variant, nr, st, counts, prow);
     }
   }
   return hipErrorInvalidValue;
@@ -402,10 +470,7 @@ int hop_max_nr(int d, int prec, int variant) {
   return nr;
 }
 
-int hop_nblocks(int Vh, int d, int variant) {
-  (void)d;
-  return variant == HOP_SITE ? (Vh + 255) / 256 : (Vh + 63) / 64;
-}
+int hop_tile_sites(int variant) { return variant == HOP_SITE ? 256 : 64; }
 
 bool hop_variant_ok(int d, int variant) {
   if (variant == HOP_SITE) return d <= 6;

@@ -27,7 +27,7 @@ CG_F64, CG_MIXED = 0, 1
 FIELD_HALF_SPINOR, FIELD_LINKS = 0, 1
 OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE = 0, 1, 2, 3, 4, 5
 (OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
- OPT_HOP_NR_F32) = 0, 1, 2, 3, 4, 5, 6
+ OPT_HOP_NR_F32, OPT_TILE_TBLOCK) = 0, 1, 2, 3, 4, 5, 6, 7
 HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR = 0, 1, 2
 REP_CODES = {'FUND': FUND, 'ADJ': ADJ, 'SYM': SYM, '2AS': ASYM}
 STATUS_NAMES = {OK: 'OK', EINVAL: 'EINVAL', EUNSUPPORTED: 'EUNSUPPORTED', EHIP: 'EHIP',
@@ -40,7 +40,7 @@ class Geom(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [('variant', ctypes.c_int32), ('nr', ctypes.c_int32), ('xcd_remap', ctypes.c_int32),
-                ('candidates', ctypes.c_int32), ('us', ctypes.c_double)]
+                ('tblock', ctypes.c_int32), ('candidates', ctypes.c_int32), ('us', ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -59,6 +59,7 @@ _I = ctypes.c_int
 _D = ctypes.c_double
 _SIGS = {
     'wdirac_create': (_I, [ctypes.POINTER(_P), _I, _I, ctypes.POINTER(Geom)]),
+    'wdirac_create_batch': (_I, [ctypes.POINTER(_P), _I, _I, ctypes.POINTER(Geom), _I]),
     'wdirac_destroy': (_I, [_P]),
     'wdirac_set_option': (_I, [_P, _I, _D]),
     'wdirac_rep_info': (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
@@ -124,23 +125,36 @@ def _stream(stream):
 class Lattice:
     """A libwdirac context: SU(N) fermions in representation `rep` on `dims`.
 
-    dims = (T, X, Y, Z), bc = per-direction fermion boundary phase (+1/-1)."""
+    dims = (T, X, Y, Z), bc = per-direction fermion boundary phase (+1/-1).
+    A list of shapes, dims = [(T, X, Y, Z), ...], makes a batch of lattices
+    processed together (one right-hand side each; canonical batch tensors are
+    the per-lattice arrays flattened and concatenated)."""
 
     def __init__(self, N, rep, dims, bc=(-1, 1, 1, 1)):
         self.N = int(N)
         self.rep_name = rep if isinstance(rep, str) else {v: k for k, v in REP_CODES.items()}[rep]
         self.rep = REP_CODES[self.rep_name] if isinstance(rep, str) else int(rep)
-        self.dims = tuple(int(x) for x in dims)
+        self.batch = isinstance(dims[0], (tuple, list))
+        shapes = [tuple(int(x) for x in dd) for dd in dims] if self.batch else [tuple(int(x) for x in dims)]
+        self.shapes = shapes
         self.bc = tuple(int(x) for x in bc)
-        g = Geom((ctypes.c_int32 * 4)(*self.dims), (ctypes.c_int32 * 4)(*self.bc))
+        geoms = (Geom * len(shapes))(*[Geom((ctypes.c_int32 * 4)(*dd), (ctypes.c_int32 * 4)(*self.bc))
+                                         for dd in shapes])
         h = _P()
-        _check(_lib.wdirac_create(ctypes.byref(h), self.N, self.rep, ctypes.byref(g)), 'create')
+        _check(_lib.wdirac_create_batch(ctypes.byref(h), self.N, self.rep, geoms, len(shapes)), 'create')
         self._h = h
         d, real = _I(), _I()
         _check(_lib.wdirac_rep_info(h, ctypes.byref(d), ctypes.byref(real)), 'rep_info')
         self.d, self.real = d.value, bool(real.value)
-        self.V = self.dims[0] * self.dims[1] * self.dims[2] * self.dims[3]
+        self.dims = shapes[0] if not self.batch else None
+        self.volumes = [dd[0] * dd[1] * dd[2] * dd[3] for dd in shapes]
+        self.V = sum(self.volumes)
         self.Vh = self.V // 2
+        self.nlat = len(shapes)
+
+    def nsys(self, nrhs=1):
+        """Independent systems of a call: the right-hand sides, or the lattices of a batch."""
+        return self.nlat if self.batch else int(nrhs)
 
     def __del__(self):
         h = getattr(self, '_h', None)
@@ -221,22 +235,23 @@ class Lattice:
 
     def norm2(self, v, nrhs=1, prec=F64, workspace=None, stream=None):
         ws = workspace if workspace is not None else self.new_workspace(OP_NORM, nrhs, prec)
-        out = (_D * nrhs)()
+        out = (_D * self.nsys(nrhs))()
         _check(_lib.wdirac_norm2(self._h, out, _ptr(v), nrhs, prec, _ptr(ws), _stream(stream)), 'norm2')
         return list(out)
 
     def dot(self, a, b, nrhs=1, prec=F64, workspace=None, stream=None):
         """[<a_k, b_k>] as Python complex numbers."""
         ws = workspace if workspace is not None else self.new_workspace(OP_DOT, nrhs, prec)
-        out = (_D * (2 * nrhs))()
+        ns = self.nsys(nrhs)
+        out = (_D * (2 * ns))()
         _check(_lib.wdirac_dot(self._h, out, _ptr(a), _ptr(b), nrhs, prec, _ptr(ws), _stream(stream)), 'dot')
-        return [complex(out[2 * k], out[2 * k + 1]) for k in range(nrhs)]
+        return [complex(out[2 * k], out[2 * k + 1]) for k in range(ns)]
 
     def cg_eo(self, x, b, UR64, m0, tol=1e-10, maxit=10000, nrhs=1, mode=CG_F64, UR32=None, workspace=None,
               stream=None, allow=(ENOCONV, EBREAKDOWN)):
         """Returns (status, [stats dict per rhs])."""
         ws = workspace if workspace is not None else self.new_workspace(OP_CG, nrhs, mode)
-        stats = (CgStats * nrhs)()
+        stats = (CgStats * self.nsys(nrhs))()
         rc = _lib.wdirac_cg_eo(self._h, _ptr(x), _ptr(b), _ptr(UR64), _ptr(UR32), float(m0), float(tol),
                                int(maxit), nrhs, mode, _ptr(ws), stats, _stream(stream))
         _check(rc, 'cg_eo', allow)
@@ -259,14 +274,16 @@ class Lattice:
         return out
 
     def unpack_half(self, packed, parity, nrhs=1, prec=F64, into=None):
-        """Canonical full spinor tensor (zeros on the other parity) from a packed half field."""
-        shape = (nrhs,) + self.dims + (4, self.d)
+        """Canonical full spinor tensor (zeros on the other parity) from a packed half field
+        (for a batch: the flat concatenation of the lattices' spinors, shape (V_total, 4, d))."""
+        shape = ((nrhs,) + self.dims + (4, self.d)) if not self.batch else (self.V, 4, self.d)
         canon = into if into is not None else torch.zeros(shape, dtype=self.spinor_dtype(prec), device='cuda')
         self.unpack_spinor(canon, packed, parity, nrhs, prec)
         return canon
 
     def links_canonical(self, UR, prec=F64):
         dt = torch.float64 if self.real else torch.complex128
-        out = torch.empty(self.dims + (4, self.d, self.d), dtype=dt, device='cuda')
+        shape = (self.dims if not self.batch else (self.V,)) + (4, self.d, self.d)
+        out = torch.empty(shape, dtype=dt, device='cuda')
         self.unpack_links(out, UR, prec)
         return out

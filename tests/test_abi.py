@@ -113,3 +113,28 @@ def test_site_variant_unavailable_for_large_rep(W):
     assert rc == W.OK
     assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_SITE) == W.EUNSUPPORTED
     W._lib.wdirac_destroy(h)
+
+
+def create_batch(W, N, rep, shapes, bc=(-1, 1, 1, 1)):
+    h = ctypes.c_void_p()
+    gs = (W.Geom * len(shapes))(*[geom(W, dd, bc) for dd in shapes]) if shapes else None
+    rc = W._lib.wdirac_create_batch(ctypes.byref(h), N, rep, gs, len(shapes))
+    return rc, h
+
+
+def test_batch_sizes_and_rejects(W):
+    shapes = [(4, 6, 4, 6), (2, 2, 2, 2), (8, 8, 8, 8)]
+    rc, h = create_batch(W, 3, 2, shapes)            # SU(3) SYM, d = 6
+    assert rc == W.OK
+    strides = [((dd[0] * dd[1] * dd[2] * dd[3] // 2 + 255) // 256) * 256 for dd in shapes]
+    assert W._lib.wdirac_field_bytes(h, W.FIELD_HALF_SPINOR, 1, W.F64) == 4 * 6 * sum(strides) * 16
+    assert W._lib.wdirac_field_bytes(h, W.FIELD_LINKS, 1, W.F32) == 8 * 36 * sum(strides) * 8
+    dummy = ctypes.c_void_p(0x1000)
+    # a batch carries one right-hand side per lattice
+    assert W._lib.wdirac_dslash_eo(h, dummy, ctypes.c_void_p(0x2000), dummy, 0, 0, 2, 0.0, None, 1.0, 0,
+                                   None) == W.EINVAL
+    assert 'one right-hand side' in W.last_error()
+    assert W._lib.wdirac_destroy(h) == W.OK
+    assert create_batch(W, 3, 0, [(4, 4, 4, 4)] * 9)[0] == W.EINVAL        # more than 8 lattices
+    assert create_batch(W, 3, 0, [])[0] == W.EINVAL                         # none
+    assert create_batch(W, 3, 0, [(4, 4, 4, 4), (4, 3, 4, 4)])[0] == W.EINVAL  # an odd extent in a later lattice

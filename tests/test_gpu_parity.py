@@ -113,6 +113,23 @@ def test_dslash_rhs_groups(W, N, rep):
                     assert rel(got, exp) < TOL[prec], (nrhs, prec, nr, p)
 
 
+@pytest.mark.parametrize('variant', [1, 2, 0])
+def test_dslash_tile_orders(W, variant):
+    """t-blocked tile orders permute the work, never the result."""
+    s = Setup(3, 'FUND', (8, 6, 8, 16), seed=270)   # Y*Z = 128: whole tiles per (t, x) row
+    psi = s.spinor(271, 2)
+    for tb in (0, 2, 4, 8):
+        s.lat.set_option(W.OPT_TILE_TBLOCK, tb)
+        for prec in (0, 1):
+            s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, variant)
+            for p, dagger in ((0, 0), (1, 1)):
+                inp = s.to_gpu_half(psi, 1 - p, prec)
+                out = s.lat.new_half(2, prec)
+                s.lat.dslash_eo(out, inp, s.URg[prec], p, dagger, 2, 0.0, None, 1.0, prec)
+                got = s.from_gpu_half(out, p, 2, prec)
+                assert rel(got, hop_expect(s, psi, p, dagger, 0.0, 1.0, None)) < TOL[prec], (tb, prec, p)
+
+
 def test_autotune_keeps_results(W):
     s = Setup(3, 'SYM', (4, 6, 4, 6), seed=260)
     for prec in (0, 1):
