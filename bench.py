@@ -11,9 +11,13 @@ Headline value: hop bandwidth on compulsory bytes (8 links + 1 input spinor
 + 1 output spinor per output site), from HIP events around back-to-back
 dslash_eo launches on the stream they run on.  Also reported: the roofline of
 the hop kernel against the 8 TB/s HBM peak, CG time-to-solution in FP64 and
-mixed precision, and the CPU oracle timed on a bounded sample.
+mixed precision, and the CPU oracle timed on a bounded sample.  Once per run,
+after the timed steps: 12 point sources on SU(3) SYM 48x24^3 solved as one
+batched call and as 12 single calls (FP64 and mixed), FP64 against mixed CG on
+SU(4) 2AS 96x48^3, the three-lattice SU(3) SYM batch against separate solves,
+and the force on SU(2) ADJ 32x16^3.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--hops H] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--hops H] [--no-cpu] [--no-multi]
 """
 import argparse
 import hashlib
@@ -161,15 +165,132 @@ def multi_rhs_cg(W, torch, synth, name='su3_sym_48x24x24x24'):
     return out
 
 
+def mixed_cg_large(W, torch, synth, name='su4_2as_96x48x48x48'):
+    """Time-to-1e-10 of FP64 CG and mixed-precision CG (FP32 hops, FP64
+    reliable updates) on SU(4) 2AS 96x48^3, right-hand side D-hat^+ eta with
+    Gaussian eta.  Run once, after the timed steps."""
+    cfg = synth.CONFIGS[name]
+    dims, m0 = cfg['dims'], cfg['m0']
+    log(f'[bench] mixed vs FP64 CG on {name}: generating inputs')
+    lat = W.Lattice(cfg['N'], cfg['rep'], dims, cfg['bc'])
+    U = synth.expH_links_torch(dims, cfg['N'], cfg['eps'], cfg['seed'])
+    UR64, UR32 = lat.new_links(W.F64), lat.new_links(W.F32)
+    lat.rep_links(UR64, U, W.F64)
+    lat.rep_links(UR32, U, W.F32)
+    del U
+    g = torch.Generator(device='cuda')
+    g.manual_seed(cfg['seed'] + 11)
+    eta = torch.randn((1,) + tuple(dims) + (4, lat.d), dtype=torch.complex128, device='cuda', generator=g)
+    eta_e = lat.pack_half(eta, 0)
+    del eta
+    b = lat.new_half()
+    lat.apply_dhat(b, eta_e, UR64, m0, dagger=1)
+    del eta_e
+    lat.autotune(UR64, W.F64, 1)
+    lat.autotune(UR32, W.F32, 1)
+    ws = lat.new_workspace(W.OP_CG, 1, W.CG_MIXED)
+    x = lat.new_half()
+    out = {'workload': name, 'source': 'D-hat^+ eta, eta Gaussian'}
+    for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
+        x.zero_()
+        rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, mode=mode, UR32=UR32, workspace=ws)
+        st = st[0]
+        log(f'[bench]   {key}: {st["seconds"]:.3f} s, {st["iters"]} iterations, residual {st["true_rel_resid"]:.2e}')
+        out[key] = {'seconds': round(st['seconds'], 4), 'iters': st['iters'], 'hops': st['hops'],
+                    'reliable_updates': st['reliable_updates'], 'true_rel_resid': st['true_rel_resid'],
+                    'status': W.STATUS_NAMES.get(rc)}
+    out['mixed_speedup'] = round(out['f64']['seconds'] / out['mixed']['seconds'], 3)
+    return out
+
+
+def lattice_batch_cg(W, torch, synth):
+    """SU(3) SYM on 8^4, 12^4 and 16^3x32 (m0 = -0.4, Gaussian sources on the
+    even sites): one batched CG call over the three lattices against three
+    separate single-lattice calls, FP64."""
+    shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (32, 16, 16, 16)]
+    m0, bc, seed = -0.4, (-1, 1, 1, 1), 1003
+    log('[bench] batch of three lattices: generating inputs')
+    Us = [torch.from_numpy(synth.expH_links(dd, 3, 0.3, seed + 10 + k)).cuda() for k, dd in enumerate(shapes)]
+    etas = [torch.from_numpy(synth.gaussian_spinor((1,) + dd + (4, 6), seed + 20 + k)).cuda()
+            for k, dd in enumerate(shapes)]
+    lat = W.Lattice(3, 'SYM', shapes, bc)
+    UR = lat.new_links(W.F64)
+    lat.rep_links(UR, torch.cat([u.reshape(-1, 4, 3, 3) for u in Us]))
+    b = lat.pack_half(torch.cat([e.reshape(-1, 4, 6) for e in etas]), 0)
+    lat.autotune(UR, W.F64, 1)
+    x = lat.new_half()
+    lat.cg_eo(x, b, UR, m0, tol=1e-10, maxit=20000)       # warm-up
+    x.zero_()
+    rc, st = lat.cg_eo(x, b, UR, m0, tol=1e-10, maxit=20000)
+    out = {'lattices': ['x'.join(map(str, dd)) for dd in shapes], 'batched_seconds': round(st[0]['seconds'], 4),
+           'batched_iters': [s['iters'] for s in st], 'status': W.STATUS_NAMES.get(rc)}
+    sep, its = 0.0, []
+    for k, dd in enumerate(shapes):
+        l1 = W.Lattice(3, 'SYM', dd, bc)
+        U1 = l1.new_links(W.F64)
+        l1.rep_links(U1, Us[k])
+        b1 = l1.pack_half(etas[k], 0)
+        l1.autotune(U1, W.F64, 1)
+        x1 = l1.new_half()
+        l1.cg_eo(x1, b1, U1, m0, tol=1e-10, maxit=20000)   # warm-up
+        x1.zero_()
+        rc1, st1 = l1.cg_eo(x1, b1, U1, m0, tol=1e-10, maxit=20000)
+        sep += st1[0]['seconds']
+        its.append(st1[0]['iters'])
+    out.update({'separate_seconds': round(sep, 4), 'separate_iters': its,
+                'batched_speedup': round(sep / out['batched_seconds'], 3)})
+    log(f'[bench]   batched {out["batched_seconds"]} s vs separate {out["separate_seconds"]} s')
+    return out
+
+
+def force_timing(W, torch, synth, name='su2_adj_32x16x16x16', reps=10):
+    """The fermion force (three hops and the per-link kernel) and one
+    autograd forward + backward of the pseudofermion action on SU(2) ADJ
+    32x16^3, phi = D-hat^+ eta."""
+    from paper_2503_06721_amd.autograd import fermion_action
+    cfg = synth.CONFIGS[name]
+    dims, m0 = cfg['dims'], cfg['m0']
+    lat = W.Lattice(cfg['N'], cfg['rep'], dims, cfg['bc'])
+    U = torch.from_numpy(synth.links_for(cfg)).cuda()
+    UR = lat.new_links(W.F64)
+    lat.rep_links(UR, U)
+    lat.autotune(UR, W.F64, 1)
+    eta = torch.from_numpy(synth.gaussian_spinor((1,) + dims + (4, lat.d), cfg['seed'] + 2)).cuda()
+    phi = lat.new_half()
+    lat.apply_dhat(phi, lat.pack_half(eta, 0), UR, m0, dagger=1)
+    x = lat.new_half()
+    lat.cg_eo(x, phi, UR, m0, tol=1e-10)
+    G = torch.empty_like(U)
+    ws = lat.new_workspace(W.OP_FORCE)
+    lat.force_eo(G, x, UR, m0, U=U, workspace=ws)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lat.force_eo(G, x, UR, m0, U=U, workspace=ws)
+    t_force = (time.perf_counter() - t0) / reps
+    Uv = U.clone().requires_grad_(True)
+    fermion_action(Uv, phi, lat, m0, tol=1e-10).backward()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Uv.grad = None
+    S = fermion_action(Uv, phi, lat, m0, tol=1e-10)
+    S.backward()
+    torch.cuda.synchronize()
+    t_ag = time.perf_counter() - t0
+    return {'workload': name, 'force_eo_ms': round(t_force * 1e3, 3),
+            'autograd_action_and_gradient_ms': round(t_ag * 1e3, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=3)
     ap.add_argument('--warmup', type=int, default=1)
-    ap.add_argument('--hops', type=int, default=50, help='dslash_eo launches timed per step')
+    ap.add_argument('--hops', type=int, default=200, help='dslash_eo launches timed per step')
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU-oracle baseline')
     ap.add_argument('--no-cg', action='store_true', help='profiling aid: hops and links only')
-    ap.add_argument('--no-multi', action='store_true', help='skip the 12-source batched-vs-single CG comparison')
+    ap.add_argument('--no-multi', action='store_true',
+                    help='skip the one-off solver comparisons (12 sources batched vs single, SU(4) 2AS mixed vs '
+                         'FP64, three-lattice batch) and the force timing')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='run only a device copy of 2 GiB (x3), the known-size kernel that calibrates the '
                          'FETCH_SIZE / WRITE_SIZE counters, and print its bandwidth')
@@ -258,6 +379,7 @@ def main():
     wall = time.perf_counter() - t0
 
     hop_ms = float(np.mean([r['hop_ms'] for r in recs]))
+    hop_ms_median = float(np.median([r['hop_ms'] for r in recs]))
     copy_gbs = round(device_copy_gbps(torch)[1], 1)
     gbs = bytes_per_launch / (hop_ms * 1e-3) / 1e9
     traffic = measured_traffic(bytes_per_launch)
@@ -288,8 +410,10 @@ def main():
                                              / 1e9, 2),
                      'device_copy_GBps': copy_gbs,
                      'kernel': variant_name[tuned['f64']['variant']] + f' d=3 complex FP64, '
-                               f'xcd_remap={tuned["f64"]["xcd_remap"]}',
-                     'bytes_per_launch': bytes_per_launch, 'us_per_launch': round(hop_ms * 1e3, 3)},
+                               f'xcd_remap={tuned["f64"]["xcd_remap"]}, t-block={tuned["f64"]["tblock"]}',
+                     'bytes_per_launch': bytes_per_launch, 'us_per_launch': round(hop_ms * 1e3, 3),
+                     'us_per_launch_median_of_steps': round(hop_ms_median * 1e3, 3),
+                     'frac_of_device_copy': round(gbs / copy_gbs, 4)},
     }
     if not args.no_cg:
         def agg(key):
@@ -304,6 +428,11 @@ def main():
         del halves, x64, xmix, ws_cg, b, UR32
         torch.cuda.empty_cache()
         out['cg_multi_rhs_time_to_1e-10'] = multi_rhs_cg(W, torch, synth)
+        torch.cuda.empty_cache()
+        out['cg_mixed_vs_f64_time_to_1e-10'] = mixed_cg_large(W, torch, synth)
+        torch.cuda.empty_cache()
+        out['cg_lattice_batch_time_to_1e-10'] = lattice_batch_cg(W, torch, synth)
+        out['force'] = force_timing(W, torch, synth)
     if not args.no_cpu:
         log('[bench] timing the CPU oracle on a bounded sample')
         cb = cpu_baseline(cfg, U, psi[0])

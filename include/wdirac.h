@@ -67,7 +67,8 @@ typedef enum {
   WDIRAC_OP_FORCE = 2,
   WDIRAC_OP_NORM = 3,
   WDIRAC_OP_DOT = 4,
-  WDIRAC_OP_TUNE = 5
+  WDIRAC_OP_TUNE = 5,
+  WDIRAC_OP_MSHIFT = 6   /* `nrhs` argument = number of shifts (1..32) */
 } wdirac_op;
 
 typedef struct {
@@ -126,9 +127,12 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                      b divides T and tiles do not straddle
  *                                      (t, x) rows)
  *   WDIRAC_OPT_HOP_NR_F64 / _F32       right-hand sides sharing each link load
- *                                      in the colour-split form (1..4; the
+ *                                      (1..4).  Colour-split form: the
  *                                      largest divisor of nrhs not above it
- *                                      whose LDS staging fits is used)
+ *                                      whose LDS staging fits is used.
+ *                                      Site-parallel form: 4 (4 rhs across
+ *                                      the lanes of a wavefront) when it is 4
+ *                                      and divides nrhs, else 1
  * Options set here apply to every nrhs except those that wdirac_autotune()
  * has tuned.  Errors: EINVAL (unknown option or value), EUNSUPPORTED. */
 typedef enum {
@@ -150,14 +154,17 @@ typedef struct {
   int32_t xcd_remap;  /* 1 = contiguous tile ranges per XCD               */
   int32_t tblock;     /* t-block of the tile order (0 = lexicographic)    */
   int32_t candidates; /* number of shapes timed                           */
-  double us;          /* mean time of one hop launch with that shape      */
+  double us;          /* mean time of one hop launch with that shape (best
+                         round of the second pass)                        */
 } wdirac_tuning;
 
 /* Autotuner: times every available launch shape of the hopping kernel
- * (variant x right-hand sides per block x XCD tile mapping) for nrhs
- * right-hand sides in precision prec on the links UR (HIP events, 3 warm-up
- * and 10 timed launches each), and makes the fastest the one used for this
- * (prec, nrhs) by every later call on ctx (CG included).  Results never change
+ * (variant x right-hand sides per block x XCD tile mapping x tile order) for
+ * nrhs right-hand sides in precision prec on the links UR (HIP events: 3
+ * warm-up and 10 timed launches each, then the four fastest again in three
+ * interleaved rounds of 20, each keeping its fastest round), and makes the
+ * fastest the one used for this (prec, nrhs) by every later call on ctx (CG
+ * included).  Results never change
  * beyond rounding.  workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_TUNE,
  * nrhs, prec) bytes (overwritten).  best (host, nullable) receives the choice.
  * Synchronises.  Errors: EINVAL, EHIP. */
@@ -277,6 +284,32 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
                  double m0, double tol, int maxit, int nrhs, int mode, void *workspace,
                  wdirac_cg_stats *stats, void *stream);
 
+/* Multi-shift conjugate gradient (the multi-shift inversion of the RHMC,
+ * Sec. 5.3.2): x_k = (D-hat^+ D-hat + sigma_k)^{-1} b for the nshift shifts
+ * sigma_k >= 0 (host array, any order, 1 <= nshift <= 32), all from one
+ * Krylov space: the recursion runs on the smallest shift; the solution of
+ * every other shift is updated through the collinearity of the shifted
+ * residuals (r_k = zeta_k r), and a shift stops being updated once
+ * |zeta_k| ||r|| <= tol ||b|| / 2 (the margin covers the drift of the
+ * recursive residuals).  One right-hand side, FP64, single lattice
+ * (EUNSUPPORTED for a batch).  x: nshift packed FP64 even fields one after
+ * the other (out; every field overwritten, no initial guess), b: packed FP64
+ * even field.  stats: host array of nshift records, true_rel_resid =
+ * ||b - (A + sigma_k) x_k|| / ||b|| recomputed in FP64; status ENOCONV if it
+ * is above tol.  workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_MSHIFT,
+ * nshift, WDIRAC_F64).  Synchronises.  Errors: EINVAL, EUNSUPPORTED, EHIP,
+ * ENOCONV, EBREAKDOWN. */
+int wdirac_cg_mshift_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, double m0,
+                        const double *shifts, int nshift, double tol, int maxit, void *workspace,
+                        wdirac_cg_stats *stats, void *stream);
+
+/* out = a x + b y for nrhs packed half spinors of precision prec (y may be
+ * NULL: out = a x; out may alias x or y).  The linear combinations of
+ * solver outputs that a rational function needs, e.g. r(A) phi =
+ * gamma_0 phi + sum_k gamma_k x_k (Sec. 5.3.2).  Errors: EINVAL, EHIP. */
+int wdirac_axpby(const wdirac_ctx *ctx, void *out, double a, const void *x, double b, const void *y, int nrhs,
+                 int prec, void *stream);
+
 /* Fermion force of S_f = phi^+ (D-hat^+ D-hat)^{-1} phi (Sec. 5.3.1, force of
  * Sec. 2.5 in even-odd form) given the solution x = (D-hat^+ D-hat)^{-1} phi
  * (packed FP64 even half): for every link, the Hermitian traceless matrix
@@ -287,7 +320,10 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
  * receives scale * F (accumulate = 0) or out += scale * F (accumulate = 1),
  * where F = P when U is NULL, and F = G = 2i P U (U: the canonical
  * fundamental links) otherwise: G is the gradient in the convention
- * dS = Re tr(G^+ dU) for tangent variations dU = i w^a T^a U.  workspace:
+ * dS = Re tr(G^+ dU) for tangent variations dU = i w^a T^a U.  The same
+ * formula gives the force of one pole of a rational action (Sec. 5.3.2),
+ * phi^+ (D-hat^+ D-hat + sigma)^{-1} phi, with x = (D-hat^+ D-hat + sigma)^{-1}
+ * phi: scale = gamma_k and accumulate = 1 sum the poles.  workspace:
  * wdirac_workspace_bytes(ctx, WDIRAC_OP_FORCE, 1, WDIRAC_F64).  Synchronises.
  * Errors: EINVAL, EHIP. */
 int wdirac_force_eo(const wdirac_ctx *ctx, void *out, const void *x_e, const void *UR64, const void *U,

@@ -429,4 +429,198 @@ hipError_t launch_accum_x(void *x64, void *x32, const FieldShape &f, hipStream_t
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ multi-shift CG
+// Recursion of the base system (smallest shift sigma0) plus, for every shift
+// k with delta_k = sigma_k - sigma0 >= 0, the collinear shifted residual
+// r_k = zeta_k r.  With a_{-1} = 1, b_{-1} = 0, zeta_{-1} = zeta_0 = 1:
+//   zeta_k' = zeta_k zeta_k^old a_old / (a b_old (zeta_k^old - zeta_k)
+//                                        + zeta_k^old a_old (1 + delta_k a)),
+//   alpha_k = a zeta_k' / zeta_k,   beta_k = b (zeta_k' / zeta_k)^2,
+//   x_k += alpha_k p_k,   p_k = zeta_k' r' + beta_k p_k.
+__global__ void k_ms_init(MsScalars *S, const double *b2_partial, int nblk, ShiftList d, int nshift, int base,
+                          double sigma0, double tol) {
+  const double b2 = sum_partials(b2_partial, nblk);
+  if (threadIdx.x != 0) return;
+  MsScalars &s = *S;
+  s.b2 = b2;
+  s.stop2 = tol * tol * b2;
+  s.rr = b2;
+  s.pAp = 0.0;
+  s.alpha = 0.0;
+  s.alpha_old = 1.0;
+  s.beta = 0.0;
+  s.beta_old = 0.0;
+  s.sigma0 = sigma0;
+  s.iters = 0;
+  s.status = 0;
+  s.nshift = nshift;
+  s.base = base;
+  s.active = b2 > 0.0 ? 1 : 0;
+  for (int k = 0; k < MAXSHIFT; ++k) {
+    s.delta[k] = k < nshift ? d.v[k] : 0.0;
+    s.zeta[k] = s.zeta_old[k] = s.zeta_new[k] = 1.0;
+    s.as[k] = s.bs[k] = 0.0;
+    s.sact[k] = k < nshift ? s.active : 0;
+    s.upd[k] = 0;
+    s.siters[k] = 0;
+  }
+}
+
+hipError_t launch_ms_init(MsScalars *s, const double *b2_partial, int nblk, const ShiftList &delta, int nshift,
+                          int base, double sigma0, double tol, hipStream_t st) {
+  hipLaunchKernelGGL(k_ms_init, dim3(1), dim3(BT), 0, st, s, b2_partial, nblk, delta, nshift, base, sigma0, tol);
+  return hipGetLastError();
+}
+
+// <p, (A + sigma0) p> = ||D-hat p||^2 + sigma0 ||p||^2, base step length and
+// the shifted step lengths.
+__global__ void k_ms_alpha(MsScalars *S, const double *uu, int prow, int cnt, const double *pp, int nblk_pp) {
+  MsScalars &s = *S;
+  if (!s.active) return;
+  double pAp = sum_partials(uu, cnt);
+  if (pp) {
+    const double p2 = sum_partials(pp, nblk_pp);
+    pAp += s.sigma0 * p2;
+  }
+  (void)prow;
+  if (threadIdx.x != 0) return;
+  s.pAp = pAp;
+  if (!(pAp > 0.0) || !isfinite(pAp)) {
+    s.status = -5;
+    s.active = 0;
+    for (int k = 0; k < s.nshift; ++k) s.sact[k] = s.upd[k] = 0;
+    return;
+  }
+  const double a = s.rr / pAp;
+  s.alpha = a;
+  for (int k = 0; k < s.nshift; ++k) {
+    if (!s.sact[k]) continue;
+    const double z = s.zeta[k], zo = s.zeta_old[k];
+    const double den = a * s.beta_old * (zo - z) + zo * s.alpha_old * (1.0 + s.delta[k] * a);
+    const double zn = z * zo * s.alpha_old / den;
+    s.zeta_new[k] = zn;
+    s.as[k] = a * zn / z;
+  }
+}
+
+hipError_t launch_ms_alpha(MsScalars *s, const double *uu_partial, int prow, const Counts &counts,
+                           const double *pp_partial, int nblk_pp, hipStream_t st) {
+  hipLaunchKernelGGL(k_ms_alpha, dim3(1), dim3(BT), 0, st, s, uu_partial, prow, counts.n[0], pp_partial, nblk_pp);
+  return hipGetLastError();
+}
+
+// r -= alpha q (FP64), per-block partial sums of |r|^2.
+__global__ __launch_bounds__(BT) void k_ms_update_r(void *r, const void *q, const MsScalars *S, double *partial,
+                                                    FieldShape f) {
+  __shared__ double sh[BT / 64];
+  if (!S->active) return;
+  const double a = S->alpha;
+  const int i = blockIdx.x * BT + threadIdx.x;
+  double nrm = 0.0;
+  if (i < f.vh[0]) {
+    const size_t base = (size_t)f.off[0] + i;
+    for (int c = 0; c < f.ncomp; ++c) {
+      const size_t o = base + (size_t)c * f.stride[0];
+      const cplx<double> qv = ld<double>(q, o);
+      cplx<double> rv = ld<double>(r, o);
+      rv.re = fma(-a, qv.re, rv.re);
+      rv.im = fma(-a, qv.im, rv.im);
+      static_cast<cplx<double> *>(r)[o] = rv;
+      nrm += rv.re * rv.re + rv.im * rv.im;
+    }
+  }
+  nrm = block_sum(nrm, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = nrm;
+}
+
+hipError_t launch_ms_update_r(void *r, const void *q, const MsScalars *s, double *partial, const FieldShape &f,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_ms_update_r, dim3(blas_nblocks(f)), dim3(BT), 0, st, r, q, s, partial, f);
+  return hipGetLastError();
+}
+
+// beta, the shifted beta_k, rotation of the zeta history, and convergence of
+// each shift (|zeta_k| ||r|| <= tol ||b||: its update of this iteration is its
+// last).  The base recursion runs while any shift is still being updated.
+__global__ void k_ms_beta(MsScalars *S, const double *rr_partial, int nblk) {
+  MsScalars &s = *S;
+  if (!s.active) return;
+  const double rr = sum_partials(rr_partial, nblk);
+  if (threadIdx.x != 0) return;
+  s.iters += 1;
+  if (!isfinite(rr)) {
+    s.status = -5;
+    s.active = 0;
+    for (int k = 0; k < s.nshift; ++k) s.sact[k] = s.upd[k] = 0;
+    return;
+  }
+  const double b = rr / s.rr;
+  int any = 0;
+  for (int k = 0; k < s.nshift; ++k) {
+    s.upd[k] = s.sact[k];
+    if (!s.sact[k]) continue;
+    const double q = s.zeta_new[k] / s.zeta[k];
+    s.bs[k] = b * q * q;
+    s.siters[k] += 1;
+    s.zeta_old[k] = s.zeta[k];
+    s.zeta[k] = s.zeta_new[k];
+    if (s.zeta[k] * s.zeta[k] * rr <= s.stop2) s.sact[k] = 0;
+    any |= s.sact[k];
+  }
+  s.alpha_old = s.alpha;
+  s.beta_old = b;
+  s.beta = b;
+  s.rr = rr;
+  s.active = any;
+}
+
+hipError_t launch_ms_beta(MsScalars *s, const double *rr_partial, int nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_ms_beta, dim3(1), dim3(BT), 0, st, s, rr_partial, nblk);
+  return hipGetLastError();
+}
+
+// For every shift k (blockIdx.y): x_k += alpha_k p_k if it was updated this
+// iteration; p_k = zeta_k r + beta_k p_k if it is still needed (the base
+// direction while the recursion runs, the others while not converged).
+// Shift fields are `fstride` complex elements apart.
+__global__ __launch_bounds__(BT) void k_ms_update_xp(void *x, void *p, const void *r, const MsScalars *S,
+                                                     long long fstride, FieldShape f) {
+  const int k = blockIdx.y;
+  const MsScalars &s = *S;
+  const bool ux = s.upd[k] != 0;
+  const bool upd_p = k == s.base ? s.active != 0 : s.sact[k] != 0;
+  if (!ux && !upd_p) return;
+  const double a = s.as[k], z = s.zeta[k], b = s.bs[k];
+  const int i = blockIdx.x * BT + threadIdx.x;
+  if (i >= f.vh[0]) return;
+  cplx<double> *xk = static_cast<cplx<double> *>(x) + (size_t)k * fstride;
+  cplx<double> *pk = static_cast<cplx<double> *>(p) + (size_t)k * fstride;
+  const cplx<double> *rr = static_cast<const cplx<double> *>(r);
+  const size_t base = (size_t)f.off[0] + i;
+  for (int c = 0; c < f.ncomp; ++c) {
+    const size_t o = base + (size_t)c * f.stride[0];
+    const cplx<double> pv = pk[o];
+    if (ux) {
+      cplx<double> xv = xk[o];
+      xv.re = fma(a, pv.re, xv.re);
+      xv.im = fma(a, pv.im, xv.im);
+      xk[o] = xv;
+    }
+    if (upd_p) {
+      const cplx<double> rv = rr[o];
+      cplx<double> pn;
+      pn.re = fma(z, rv.re, b * pv.re);
+      pn.im = fma(z, rv.im, b * pv.im);
+      pk[o] = pn;
+    }
+  }
+}
+
+hipError_t launch_ms_update_xp(void *x, void *p, const void *r, const MsScalars *s, long long fstride,
+                               const FieldShape &f, int nshift, hipStream_t st) {
+  dim3 grid(blas_nblocks(f), nshift);
+  hipLaunchKernelGGL(k_ms_update_xp, grid, dim3(BT), 0, st, x, p, r, s, fstride, f);
+  return hipGetLastError();
+}
+
 }  // namespace wd

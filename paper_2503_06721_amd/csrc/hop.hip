@@ -78,7 +78,7 @@ __device__ __forceinline__ cplx<T> link_mac(T u, cplx<T> h, cplx<T> acc, bool) {
 }
 
 // ------------------------------------------------------- site-parallel form
-template <int D, bool REAL, typename T, int MU, int SIG, bool BWD>
+template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, bool NTL>
 __device__ __forceinline__ void sp_dir(cplx<T> (&acc)[4][D], const cplx<T> *__restrict__ in, int stride, int nb,
                                        const typename LinkT<T, REAL>::type *__restrict__ lk, int lsite) {
   cplx<T> h[2][D];
@@ -89,6 +89,9 @@ __device__ __forceinline__ void sp_dir(cplx<T> (&acc)[4][D], const cplx<T> *__re
     for (int s = 0; s < 4; ++s) p[s] = in[(size_t)(s * D + c) * stride + nb];
     h[0][c] = p[0] + ipow<PROJ_PH(MU, SIG, 0)>(p[2 + ECOL(MU, 0)]);
     h[1][c] = p[1] + ipow<PROJ_PH(MU, SIG, 1)>(p[2 + ECOL(MU, 1)]);
+    // FP64, large d_R: at most half of the spinor loads in flight
+    if constexpr (D >= 6 && sizeof(T) == 8)
+      if (2 * c + 2 == D) __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -96,7 +99,7 @@ __device__ __forceinline__ void sp_dir(cplx<T> (&acc)[4][D], const cplx<T> *__re
 #pragma unroll
     for (int b = 0; b < D; ++b) {
       // forward: U_ab;  backward: (U^+)_ab = conj(U_ba)
-      const auto u = lk[(size_t)(BWD ? b * D + a : a * D + b) * stride + lsite];
+      const auto u = ld_stream<NTL>(lk + (size_t)(BWD ? b * D + a : a * D + b) * stride + lsite);
       chi[0] = link_mac(u, h[0][b], chi[0], BWD);
       chi[1] = link_mac(u, h[1][b], chi[1], BWD);
     }
@@ -104,33 +107,50 @@ __device__ __forceinline__ void sp_dir(cplx<T> (&acc)[4][D], const cplx<T> *__re
     acc[1][a] = acc[1][a] + chi[1];
     acc[2][a] = acc[2][a] + ipow<RECON_PH(MU, SIG, 0)>(chi[RECON_SRC(MU, 0)]);
     acc[3][a] = acc[3][a] + ipow<RECON_PH(MU, SIG, 1)>(chi[RECON_SRC(MU, 1)]);
+    // large d_R: keep each row's link loads next to their use, so that the
+    // d_R^2 entries of a link are not all live at once
+    if constexpr (D >= 6) __builtin_amdgcn_sched_barrier(0);
   }
   __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int D, bool REAL, typename T, bool DAG, int MU>
+template <int D, bool REAL, typename T, bool DAG, int MU, bool NTL>
 __device__ __forceinline__ void sp_mu(cplx<T> (&acc)[4][D], const Geom &g, int parity,
                                       const typename LinkT<T, REAL>::type *links, const cplx<T> *in, int i, int t,
                                       int x, int y, int z) {
   const size_t lstride = (size_t)D * D * g.stride;
   constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
   const int nbf = nb_index(g, t, x, y, z, MU, 1);
-  sp_dir<D, REAL, T, MU, SF, false>(acc, in, g.stride, nbf, links + (size_t)(parity * 4 + MU) * lstride, i);
+  sp_dir<D, REAL, T, MU, SF, false, NTL>(acc, in, g.stride, nbf, links + (size_t)(parity * 4 + MU) * lstride, i);
   const int nbb = nb_index(g, t, x, y, z, MU, 0);
-  sp_dir<D, REAL, T, MU, -SF, true>(acc, in, g.stride, nbb, links + (size_t)((1 - parity) * 4 + MU) * lstride,
+  sp_dir<D, REAL, T, MU, -SF, true, NTL>(acc, in, g.stride, nbb, links + (size_t)((1 - parity) * 4 + MU) * lstride,
                                     nbb);
 }
 
-template <int D, bool REAL, typename T, bool DAG, int W>
+// Lanes of a site-parallel block: RL = 1: 256 sites of one right-hand side.
+// RL = 4: 64 sites x 4 right-hand sides; in each wavefront 16 consecutive
+// sites x 4 rhs (rhs = lane / 16), so the 4 lanes of a site load the same
+// link entries (one memory request serves them) and each rhs reads 16
+// consecutive spinor elements.  Work item = (tile, group of RL rhs), group
+// fastest.  NTL: links read with streaming loads (set when the launch has a
+// single group, so no other block re-reads them).
+template <int D, bool REAL, typename T, bool DAG, bool NTL, int RL, int W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k_hop_sp(HopArgs a) {
   using L = typename LinkT<T, REAL>::type;
-  const int tile = tile_order(tile_of_block(blockIdx.x, a.ntiles, a.xcd_remap), a);
+  constexpr int TS = 256 / RL;   // sites per tile
+  const int ngroups = a.ngroups;
+  const int w = tile_of_block(blockIdx.x, a.ntiles * ngroups, a.xcd_remap);
+  const int q = w / ngroups, grp = w - q * ngroups;
+  const int tile = tile_order(q, a);
   const int l = lattice_of_tile(a, tile);
   const Geom g = a.lat[l].g;
   const int tl = tile - a.lat[l].tile0;   // tile within its lattice
-  const int i = tl * 256 + threadIdx.x;
-  const int r = blockIdx.y;
-  const int sys = l * gridDim.y + r;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int sl = RL == 1 ? (int)threadIdx.x : wv * 16 + (lane & 15);
+  const int rk = RL == 1 ? 0 : lane >> 4;   // rhs of this lane within the group
+  const int i = tl * TS + sl;
+  const int r = grp * RL + rk;
+  const int sys0 = l * ngroups * RL + grp * RL;
   const size_t rstride = (size_t)4 * D * g.stride;
   const size_t fbase = (size_t)a.lat[l].soff + r * rstride;
   const L *links = static_cast<const L *>(a.links) + a.lat[l].loff;
@@ -147,14 +167,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[s][c] = mk<T>(0, 0);
-  sp_mu<D, REAL, T, DAG, 0>(acc, g, a.parity, links, in, is, t, x, y, z);
-  sp_mu<D, REAL, T, DAG, 1>(acc, g, a.parity, links, in, is, t, x, y, z);
-  sp_mu<D, REAL, T, DAG, 2>(acc, g, a.parity, links, in, is, t, x, y, z);
-  sp_mu<D, REAL, T, DAG, 3>(acc, g, a.parity, links, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 0, NTL>(acc, g, a.parity, links, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 1, NTL>(acc, g, a.parity, links, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 2, NTL>(acc, g, a.parity, links, in, is, t, x, y, z);
+  sp_mu<D, REAL, T, DAG, 3, NTL>(acc, g, a.parity, links, in, is, t, x, y, z);
   cplx<T> *out = static_cast<cplx<T> *>(a.out) + fbase;
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
   double nrm = 0.0;
-  // two straight-line epilogues: every accumulator is used on both paths
+  // Two straight-line epilogues: every accumulator is used on both paths.
+  // The output and x_add are streamed (each element is touched once).
   if (a.xadd) {
     const cplx<T> *xa = static_cast<const cplx<T> *>(a.xadd) + fbase;
 #pragma unroll
@@ -163,10 +184,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
       for (int c = 0; c < D; ++c) {
         const size_t o = (size_t)(s * D + c) * g.stride + i;
         cplx<T> v = cb * acc[s][c];
-        const cplx<T> xv = xa[o];
+        const cplx<T> xv = ld_nt(xa + o);
         v.re = fma(ca, xv.re, v.re);
         v.im = fma(ca, xv.im, v.im);
-        out[o] = v;
+        st_nt(out + o, v);
         nrm += (double)v.re * v.re + (double)v.im * v.im;
       }
   } else {
@@ -176,14 +197,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
       for (int c = 0; c < D; ++c) {
         const size_t o = (size_t)(s * D + c) * g.stride + i;
         const cplx<T> v = cb * acc[s][c];
-        out[o] = v;
+        st_nt(out + o, v);
         nrm += (double)v.re * v.re + (double)v.im * v.im;
       }
   }
   if (a.partial) {
-    __shared__ double sh[4];
-    const double s = block_sum(valid ? nrm : 0.0, sh);
-    if (threadIdx.x == 0) a.partial[(size_t)sys * a.prow + tl] = s;
+    __shared__ double sh[4][RL];
+    double v = valid ? nrm : 0.0;
+    if constexpr (RL == 1) {
+      v = block_sum(v, &sh[0][0]);
+      if (threadIdx.x == 0) a.partial[(size_t)sys0 * a.prow + tl] = v;
+    } else {
+      // sum over the 16 sites of each rhs in the wave, then over the waves
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      __syncthreads();
+      if ((lane & 15) == 0) sh[wv][rk] = v;
+      __syncthreads();
+      if (threadIdx.x < RL) {
+        const double s4 = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+        a.partial[(size_t)(sys0 + threadIdx.x) * a.prow + tl] = s4;
+      }
+    }
   }
 }
 
@@ -191,7 +226,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
 // Stage: this lane's link entries (row `row` of U for a forward hop, column
 // `row` of U for a backward hop, whose U^+ row is the conjugated column) and
 // colour component `row` of the neighbour spinor, spin-projected into LDS.
-template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, int NR>
+template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, int NR, bool NTL>
 __device__ __forceinline__ void cs_stage(typename LinkT<T, REAL>::type (&u)[D], cplx<T> (*hs)[2][D][64],
                                          const Geom &g, int parity, const typename LinkT<T, REAL>::type *links,
                                          const cplx<T> *in0, size_t rstride, int nb, int lsite, int row, int lane) {
@@ -200,7 +235,7 @@ __device__ __forceinline__ void cs_stage(typename LinkT<T, REAL>::type (&u)[D], 
   const int lpar = BWD ? 1 - parity : parity;
   const L *lk = links + (size_t)(lpar * 4 + MU) * D * D * stride;
 #pragma unroll
-  for (int b = 0; b < D; ++b) u[b] = lk[(size_t)(BWD ? b * D + row : row * D + b) * stride + lsite];
+  for (int b = 0; b < D; ++b) u[b] = ld_stream<NTL>(lk + (size_t)(BWD ? b * D + row : row * D + b) * stride + lsite);
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     const cplx<T> *in = in0 + k * rstride;
@@ -238,7 +273,7 @@ __device__ __forceinline__ void cs_compute(cplx<T> (&acc)[NR][4], const typename
 // phases (LDS buffers 0 and 1).  PAIR = true: both are staged before a single
 // barrier (LDS buffers 2*(MU&1) and 2*(MU&1)+1), which halves the barriers and
 // doubles the loads in flight per phase at the cost of twice the LDS.
-template <int D, bool REAL, typename T, int MU, int SF, int NR, bool PAIR, int NB>
+template <int D, bool REAL, typename T, int MU, int SF, int NR, bool PAIR, bool NTL, int NB>
 __device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64], const Geom &g, int parity,
                                       const typename LinkT<T, REAL>::type *links, const cplx<T> *in0, size_t rstride,
                                       int t, int x, int y, int z, int is, int row, int lane) {
@@ -248,22 +283,24 @@ __device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2
   L uf[D], ub[D];
   if constexpr (PAIR) {
     constexpr int B0 = 2 * (MU & 1);
-    cs_stage<D, REAL, T, MU, SF, false, NR>(uf, hs[B0], g, parity, links, in0, rstride, nbf, is, row, lane);
-    cs_stage<D, REAL, T, MU, -SF, true, NR>(ub, hs[B0 + 1], g, parity, links, in0, rstride, nbb, nbb, row, lane);
+    cs_stage<D, REAL, T, MU, SF, false, NR, NTL>(uf, hs[B0], g, parity, links, in0, rstride, nbf, is, row, lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL>(ub, hs[B0 + 1], g, parity, links, in0, rstride, nbb, nbb, row, lane);
     __syncthreads();
     cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[B0], lane);
     cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[B0 + 1], lane);
   } else {
-    cs_stage<D, REAL, T, MU, SF, false, NR>(uf, hs[0], g, parity, links, in0, rstride, nbf, is, row, lane);
+    cs_stage<D, REAL, T, MU, SF, false, NR, NTL>(uf, hs[0], g, parity, links, in0, rstride, nbf, is, row, lane);
     __syncthreads();
     cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[0], lane);
-    cs_stage<D, REAL, T, MU, -SF, true, NR>(ub, hs[1], g, parity, links, in0, rstride, nbb, nbb, row, lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL>(ub, hs[1], g, parity, links, in0, rstride, nbb, nbb, row, lane);
     __syncthreads();
     cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[1], lane);
   }
 }
 
-template <int D, bool REAL, typename T, bool DAG, int NR, bool PAIR, int W>
+// NTL: links read with streaming loads (set when the launch has a single
+// group of right-hand sides, so that no other block re-reads them).
+template <int D, bool REAL, typename T, bool DAG, int NR, bool PAIR, bool NTL, int W>
 __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) void k_hop_cs(HopArgs a) {
   constexpr int NB = PAIR ? 4 : 2;   // LDS buffers
   __shared__ cplx<T> hs[NB][NR][2][D][64];
@@ -298,13 +335,14 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[k][s] = mk<T>(0, 0);
   constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
-  cs_mu<D, REAL, T, 0, SF, NR, PAIR, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
-  cs_mu<D, REAL, T, 1, SF, NR, PAIR, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
-  cs_mu<D, REAL, T, 2, SF, NR, PAIR, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
-  cs_mu<D, REAL, T, 3, SF, NR, PAIR, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 0, SF, NR, PAIR, NTL, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 1, SF, NR, PAIR, NTL, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 2, SF, NR, PAIR, NTL, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 3, SF, NR, PAIR, NTL, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
   // Two straight-line epilogues (with and without x_add): every accumulator
-  // is used on both paths, so no arithmetic is sunk behind a branch.
+  // is used on both paths, so no arithmetic is sunk behind a branch.  The
+  // output and x_add are streamed (each element is touched once).
   double nrm[NR];
   if (a.xadd) {
 #pragma unroll
@@ -316,10 +354,10 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
       for (int s = 0; s < 4; ++s) {
         const size_t o = (size_t)(s * D + row) * g.stride + i;   // i < stride always
         cplx<T> v = cb * acc[k][s];
-        const cplx<T> xv = xa[o];
+        const cplx<T> xv = ld_nt(xa + o);
         v.re = fma(ca, xv.re, v.re);
         v.im = fma(ca, xv.im, v.im);
-        out[o] = v;
+        st_nt(out + o, v);
         nrm[k] += (double)v.re * v.re + (double)v.im * v.im;
       }
     }
@@ -332,7 +370,7 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
       for (int s = 0; s < 4; ++s) {
         const size_t o = (size_t)(s * D + row) * g.stride + i;
         const cplx<T> v = cb * acc[k][s];
-        out[o] = v;
+        st_nt(out + o, v);
         nrm[k] += (double)v.re * v.re + (double)v.im * v.im;
       }
     }
@@ -348,16 +386,23 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
 
 // -------------------------------------------------------------- dispatch
 // Waves per SIMD the register allocator is asked to allow (VGPR budget
-// 512 / W per lane), chosen per (d_R, precision) as the largest value that
-// compiles without spills for the colour-split kernel.
-constexpr int cs_waves(int D, bool dbl) {
-  return dbl ? (D <= 3 ? 4 : D <= 8 ? 3 : 2) : (D <= 4 ? 6 : D <= 6 ? 5 : D <= 10 ? 4 : 3);
+// 512 / W per lane), chosen per (d_R, precision, right-hand sides per block)
+// as the largest value that compiles without spills for the colour-split
+// kernel.  (d_R = 15 is capped at 128 VGPRs by its 960-lane block and
+// spills a little.)
+constexpr int cs_waves(int D, bool dbl, int NR) {
+  const int w = dbl ? (D <= 3 ? 4 : D <= 8 ? 3 : 2) : (D <= 4 ? 6 : D <= 6 ? 5 : D <= 10 ? 4 : 3);
+  const int cut = NR >= 3 ? 2 : NR == 2 ? 1 : 0;
+  return w - cut > 1 ? w - cut : 1;
 }
-constexpr int sp_waves(int D, bool dbl) { return dbl ? 2 : (D <= 2 ? 4 : 2); }
-// LDS of one colour-split block, hs[NB][NR][2][D][64], must fit 64 KB.
+constexpr int sp_waves(int D, bool dbl) { return dbl ? 2 : (D <= 2 ? 4 : D <= 4 ? 2 : 3); }
+// LDS of one colour-split block, hs[NB][NR][2][D][64], must fit the 160 KB
+// a gfx950 workgroup may allocate (less the reduction scratch).  Blocks above
+// 80 KB run one per CU; the autotuner weighs that against the link sharing.
+constexpr int LDS_BUDGET = 160 * 1024 - 256;
 template <int D, typename T, int NR, bool PAIR>
 constexpr bool cs_fits() {
-  return (PAIR ? 4 : 2) * NR * 2 * D * 64 * (int)sizeof(cplx<T>) <= 65536;
+  return (PAIR ? 4 : 2) * NR * 2 * D * 64 * (int)sizeof(cplx<T>) <= LDS_BUDGET;
 }
 
 // Tile bookkeeping of a launch with tiles of ts sites: per-lattice tile
@@ -388,21 +433,31 @@ static void set_tiles(HopArgs &a, int ts, int nrhs, Counts *counts, int *prow) {
   }
 }
 
+template <int D, bool REAL, typename T, bool DAG, int NR, bool NTL>
+static hipError_t launch_cs2(const HopArgs &a, int pair, hipStream_t st) {
+  constexpr int W = cs_waves(D, sizeof(T) == 8, NR);
+  dim3 grid(a.ntiles * a.ngroups);
+  if constexpr (cs_fits<D, T, NR, true>()) {
+    if (pair) {
+      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, true, NTL, W>), grid, dim3(64 * D), 0, st, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, false, NTL, W>), grid, dim3(64 * D), 0, st, a);
+  return hipGetLastError();
+}
+
+// Links are streamed when one block group covers all right-hand sides (with
+// several groups the groups of a tile re-read the links from L2).  Only the
+// one-rhs-per-block kernels carry the streaming form.
 template <int D, bool REAL, typename T, bool DAG, int NR>
 static hipError_t launch_cs(HopArgs a, int nrhs, int pair, hipStream_t st, Counts *counts, int *prow) {
   set_tiles(a, 64, nrhs, counts, prow);
   a.ngroups = nrhs / NR;
-  dim3 grid(a.ntiles * a.ngroups);
-  if constexpr (cs_fits<D, T, NR, true>()) {
-    if (pair) {
-      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, true, cs_waves(D, sizeof(T) == 8)>), grid, dim3(64 * D), 0,
-                         st, a);
-      return hipGetLastError();
-    }
+  if constexpr (NR == 1) {
+    if (a.ngroups == 1) return launch_cs2<D, REAL, T, DAG, 1, true>(a, pair, st);
   }
-  hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, false, cs_waves(D, sizeof(T) == 8)>), grid, dim3(64 * D), 0,
-                     st, a);
-  return hipGetLastError();
+  return launch_cs2<D, REAL, T, DAG, NR, false>(a, pair, st);
 }
 
 template <int D, bool REAL, typename T, bool DAG>
@@ -412,9 +467,18 @@ static hipError_t launch_typed(const HopArgs &a0, int nrhs, int variant, int nr,
   if (variant == HOP_SITE) {
     if constexpr (D <= 6) {
       HopArgs a = a0;
-      set_tiles(a, 256, nrhs, counts, prow);
-      dim3 grid(a.ntiles, nrhs);
-      hipLaunchKernelGGL((k_hop_sp<D, REAL, T, DAG, sp_waves(D, sizeof(T) == 8)>), grid, dim3(256), 0, st, a);
+      const int rl = (nr == 4 && nrhs % 4 == 0) ? 4 : 1;
+      set_tiles(a, 256 / rl, nrhs, counts, prow);
+      a.ngroups = nrhs / rl;
+      dim3 grid(a.ntiles * a.ngroups);
+      constexpr int SW = sp_waves(D, sizeof(T) == 8);
+      if (rl == 4) {
+        if (a.ngroups == 1) hipLaunchKernelGGL((k_hop_sp<D, REAL, T, DAG, true, 4, SW>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_hop_sp<D, REAL, T, DAG, false, 4, SW>), grid, dim3(256), 0, st, a);
+      } else {
+        if (a.ngroups == 1) hipLaunchKernelGGL((k_hop_sp<D, REAL, T, DAG, true, 1, SW>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_hop_sp<D, REAL, T, DAG, false, 1, SW>), grid, dim3(256), 0, st, a);
+      }
       return hipGetLastError();
     } else {
       return hipErrorInvalidValue;
@@ -466,11 +530,9 @@ int hop_max_nr(int d, int prec, int variant) {
   // largest NR in {1..4} whose LDS staging fits, as in cs_fits
   const int cb = prec == 0 ? 16 : 8, nbuf = variant == HOP_COLOUR_PAIR ? 4 : 2;
   int nr = 4;
-  while (nr > 1 && nbuf * nr * 2 * d * 64 * cb > 65536) --nr;
+  while (nr > 1 && nbuf * nr * 2 * d * 64 * cb > LDS_BUDGET) --nr;
   return nr;
 }
-
-int hop_tile_sites(int variant) { return variant == HOP_SITE ? 256 : 64; }
 
 bool hop_variant_ok(int d, int variant) {
   if (variant == HOP_SITE) return d <= 6;

@@ -56,6 +56,31 @@ __device__ __forceinline__ cplx<T> rfma(T r, cplx<T> b, cplx<T> acc) {
   acc.im = fma(r, b.im, acc.im);
   return acc;
 }
+// Non-temporal (streaming) loads and stores: the data is not kept in L2
+// for reuse, so it does not displace data that is.
+template <typename T>
+__device__ __forceinline__ cplx<T> ld_nt(const cplx<T> *p) {
+  using V = T __attribute__((ext_vector_type(2)));
+  const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+  return mk<T>(v.x, v.y);
+}
+__device__ __forceinline__ double ld_nt(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_nt(const float *p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void st_nt(cplx<T> *p, cplx<T> c) {
+  using V = T __attribute__((ext_vector_type(2)));
+  V v;
+  v.x = c.re;
+  v.y = c.im;
+  __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+}
+// *p, streamed if NT
+template <bool NT, typename L>
+__device__ __forceinline__ L ld_stream(const L *p) {
+  if constexpr (NT) return ld_nt(p);
+  else return *p;
+}
+
 // i^K * a for a compile-time K in {0,1,2,3}
 template <int K, typename T>
 __device__ __forceinline__ cplx<T> ipow(cplx<T> a) {

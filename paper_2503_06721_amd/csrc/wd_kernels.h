@@ -53,13 +53,13 @@ struct Counts {
 };
 
 // nr: right-hand sides per block of the colour-split form (1..4; reduced to
-// one that divides nrhs and fits LDS).  On return counts->n[s] holds the
+// one that divides nrhs and fits LDS); of the site-parallel form 1 or 4 (4 rhs
+// across the lanes of each wavefront).  On return counts->n[s] holds the
 // number of partial sums written for system s (the tiles of its lattice) and
 // *prow their row length.
 hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant, int nr,
                       hipStream_t st, Counts *counts, int *prow);
 int hop_max_nr(int d, int prec, int variant);
-int hop_tile_sites(int variant);
 bool hop_variant_ok(int d, int variant);
 
 // rep.hip (one lattice per call; the caller offsets the pointers)
@@ -129,6 +129,36 @@ hipError_t launch_cg_restart(CgScalars *s, const double *partial, int nblk, int 
                              int first, hipStream_t st);
 // x64 += x32, then x32 = 0
 hipError_t launch_accum_x(void *x64, void *x32, const FieldShape &f, hipStream_t st);
+
+// Multi-shift CG (see blas.hip for the recurrences).  One system (one rhs of
+// a single lattice); shift k's fields are `fstride` complex elements apart.
+constexpr int MAXSHIFT = 32;
+struct ShiftList {
+  double v[MAXSHIFT];
+};
+struct MsScalars {
+  double rr;          // <r, r> of the base recursion
+  double pAp;         // <p, (A + sigma0) p>
+  double alpha, alpha_old, beta, beta_old;
+  double b2, stop2;   // ||b||^2, tol^2 ||b||^2
+  double sigma0;      // base (smallest) shift
+  int iters, active, status, nshift, base, pad;
+  double delta[MAXSHIFT];   // sigma_k - sigma0
+  double zeta[MAXSHIFT], zeta_old[MAXSHIFT], zeta_new[MAXSHIFT];
+  double as[MAXSHIFT], bs[MAXSHIFT];   // shifted alpha_k, beta_k
+  int sact[MAXSHIFT];     // shift k is still updated
+  int upd[MAXSHIFT];      // shift k's x update is due in this iteration
+  int siters[MAXSHIFT];   // iterations that updated shift k
+};
+hipError_t launch_ms_init(MsScalars *s, const double *b2_partial, int nblk, const ShiftList &delta, int nshift,
+                          int base, double sigma0, double tol, hipStream_t st);
+hipError_t launch_ms_alpha(MsScalars *s, const double *uu_partial, int prow, const Counts &counts,
+                           const double *pp_partial, int nblk_pp, hipStream_t st);
+hipError_t launch_ms_update_r(void *r, const void *q, const MsScalars *s, double *partial, const FieldShape &f,
+                              hipStream_t st);
+hipError_t launch_ms_beta(MsScalars *s, const double *rr_partial, int nblk, hipStream_t st);
+hipError_t launch_ms_update_xp(void *x, void *p, const void *r, const MsScalars *s, long long fstride,
+                               const FieldShape &f, int nshift, hipStream_t st);
 
 // force.hip (one lattice per call; the caller offsets the pointers)
 // U nullable: if given, the output is 2i P U instead of P

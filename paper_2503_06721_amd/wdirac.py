@@ -25,7 +25,8 @@ FUND, ADJ, SYM, ASYM = 0, 1, 2, 3
 F64, F32 = 0, 1
 CG_F64, CG_MIXED = 0, 1
 FIELD_HALF_SPINOR, FIELD_LINKS = 0, 1
-OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE = 0, 1, 2, 3, 4, 5
+OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE, OP_MSHIFT = 0, 1, 2, 3, 4, 5, 6
+MAX_SHIFTS = 32
 (OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
  OPT_HOP_NR_F32, OPT_TILE_TBLOCK) = 0, 1, 2, 3, 4, 5, 6, 7
 HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR = 0, 1, 2
@@ -80,6 +81,9 @@ _SIGS = {
     'wdirac_dot': (_I, [_P, ctypes.POINTER(_D), _P, _P, _I, _I, _P, _P]),
     'wdirac_force_eo': (_I, [_P, _P, _P, _P, _P, _D, _D, _I, _P, _P]),
     'wdirac_autotune': (_I, [_P, _P, _I, _I, _P, ctypes.POINTER(Tuning), _P]),
+    'wdirac_cg_mshift_eo': (_I, [_P, _P, _P, _P, _D, ctypes.POINTER(_D), _I, _D, _I, _P, ctypes.POINTER(CgStats),
+                                 _P]),
+    'wdirac_axpby': (_I, [_P, _P, _D, _P, _D, _P, _I, _I, _P]),
     'wdirac_last_error': (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -256,6 +260,32 @@ class Lattice:
                                int(maxit), nrhs, mode, _ptr(ws), stats, _stream(stream))
         _check(rc, 'cg_eo', allow)
         return rc, [s.as_dict() for s in stats]
+
+    def new_shift_fields(self, nshift):
+        """Output buffer of cg_mshift_eo: nshift packed FP64 even fields, one after the other."""
+        return torch.zeros(nshift * self.field_bytes(FIELD_HALF_SPINOR, 1, F64), dtype=torch.uint8, device='cuda')
+
+    def shift_field(self, x, k):
+        """View of field k of a cg_mshift_eo output buffer."""
+        n = self.field_bytes(FIELD_HALF_SPINOR, 1, F64)
+        return x[k * n:(k + 1) * n]
+
+    def cg_mshift_eo(self, x, b, UR64, m0, shifts, tol=1e-10, maxit=10000, workspace=None, stream=None,
+                     allow=(ENOCONV, EBREAKDOWN)):
+        """x_k = (D-hat^+ D-hat + shifts[k])^{-1} b; returns (status, [stats dict per shift])."""
+        ns = len(shifts)
+        ws = workspace if workspace is not None else self.new_workspace(OP_MSHIFT, ns, F64)
+        sh = (_D * ns)(*[float(v) for v in shifts])
+        stats = (CgStats * ns)()
+        rc = _lib.wdirac_cg_mshift_eo(self._h, _ptr(x), _ptr(b), _ptr(UR64), float(m0), sh, ns, float(tol),
+                                      int(maxit), _ptr(ws), stats, _stream(stream))
+        _check(rc, 'cg_mshift_eo', allow)
+        return rc, [s.as_dict() for s in stats]
+
+    def axpby(self, out, a, x, b=0.0, y=None, nrhs=1, prec=F64, stream=None):
+        """out = a x + b y (y None: out = a x)."""
+        _check(_lib.wdirac_axpby(self._h, _ptr(out), float(a), _ptr(x), float(b), _ptr(y), nrhs, prec,
+                                 _stream(stream)), 'axpby')
 
     def force_eo(self, out, x_e, UR64, m0, U=None, scale=1.0, accumulate=0, workspace=None, stream=None):
         """out = scale * P (U None) or scale * 2i P U (U given), see include/wdirac.h."""

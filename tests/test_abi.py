@@ -138,3 +138,31 @@ def test_batch_sizes_and_rejects(W):
     assert create_batch(W, 3, 0, [(4, 4, 4, 4)] * 9)[0] == W.EINVAL        # more than 8 lattices
     assert create_batch(W, 3, 0, [])[0] == W.EINVAL                         # none
     assert create_batch(W, 3, 0, [(4, 4, 4, 4), (4, 3, 4, 4)])[0] == W.EINVAL  # an odd extent in a later lattice
+
+
+def test_mshift_argument_checks(W):
+    rc, h = create(W, 3, 0)
+    assert rc == W.OK
+    L = W._lib
+    dummy = ctypes.c_void_p(0x1000)
+    st = (W.CgStats * 33)()
+    sh = (ctypes.c_double * 33)(*([0.1] * 33))
+    hb = L.wdirac_field_bytes(h, W.FIELD_HALF_SPINOR, 1, W.F64)
+    x, b = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x100000 + 2 * hb)
+    assert L.wdirac_cg_mshift_eo(h, x, b, dummy, -0.2, sh, 0, 1e-10, 10, dummy, st, None) == W.EINVAL
+    assert L.wdirac_cg_mshift_eo(h, x, b, dummy, -0.2, sh, 33, 1e-10, 10, dummy, st, None) == W.EINVAL
+    neg = (ctypes.c_double * 2)(0.1, -1.0)
+    assert L.wdirac_cg_mshift_eo(h, x, b, dummy, -0.2, neg, 2, 1e-10, 10, dummy, st, None) == W.EINVAL
+    # b inside the output fields
+    assert L.wdirac_cg_mshift_eo(h, x, b, dummy, -0.2, sh, 3, 1e-10, 10, dummy, st, None) == W.EINVAL
+    assert 'overlap' in W.last_error()
+    assert L.wdirac_workspace_bytes(h, W.OP_MSHIFT, 32, W.F64) > L.wdirac_workspace_bytes(h, W.OP_MSHIFT, 1, W.F64)
+    assert L.wdirac_workspace_bytes(h, W.OP_MSHIFT, 33, W.F64) == 0
+    assert L.wdirac_workspace_bytes(h, W.OP_MSHIFT, 2, W.F32) == 0
+    assert L.wdirac_destroy(h) == W.OK
+    rc, hb2 = create_batch(W, 3, 0, [(4, 4, 4, 4), (2, 2, 2, 2)])
+    assert rc == W.OK
+    assert L.wdirac_cg_mshift_eo(hb2, x, ctypes.c_void_p(0x900000), dummy, -0.2, sh, 2, 1e-10, 10, dummy, st,
+                                 None) == W.EUNSUPPORTED
+    assert L.wdirac_workspace_bytes(hb2, W.OP_MSHIFT, 2, W.F64) == 0
+    L.wdirac_destroy(hb2)

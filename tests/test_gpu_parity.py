@@ -93,24 +93,28 @@ def test_dslash_eo(W, N, rep, dims):
                         assert err < TOL[prec], (variant, prec, p, dagger, alpha, err)
 
 
-@pytest.mark.parametrize('N,rep', [(3, 'FUND'), (3, 'SYM'), (2, 'ADJ'), (4, 'FUND')])
+@pytest.mark.parametrize('N,rep', [(3, 'FUND'), (3, 'SYM'), (2, 'ADJ'), (4, 'FUND'), (4, '2AS')])
 def test_dslash_rhs_groups(W, N, rep):
-    """Several right-hand sides sharing each link load (1..4 per block), with a
-    ragged tile tail; every rhs must equal its own single-rhs hop."""
+    """Several right-hand sides sharing each link load (1..4 per block in the
+    colour-split forms, 4 across the lanes of a wavefront in the site-parallel
+    form), with a ragged tile tail; every rhs must equal its own single-rhs
+    hop."""
     s = Setup(N, rep, (4, 6, 4, 6), seed=250 + N)
     for nrhs in (4, 6, 12):
         psi = s.spinor(251 + nrhs, nrhs)
+        exp = {(p, dagger): hop_expect(s, psi, p, dagger, 0.0, 1.0, None) for p, dagger in ((0, 0), (1, 1))}
         for prec in (0, 1):
-            for nr in (1, 2, 3, 4):
-                s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, nr)
-                log(f'rhs groups N={N} rep={rep} nrhs={nrhs} prec={prec} nr={nr}')
-                for p, dagger in ((0, 0), (1, 1)):
-                    inp = s.to_gpu_half(psi, 1 - p, prec)
-                    out = s.lat.new_half(nrhs, prec)
-                    s.lat.dslash_eo(out, inp, s.URg[prec], p, dagger, nrhs, 0.0, None, 1.0, prec)
-                    got = s.from_gpu_half(out, p, nrhs, prec)
-                    exp = hop_expect(s, psi, p, dagger, 0.0, 1.0, None)
-                    assert rel(got, exp) < TOL[prec], (nrhs, prec, nr, p)
+            for variant in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR, W.HOP_SITE):
+                s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, variant)
+                for nr in (1, 2, 3, 4):
+                    s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, nr)
+                    log(f'rhs groups N={N} rep={rep} nrhs={nrhs} prec={prec} variant={variant} nr={nr}')
+                    for p, dagger in ((0, 0), (1, 1)):
+                        inp = s.to_gpu_half(psi, 1 - p, prec)
+                        out = s.lat.new_half(nrhs, prec)
+                        s.lat.dslash_eo(out, inp, s.URg[prec], p, dagger, nrhs, 0.0, None, 1.0, prec)
+                        got = s.from_gpu_half(out, p, nrhs, prec)
+                        assert rel(got, exp[(p, dagger)]) < TOL[prec], (nrhs, prec, variant, nr, p)
 
 
 @pytest.mark.parametrize('variant', [1, 2, 0])
