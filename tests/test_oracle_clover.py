@@ -1,0 +1,139 @@
+"""Pins of the oracle's clover term (Sec. 6.1.2) and clover even-odd operator
+(Sec. 5.3.3, D-hat = D_ee - D_eo D_oo^{-1} D_oe) against closed forms,
+invariants and dense linear algebra (no GPU)."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import clover as CL
+from oracle import dense
+from oracle import dirac as D
+from oracle import lattice as L
+from oracle import reps as R
+from oracle.gamma import GAMMA, GAMMA5, I4
+from paper_2503_06721_amd import synth
+
+APBC = (-1, 1, 1, 1)
+
+
+def rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+
+
+def test_sigma_munu():
+    for m in range(4):
+        for n in range(4):
+            S = CL.SIGMA_MUNU[m, n]
+            assert np.allclose(S, S.conj().T)                       # Hermitian
+            assert np.allclose(S @ GAMMA5, GAMMA5 @ S)              # chirality blocks
+            assert np.allclose(S, -CL.SIGMA_MUNU[n, m])
+            if m != n:
+                assert np.allclose(S, 1j * GAMMA[m] @ GAMMA[n])
+                assert np.allclose(S @ S, I4)
+
+
+@pytest.mark.parametrize('N,rep', [(2, 'FUND'), (3, 'SYM'), (2, 'ADJ')])
+def test_clover_hermitian_and_chiral(N, rep):
+    dims = (2, 4, 2, 2)
+    UR = R.represent(synth.haar_links(dims, N, 61), rep)
+    d = UR.shape[-1]
+    M = CL.diagonal_blocks(UR, -0.3, 1.7)
+    assert np.allclose(M, np.conj(np.swapaxes(M, -1, -2)), atol=1e-14)
+    G5 = np.kron(GAMMA5, np.eye(d))
+    assert np.allclose(M @ G5, G5 @ M, atol=1e-14)
+
+
+def test_free_field_clover_vanishes():
+    dims = (2, 2, 2, 2)
+    UR = R.represent(synth.unit_links(dims, 3), 'SYM')
+    assert np.abs(CL.clover_term(UR, 1.3)).max() < 1e-15
+
+
+@pytest.mark.parametrize('N,rep', [(2, 'FUND'), (3, 'FUND'), (3, '2AS'), (2, 'ADJ')])
+def test_gauge_covariance(N, rep):
+    dims = (2, 2, 4, 2)
+    U = synth.haar_links(dims, N, 62)
+    g = synth.gauge_transform(dims, N, 63)
+    Ug = np.empty_like(U)
+    for mu in range(4):
+        gf = np.roll(g, -1, axis=mu)
+        Ug[..., mu, :, :] = g @ U[..., mu, :, :] @ np.conj(np.swapaxes(gf, -1, -2))
+    C = CL.clover_term(R.represent(U, rep), 0.9)
+    Cg = CL.clover_term(R.represent(Ug, rep), 0.9)
+    gR = R.represent(g[..., None, :, :], rep)[..., 0, :, :]
+    G = np.einsum('st,...ab->...satb', I4, gR).reshape(C.shape)
+    assert np.allclose(Cg, G @ C @ np.conj(np.swapaxes(G, -1, -2)), atol=1e-13)
+
+
+@pytest.mark.parametrize('rep', ['FUND', 'ADJ', 'SYM'])
+def test_constant_abelian_field_closed_form(rep):
+    """U_1(x) = exp(i theta x_2 sigma_3), other links 1, theta = 2 pi / L_2:
+    every leaf of the (1,2) plane is P = exp(-i theta sigma_3), so
+    F_12 = -F_21 = (R(P) - R(P)^+)/2 and all other F vanish."""
+    dims = (2, 2, 4, 2)
+    N, th, csw, m = 2, 2 * np.pi / 4, 1.3, -0.2
+    U = synth.unit_links(dims, N)
+    s3 = np.diag([1.0, -1.0]).astype(complex)
+    for x2 in range(dims[2]):
+        U[:, :, x2, :, 1] = scipy.linalg.expm(1j * th * x2 * s3)
+    UR = R.represent(U, rep)
+    d = UR.shape[-1]
+    PR = R.represent(scipy.linalg.expm(-1j * th * s3)[None], rep)[0]
+    F12 = (PR - PR.conj().T) / 2.0
+    site = (4.0 + m) * np.eye(4 * d) + 0.25j * csw * 2 * np.kron(CL.SIGMA_MUNU[1, 2], F12)
+    M = CL.diagonal_blocks(UR, m, csw)
+    assert np.allclose(M, site, atol=1e-13)
+
+
+def test_boundary_phase_cancels():
+    dims = (4, 2, 2, 2)
+    UR = R.represent(synth.haar_links(dims, 3, 64), 'FUND')
+    assert np.allclose(CL.clover_term(UR, 1.0), CL.clover_term(D.links_with_boundary_phase(UR, APBC), 1.0),
+                       atol=1e-14)
+
+
+@pytest.mark.parametrize('exponential', [False, True])
+def test_even_odd_schur_complement(exponential):
+    """D-hat is the Schur complement of the dense clover operator, and
+    det D = det D_oo det D-hat (Sec. 5.3.3)."""
+    dims = (2, 2, 2, 2)
+    N, rep, m, csw = 2, 'FUND', -0.1, 1.4
+    UR = R.represent(synth.haar_links(dims, N, 65), rep)
+    d = UR.shape[-1]
+    n = 4 * d
+    Dm = dense.dense_matrix(lambda v: CL.dirac_clover(v, UR, m, csw, APBC, exponential), dims + (4, d))
+    ev = L.parity_field(dims).ravel() == 0
+    idx = np.arange(Dm.shape[0]).reshape(dims + (n,))
+    ie = np.concatenate([idx[tuple(c)] for c in np.argwhere(L.parity_field(dims) == 0)])
+    io = np.concatenate([idx[tuple(c)] for c in np.argwhere(L.parity_field(dims) == 1)])
+    Dee, Deo, Doe, Doo = Dm[np.ix_(ie, ie)], Dm[np.ix_(ie, io)], Dm[np.ix_(io, ie)], Dm[np.ix_(io, io)]
+    schur = Dee - Deo @ np.linalg.solve(Doo, Doe)
+    half_shape = (int(ev.sum()), 4, d)
+    Dh = dense.dense_matrix(lambda v: CL.Dhat_clover(v, UR, m, csw, APBC, dims, exponential), half_shape)
+    assert np.allclose(Dh, schur, atol=1e-12)
+    Dhd = dense.dense_matrix(lambda v: CL.Dhat_clover(v, UR, m, csw, APBC, dims, exponential, dagger=True),
+                             half_shape)
+    assert np.allclose(Dhd, schur.conj().T, atol=1e-12)
+    s0, l0 = np.linalg.slogdet(Dm)
+    s1, l1 = np.linalg.slogdet(Doo)
+    s2, l2 = np.linalg.slogdet(schur)
+    assert abs(l0 - (l1 + l2)) < 1e-10 and abs(s0 - s1 * s2) < 1e-10
+
+
+def test_zero_csw_is_plain_dhat_over_mass():
+    dims = (2, 2, 4, 2)
+    UR = R.represent(synth.haar_links(dims, 2, 66), 'ADJ')
+    m = 0.05
+    x = synth.gaussian_spinor((16, 4, 3), 67)
+    assert rel(CL.Dhat_clover(x, UR, m, 0.0, APBC, dims), D.Dhat(x, UR, m, APBC, dims) / (4.0 + m)) < 1e-15
+
+
+def test_exponential_small_csw_matches_clover_to_second_order():
+    """(4+m) exp(A/(4+m)) = (4+m) + A + O(A^2): the difference scales as c_sw^2."""
+    dims = (2, 2, 2, 2)
+    UR = R.represent(synth.haar_links(dims, 2, 68), 'FUND')
+    m = 0.0
+    diffs = []
+    for c in (1e-2, 5e-3):
+        diffs.append(np.abs(CL.diagonal_blocks(UR, m, c, True) - CL.diagonal_blocks(UR, m, c, False)).max())
+    assert 3.8 < diffs[0] / diffs[1] < 4.2
