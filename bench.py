@@ -15,7 +15,8 @@ mixed precision, and the CPU oracle timed on a bounded sample.  Once per run,
 after the timed steps: 12 point sources on SU(3) SYM 48x24^3 solved as one
 batched call and as 12 single calls (FP64 and mixed), FP64 against mixed CG on
 SU(4) 2AS 96x48^3, the three-lattice SU(3) SYM batch against separate solves,
-and the force on SU(2) ADJ 32x16^3.
+the force on SU(2) ADJ 32x16^3, and on the benchmark lattice a 12-shift
+multi-shift solve and the clover-improved CG.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--hops H] [--no-cpu] [--no-multi]
 """
@@ -280,6 +281,66 @@ def force_timing(W, torch, synth, name='su2_adj_32x16x16x16', reps=10):
             'autograd_action_and_gradient_ms': round(t_ag * 1e3, 3)}
 
 
+def rhmc_and_clover(W, torch, synth, name='su3_fund_32x32x32x32'):
+    """On the benchmark lattice: 12 shifts (a zero shift and 11 from 1e-4 to
+    5.9) in one multi-shift call against 12 one-shift calls; and the
+    clover-improved operator (c_sw = 1) -- clover field construction, FP64 and
+    mixed CG to 1e-10 on D-hat^+ D-hat with the clover D-hat."""
+    cfg = synth.CONFIGS[name]
+    dims, m0 = cfg['dims'], cfg['m0']
+    lat = W.Lattice(cfg['N'], cfg['rep'], dims, cfg['bc'])
+    U = torch.from_numpy(synth.links_for(cfg)).cuda()
+    UR64, UR32 = lat.new_links(W.F64), lat.new_links(W.F32)
+    lat.rep_links(UR64, U, W.F64)
+    lat.rep_links(UR32, U, W.F32)
+    lat.autotune(UR64, W.F64, 1)
+    lat.autotune(UR32, W.F32, 1)
+    g = torch.Generator(device='cuda')
+    g.manual_seed(cfg['seed'] + 21)
+    eta = torch.randn((1,) + tuple(dims) + (4, lat.d), dtype=torch.complex128, device='cuda', generator=g)
+    b = lat.pack_half(eta, 0)
+    del eta
+    shifts = [0.0] + [1e-4 * 3.0 ** k for k in range(11)]
+    x = lat.new_shift_fields(len(shifts))
+    ws = lat.new_workspace(W.OP_MSHIFT, len(shifts), W.F64)
+    lat.cg_mshift_eo(x, b, UR64, m0, shifts, tol=1e-10, maxit=20000, workspace=ws)    # warm-up
+    rc, st = lat.cg_mshift_eo(x, b, UR64, m0, shifts, tol=1e-10, maxit=20000, workspace=ws)
+    one, its = 0.0, []
+    for k, sh in enumerate(shifts):
+        rc1, st1 = lat.cg_mshift_eo(lat.shift_field(x, k), b, UR64, m0, [sh], tol=1e-10, maxit=20000, workspace=ws)
+        one += st1[0]['seconds']
+        its.append(st1[0]['iters'])
+    log(f'[bench] multi-shift: {st[0]["seconds"]:.3f} s for 12 shifts, 12 single shifts {one:.3f} s')
+    ms = {'shifts': len(shifts), 'seconds': round(st[0]['seconds'], 4), 'iters': [s['iters'] for s in st],
+          'worst_true_rel_resid': max(s['true_rel_resid'] for s in st), 'status': W.STATUS_NAMES.get(rc),
+          'single_shift_calls_seconds': round(one, 4), 'single_shift_iters': its,
+          'speedup': round(one / st[0]['seconds'], 3)}
+    del x, ws
+    csw = 1.0
+    c64, c32 = lat.new_clover(W.F64), lat.new_clover(W.F32)
+    cws = lat.new_workspace(W.OP_CLOVER, 1, W.F64)
+    lat.clover_field(c64, U, m0, csw, 0, W.F64, workspace=cws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.clover_field(c64, U, m0, csw, 0, W.F64, workspace=cws)
+    torch.cuda.synchronize()
+    t_field = time.perf_counter() - t0
+    lat.clover_field(c32, U, m0, csw, 0, W.F32, workspace=cws)
+    del cws
+    cg_ws = lat.new_workspace(W.OP_CG, 1, W.CG_MIXED)
+    xc = lat.new_half()
+    cl = {'csw': csw, 'clover_field_ms': round(t_field * 1e3, 3)}
+    for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
+        xc.zero_()
+        rc, stc = lat.cg_eo_clover(xc, b, UR64, c64, tol=1e-10, maxit=20000, mode=mode, UR32=UR32, clov32=c32,
+                                   workspace=cg_ws)
+        cl[key] = {'seconds': round(stc[0]['seconds'], 4), 'iters': stc[0]['iters'],
+                   'true_rel_resid': stc[0]['true_rel_resid'], 'status': W.STATUS_NAMES.get(rc)}
+    cl['mixed_speedup'] = round(cl['f64']['seconds'] / cl['mixed']['seconds'], 3)
+    log(f'[bench] clover CG: {cl}')
+    return {'workload': name, 'multi_shift_time_to_1e-10': ms, 'clover_cg_time_to_1e-10': cl}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -381,6 +442,8 @@ def main():
     hop_ms = float(np.mean([r['hop_ms'] for r in recs]))
     hop_ms_median = float(np.median([r['hop_ms'] for r in recs]))
     copy_gbs = round(device_copy_gbps(torch)[1], 1)
+    # the library's streaming probe with the hop's read:write mix (7:1)
+    stream_gbs = round(W.stream_probe(1 << 24, 7, 20), 1)
     gbs = bytes_per_launch / (hop_ms * 1e-3) / 1e9
     traffic = measured_traffic(bytes_per_launch)
     out = {
@@ -413,7 +476,9 @@ def main():
                                f'xcd_remap={tuned["f64"]["xcd_remap"]}, t-block={tuned["f64"]["tblock"]}',
                      'bytes_per_launch': bytes_per_launch, 'us_per_launch': round(hop_ms * 1e3, 3),
                      'us_per_launch_median_of_steps': round(hop_ms_median * 1e3, 3),
-                     'frac_of_device_copy': round(gbs / copy_gbs, 4)},
+                     'frac_of_device_copy': round(gbs / copy_gbs, 4),
+                     'stream_7r1w_GBps': stream_gbs,
+                     'frac_of_stream_7r1w': round(gbs / stream_gbs, 4)},
     }
     if not args.no_cg:
         def agg(key):
@@ -433,6 +498,8 @@ def main():
         torch.cuda.empty_cache()
         out['cg_lattice_batch_time_to_1e-10'] = lattice_batch_cg(W, torch, synth)
         out['force'] = force_timing(W, torch, synth)
+        torch.cuda.empty_cache()
+        out['rhmc_and_clover'] = rhmc_and_clover(W, torch, synth)
     if not args.no_cpu:
         log('[bench] timing the CPU oracle on a bounded sample')
         cb = cpu_baseline(cfg, U, psi[0])

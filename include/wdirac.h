@@ -32,6 +32,8 @@
  *   links        U_R for both parities and the four positive directions in the
  *                same site-minor order, with the fermion boundary phase folded
  *                in (Sec. 6.3.1).
+ *   clover       per parity, the two 2d x 2d chirality blocks of every site
+ *                (row-major entries, site minor).
  */
 #ifndef WDIRAC_H
 #define WDIRAC_H
@@ -59,7 +61,7 @@ typedef enum { WDIRAC_F64 = 0, WDIRAC_F32 = 1 } wdirac_prec;
 typedef enum { WDIRAC_CG_F64 = 0, WDIRAC_CG_MIXED = 1 } wdirac_cg_mode;
 
 /* Kinds of packed objects, for wdirac_field_bytes(). */
-typedef enum { WDIRAC_FIELD_HALF_SPINOR = 0, WDIRAC_FIELD_LINKS = 1 } wdirac_field_kind;
+typedef enum { WDIRAC_FIELD_HALF_SPINOR = 0, WDIRAC_FIELD_LINKS = 1, WDIRAC_FIELD_CLOVER = 2 } wdirac_field_kind;
 /* Operations that need scratch memory, for wdirac_workspace_bytes(). */
 typedef enum {
   WDIRAC_OP_DHAT = 0,
@@ -68,7 +70,8 @@ typedef enum {
   WDIRAC_OP_NORM = 3,
   WDIRAC_OP_DOT = 4,
   WDIRAC_OP_TUNE = 5,
-  WDIRAC_OP_MSHIFT = 6   /* `nrhs` argument = number of shifts (1..32) */
+  WDIRAC_OP_MSHIFT = 6,  /* `nrhs` argument = number of shifts (1..32) */
+  WDIRAC_OP_CLOVER = 7   /* construction of a clover field */
 } wdirac_op;
 
 typedef struct {
@@ -284,6 +287,49 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
                  double m0, double tol, int maxit, int nrhs, int mode, void *workspace,
                  wdirac_cg_stats *stats, void *stream);
 
+/* Clover improvement (Sec. 6.1.2).  Builds the site-diagonal blocks of the
+ * clover-improved operator from the fundamental links U (canonical complex128
+ * [T][X][Y][Z][4][N][N], lattice after lattice for a batch):
+ *   D_ee + D_oo = (4 + m0) + csw (i/4) sum_{mu,nu} sigma_mu,nu F_mu,nu(x),
+ * or with exponential = 1 the exponential form
+ *   (4 + m0) exp(csw / (4 + m0) (i/4) sum_{mu,nu} sigma_mu,nu F_mu,nu(x)),
+ * sigma_mu,nu = (i/2)[gamma_mu, gamma_nu], F_mu,nu = (Q_mu,nu - Q_mu,nu^+)/8,
+ * Q the sum of the four plaquette leaves of the (mu, nu) plane at x (all
+ * starting at x, turning from mu to nu), in the fermion representation.  The
+ * packed clover field (wdirac_field_bytes(ctx, WDIRAC_FIELD_CLOVER, 1, prec)
+ * bytes, precision prec) holds, per site, the two 2d x 2d chirality blocks:
+ * D_ee on the even sites and D_oo^{-1} on the odd sites, which is what
+ * D-hat = D_ee - D_eo D_oo^{-1} D_oe (Sec. 5.3.3) applies.  Computed in FP64.
+ * workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_CLOVER, 1, WDIRAC_F64).
+ * Errors: EINVAL, EUNSUPPORTED (d_R not in {2, 3, 4, 6}), EHIP. */
+int wdirac_clover_field(const wdirac_ctx *ctx, void *clov, const void *U, double m0, double csw, int exponential,
+                        int prec, void *workspace, void *stream);
+
+/* out = D_ee in (parity 0, even half fields) or D_oo^{-1} in (parity 1, odd
+ * half fields) with the clover field clov, for nrhs packed half spinors of
+ * precision prec (clov of the same precision).  out may alias in.  Errors:
+ * EINVAL, EUNSUPPORTED, EHIP. */
+int wdirac_apply_clover(const wdirac_ctx *ctx, void *out, const void *in, const void *clov, int parity, int nrhs,
+                        int prec, void *stream);
+
+/* Clover even-odd operator out = D-hat in, D-hat = D_ee - D_eo D_oo^{-1} D_oe
+ * (Sec. 5.3.3; dagger = 1: D-hat^+ = D_ee - D_oe^+ D_oo^{-1} D_eo^+, the
+ * blocks being Hermitian).  The mass enters through the clover field.  Note
+ * the normalisation: with csw = 0 this is the D-hat of wdirac_apply_dhat
+ * divided by (4 + m0).  workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_DHAT,
+ * nrhs, prec).  out must not alias in.  Errors: EINVAL, EUNSUPPORTED, EHIP. */
+int wdirac_apply_dhat_clover(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, const void *clov,
+                             int dagger, int nrhs, int prec, void *workspace, void *stream);
+
+/* Conjugate gradient on (D-hat^+ D-hat) x = b with the clover D-hat above;
+ * otherwise exactly as wdirac_cg_eo (mode, stopping on the FP64 true
+ * residual, reliable updates, statistics, workspace WDIRAC_OP_CG).  clov64:
+ * the FP64 clover field; clov32: the FP32 one (mode WDIRAC_CG_MIXED only,
+ * may be NULL otherwise). */
+int wdirac_cg_eo_clover(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32,
+                        const void *clov64, const void *clov32, double tol, int maxit, int nrhs, int mode,
+                        void *workspace, wdirac_cg_stats *stats, void *stream);
+
 /* Multi-shift conjugate gradient (the multi-shift inversion of the RHMC,
  * Sec. 5.3.2): x_k = (D-hat^+ D-hat + sigma_k)^{-1} b for the nshift shifts
  * sigma_k >= 0 (host array, any order, 1 <= nshift <= 32), all from one
@@ -328,6 +374,19 @@ int wdirac_axpby(const wdirac_ctx *ctx, void *out, double a, const void *x, doub
  * Errors: EINVAL, EHIP. */
 int wdirac_force_eo(const wdirac_ctx *ctx, void *out, const void *x_e, const void *UR64, const void *U,
                     double m0, double scale, int accumulate, void *workspace, void *stream);
+
+/* Measurement aid for the roofline (not part of the operator): sustained
+ * bandwidth of a pure streaming kernel with nread input streams and one output
+ * stream of `elems` 16-byte elements each, out[i] = sum_s in_s[i], one element
+ * per lane, non-temporal loads and stores -- the practical ceiling of a
+ * kernel with that read:write mix (the hop reads about 7 bytes per byte it
+ * writes).  bufs: caller-owned device memory of (nread + 1) * elems * 16
+ * bytes (inputs first, contents irrelevant; the output part is overwritten).
+ * One warm-up launch, then `reps` launches timed with HIP events on stream;
+ * *gbps (host) receives (bytes read + written) / time.  Synchronises.
+ * Errors: EINVAL (null pointer, nread outside [1, 8], elems outside
+ * [1, 2^31], reps outside [1, 1000]), EHIP. */
+int wdirac_stream_probe(void *bufs, size_t elems, int nread, int reps, double *gbps, void *stream);
 
 /* Thread-local description of the last error (empty string if none). */
 const char *wdirac_last_error(void);

@@ -234,9 +234,34 @@ int hop(const wdirac_ctx *c, void *out, const void *in, const void *UR, int out_
   return WDIRAC_OK;
 }
 
+// D_ee in (parity 0) or D_oo^{-1} in (parity 1) with a clover field, lattice
+// by lattice; out may alias in.
+int clover_apply(const wdirac_ctx *c, void *out, const void *in, const void *clov, int parity, int nrhs, int prec,
+                 hipStream_t st) {
+  const size_t cb = prec == WDIRAC_F64 ? 16 : 8;
+  for (int l = 0; l < c->nlat; ++l) {
+    const size_t so = (size_t)4 * c->d * c->spre[l] * cb;
+    const size_t co = (size_t)16 * c->d * c->d * c->spre[l] * cb;
+    WD_HIP(wd::launch_clover_apply(static_cast<char *>(out) + so, static_cast<const char *>(in) + so,
+                                   static_cast<const char *>(clov) + co, c->g[l], c->d, parity, nrhs, prec, st));
+  }
+  return WDIRAC_OK;
+}
+
 // out = D-hat in (dagger = 0) or D-hat^+ in (dagger = 1); tmp is an odd half field.
+// Without a clover field: D-hat = (4+m)^2 - D_eo D_oe (Sec. 5.3.3, one factor
+// of 4+m absorbed).  With one: D-hat = D_ee - D_eo D_oo^{-1} D_oe, whose
+// diagonal blocks are Hermitian, so the adjoint only swaps to the dagger hops.
 int dhat(const wdirac_ctx *c, void *out, const void *in, const void *UR, double m0, int dagger, int nrhs, int prec,
-         void *tmp, double *partial, hipStream_t st, wd::Counts *counts = nullptr, int *prow = nullptr) {
+         void *tmp, double *partial, hipStream_t st, wd::Counts *counts = nullptr, int *prow = nullptr,
+         const void *clov = nullptr) {
+  if (clov) {
+    WD_TRY(hop(c, tmp, in, UR, 1, dagger, nrhs, 0.0, nullptr, 1.0, prec, nullptr, st));
+    WD_TRY(clover_apply(c, tmp, tmp, clov, 1, nrhs, prec, st));
+    WD_TRY(clover_apply(c, out, in, clov, 0, nrhs, prec, st));
+    WD_TRY(hop(c, out, tmp, UR, 0, dagger, nrhs, 1.0, out, -1.0, prec, partial, st, counts, prow));
+    return WDIRAC_OK;
+  }
   const double m4 = (4.0 + m0) * (4.0 + m0);
   WD_TRY(hop(c, tmp, in, UR, 1, dagger, nrhs, 0.0, nullptr, 1.0, prec, nullptr, st));
   WD_TRY(hop(c, out, tmp, UR, 0, dagger, nrhs, m4, in, -1.0, prec, partial, st, counts, prow));
@@ -342,11 +367,19 @@ size_t wdirac_field_bytes(const wdirac_ctx *ctx, int kind, int nrhs, int prec) {
     return half_bytes(ctx, nrhs, prec);
   }
   if (kind == WDIRAC_FIELD_LINKS) return (size_t)8 * ctx->d * ctx->d * ctx->spre[ctx->nlat] * el * (ctx->real ? 1 : 2);
+  if (kind == WDIRAC_FIELD_CLOVER)
+    return wd::clover_supported(ctx->d) ? (size_t)16 * ctx->d * ctx->d * ctx->spre[ctx->nlat] * 2 * el : 0;
   return 0;
 }
 
 size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec) {
   if (!ctx) return 0;
+  if (op == WDIRAC_OP_CLOVER) {   // scratch of the clover-field construction
+    if (!wd::clover_supported(ctx->d)) return 0;
+    int mx = 0;
+    for (int l = 0; l < ctx->nlat; ++l) mx = std::max(mx, ctx->g[l].Vh);
+    return align256((size_t)6 * ctx->d * ctx->d * 2 * mx * 16);
+  }
   if (op == WDIRAC_OP_MSHIFT) {   // nrhs = number of shifts
     if (nrhs < 1 || nrhs > wd::MAXSHIFT || prec != WDIRAC_F64 || ctx->nlat != 1) return 0;
     return carve_ms(ctx, nrhs, nullptr).bytes;
@@ -685,8 +718,9 @@ int wdirac_dot(const wdirac_ctx *ctx, double *out, const void *a, const void *b,
 // equation and replaces the residual in FP64 whenever ||r|| drops below
 // delta times its largest value since the previous replacement (reliable
 // updates), accumulating the FP32 correction into the FP64 solution.
-int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32, double m0,
-                 double tol, int maxit, int nrhs, int mode, void *workspace, wdirac_cg_stats *stats, void *stream) {
+static int cg_impl(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32,
+                   const void *clov64, const void *clov32, double m0, double tol, int maxit, int nrhs, int mode,
+                   void *workspace, wdirac_cg_stats *stats, void *stream) {
   const auto t0 = std::chrono::steady_clock::now();
   WD_TRY(check_ctx(ctx));
   WD_TRY(check_ptr(x, "x"));
@@ -713,8 +747,8 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
   WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, ns, tol, 1, 1, st));
   // r = b - A x (FP64)
   auto true_residual = [&]() -> int {
-    WD_TRY(dhat(ctx, w.u, x, UR64, m0, 0, nrhs, WDIRAC_F64, w.t, nullptr, st));
-    WD_TRY(dhat(ctx, w.q, w.u, UR64, m0, 1, nrhs, WDIRAC_F64, w.v, nullptr, st));
+    WD_TRY(dhat(ctx, w.u, x, UR64, m0, 0, nrhs, WDIRAC_F64, w.t, nullptr, st, nullptr, nullptr, clov64));
+    WD_TRY(dhat(ctx, w.q, w.u, UR64, m0, 1, nrhs, WDIRAC_F64, w.v, nullptr, st, nullptr, nullptr, clov64));
     WD_HIP(wd::launch_residual(w.r, b, w.q, w.P2, f, st));
     hop_count += 4;
     return WDIRAC_OK;
@@ -722,13 +756,14 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
   WD_TRY(true_residual());
   WD_HIP(wd::launch_cg_restart(w.sc, w.P2, nbb, ns, tol, 0, 1, st));
   void *r = w.r, *p = w.p, *q = w.q, *t = w.t, *u = w.u, *v = w.v, *xi = x;
-  const void *UR = UR64;
+  const void *UR = UR64, *clov = clov64;
   int prec = WDIRAC_F64;
   if (mixed) {
     WD_HIP(wd::launch_convert(w.r32, WDIRAC_F32, w.r, WDIRAC_F64, f, st));
     WD_HIP(wd::launch_lincomb(w.x32, 0.0, w.r32, 0.0, nullptr, f, WDIRAC_F32, st));
     r = w.r32; p = w.p32; q = w.q32; t = w.t32; u = w.u32; v = w.v32; xi = w.x32;
     UR = UR32;
+    clov = clov32;
     prec = WDIRAC_F32;
   }
   WD_HIP(wd::launch_lincomb(p, 1.0, r, 0.0, nullptr, f, prec, st));
@@ -766,9 +801,9 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
     for (int it = 0; it < nit; ++it) {
       wd::Counts cnt{};
       int prow = 0;
-      WD_TRY(dhat(ctx, u, p, UR, m0, 0, nrhs, prec, t, w.P1, st, &cnt, &prow));
+      WD_TRY(dhat(ctx, u, p, UR, m0, 0, nrhs, prec, t, w.P1, st, &cnt, &prow, clov));
       WD_HIP(wd::launch_cg_alpha(w.sc, w.P1, prow, cnt, ns, st));
-      WD_TRY(dhat(ctx, q, u, UR, m0, 1, nrhs, prec, v, nullptr, st));
+      WD_TRY(dhat(ctx, q, u, UR, m0, 1, nrhs, prec, v, nullptr, st, nullptr, nullptr, clov));
       WD_HIP(wd::launch_cg_update_xr(xi, prec, r, p, q, w.sc, w.P2, f, prec, st));
       WD_HIP(wd::launch_cg_beta(w.sc, w.P2, nbb, ns, delta, st));
       WD_HIP(wd::launch_cg_update_p(p, r, w.sc, f, prec, st));
@@ -815,6 +850,72 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
   return worst;
 }
 
+int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32, double m0,
+                 double tol, int maxit, int nrhs, int mode, void *workspace, wdirac_cg_stats *stats, void *stream) {
+  return cg_impl(ctx, x, b, UR64, UR32, nullptr, nullptr, m0, tol, maxit, nrhs, mode, workspace, stats, stream);
+}
+
+// ------------------------------------------------------------------ clover
+int wdirac_clover_field(const wdirac_ctx *ctx, void *clov, const void *U, double m0, double csw, int exponential,
+                        int prec, void *workspace, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(clov, "clov"));
+  WD_TRY(check_ptr(U, "U"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  WD_TRY(check_prec(prec));
+  if (!wd::clover_supported(ctx->d)) return fail(WDIRAC_EUNSUPPORTED, "clover term available for d_R in {2,3,4,6}");
+  if (!std::isfinite(m0) || !std::isfinite(csw) || 4.0 + m0 == 0.0)
+    return fail(WDIRAC_EINVAL, "m0 and csw must be finite and 4 + m0 != 0");
+  if (exponential != 0 && exponential != 1) return fail(WDIRAC_EINVAL, "exponential must be 0 or 1");
+  const size_t el = prec == WDIRAC_F64 ? 8 : 4;
+  for (int l = 0; l < ctx->nlat; ++l) {
+    const char *Ul = static_cast<const char *>(U) + (size_t)ctx->vpre[l] * 4 * ctx->N * ctx->N * 16;
+    char *cl = static_cast<char *>(clov) + (size_t)16 * ctx->d * ctx->d * ctx->spre[l] * 2 * el;
+    WD_HIP(wd::launch_clover_field(cl, Ul, static_cast<double *>(workspace), ctx->g[l], ctx->N, ctx->rep, ctx->d, m0,
+                                   csw, exponential, prec, S(stream)));
+  }
+  return WDIRAC_OK;
+}
+
+int wdirac_apply_clover(const wdirac_ctx *ctx, void *out, const void *in, const void *clov, int parity, int nrhs,
+                        int prec, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(in, "in"));
+  WD_TRY(check_ptr(clov, "clov"));
+  WD_TRY(check_parity(parity));
+  WD_TRY(check_nrhs(ctx, nrhs));
+  WD_TRY(check_prec(prec));
+  if (!wd::clover_supported(ctx->d)) return fail(WDIRAC_EUNSUPPORTED, "clover term available for d_R in {2,3,4,6}");
+  return clover_apply(ctx, out, in, clov, parity, nrhs, prec, S(stream));
+}
+
+int wdirac_apply_dhat_clover(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, const void *clov,
+                             int dagger, int nrhs, int prec, void *workspace, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(in, "in"));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_ptr(clov, "clov"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  WD_TRY(check_nrhs(ctx, nrhs));
+  WD_TRY(check_prec(prec));
+  if (dagger != 0 && dagger != 1) return fail(WDIRAC_EINVAL, "dagger must be 0 or 1");
+  if (!wd::clover_supported(ctx->d)) return fail(WDIRAC_EUNSUPPORTED, "clover term available for d_R in {2,3,4,6}");
+  if (out == in) return fail(WDIRAC_EINVAL, "out must not alias in");
+  return dhat(ctx, out, in, UR, 0.0, dagger, nrhs, prec, workspace, nullptr, S(stream), nullptr, nullptr, clov);
+}
+
+int wdirac_cg_eo_clover(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32,
+                        const void *clov64, const void *clov32, double tol, int maxit, int nrhs, int mode,
+                        void *workspace, wdirac_cg_stats *stats, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(clov64, "clov64"));
+  if (mode == WDIRAC_CG_MIXED) WD_TRY(check_ptr(clov32, "clov32"));
+  if (!wd::clover_supported(ctx->d)) return fail(WDIRAC_EUNSUPPORTED, "clover term available for d_R in {2,3,4,6}");
+  return cg_impl(ctx, x, b, UR64, UR32, clov64, clov32, 0.0, tol, maxit, nrhs, mode, workspace, stats, stream);
+}
+
 // ------------------------------------------------------------ multi-shift CG
 int wdirac_cg_mshift_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, double m0,
                         const double *shifts, int nshift, double tol, int maxit, void *workspace,
@@ -849,12 +950,10 @@ int wdirac_cg_mshift_eo(const wdirac_ctx *ctx, void *x, const void *b, const voi
   wd::ShiftList dl{};
   for (int k = 0; k < nshift; ++k) dl.v[k] = shifts[k] - sigma0;
   auto field = [&](void *base_ptr, int k) { return static_cast<void *>(static_cast<char *>(base_ptr) + (size_t)k * hb); };
-  // x_k = 0, p_k = b, r = b
+  // x_k = 0 (padding included), p_k = b, r = b
+  WD_HIP(hipMemsetAsync(x, 0, (size_t)nshift * hb, st));
   WD_HIP(wd::launch_lincomb(w.r, 1.0, b, 0.0, nullptr, f, WDIRAC_F64, st));
-  for (int k = 0; k < nshift; ++k) {
-    WD_HIP(wd::launch_lincomb(field(x, k), 0.0, b, 0.0, nullptr, f, WDIRAC_F64, st));
-    WD_HIP(wd::launch_lincomb(field(w.p, k), 1.0, b, 0.0, nullptr, f, WDIRAC_F64, st));
-  }
+  for (int k = 0; k < nshift; ++k) WD_HIP(wd::launch_lincomb(field(w.p, k), 1.0, b, 0.0, nullptr, f, WDIRAC_F64, st));
   WD_HIP(wd::launch_norm2_partial(w.P2, b, f, WDIRAC_F64, st));
   // the recursion stops at half the tolerance, leaving room for the drift of
   // the recursive residuals from the true ones checked below

@@ -476,7 +476,13 @@ hipError_t launch_ms_init(MsScalars *s, const double *b2_partial, int nblk, cons
 // the shifted step lengths.
 __global__ void k_ms_alpha(MsScalars *S, const double *uu, int prow, int cnt, const double *pp, int nblk_pp) {
   MsScalars &s = *S;
-  if (!s.active) return;
+  const int act = s.active;
+  __syncthreads();
+  // the x updates flagged by the previous iteration's beta step are done:
+  // iterations launched after convergence must not repeat them
+  if (threadIdx.x == 0)
+    for (int k = 0; k < MAXSHIFT; ++k) s.upd[k] = 0;
+  if (!act) return;
   double pAp = sum_partials(uu, cnt);
   if (pp) {
     const double p2 = sum_partials(pp, nblk_pp);

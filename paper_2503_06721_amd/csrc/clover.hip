@@ -1,0 +1,422 @@
+// Clover improvement (Sec. 6.1.2): the site-diagonal blocks
+//   D_ee + D_oo = (4 + m) + c_sw (i/4) sum_{mu,nu} sigma_mu,nu F_mu,nu
+// (or, exponential form, (4 + m) exp(c_sw/(4+m) (i/4) sum sigma F)), with
+// F_mu,nu = (Q_mu,nu - Q_mu,nu^+)/8 and Q the sum of the four clover leaves of
+// the (mu, nu) plane at x, all starting at x and turning from mu to nu.
+//
+// The leaves are products of fundamental links (N x N); each leaf is mapped to
+// the fermion representation entry by entry (wd_rep.h), which is far cheaper
+// than multiplying d_R x d_R represented links.  Since R(L)^+ = R(L^+),
+//   F_R = sum_leaves (R(L) - R(L)^+) / 8.
+// sigma_mu,nu = (i/2)[gamma_mu, gamma_nu] commutes with gamma_5 =
+// diag(1,1,-1,-1), so each site holds two 2d x 2d chirality blocks (spins
+// {0,1} and {2,3}).  Stored per parity: the even sites keep the blocks
+// (D_ee), the odd sites their inverses (D_oo^{-1}), which is what the
+// even-odd operator D-hat = D_ee - D_eo D_oo^{-1} D_oe applies.
+#include "wd_common.h"
+#include "wd_kernels.h"
+#include "wd_rep.h"
+
+namespace wd {
+
+// Plane p = 0..5 <-> (mu, nu) = (0,1) (0,2) (0,3) (1,2) (1,3) (2,3).
+__device__ __forceinline__ void plane_dirs(int p, int &mu, int &nu) {
+  mu = p < 3 ? 0 : p < 5 ? 1 : 2;
+  nu = p < 3 ? p + 1 : p < 5 ? p - 1 : 3;
+}
+
+// Lexicographic index of c + a e_mu + b e_nu (periodic wrap).
+__device__ __forceinline__ size_t lex_at(const Geom &g, const int (&c)[4], int mu, int a, int nu, int b) {
+  int q[4] = {c[0], c[1], c[2], c[3]};
+  const int L[4] = {g.T, g.X, g.Y, g.Z};
+  q[mu] += a;
+  q[nu] += b;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) q[k] = (q[k] + L[k]) % L[k];
+  return (((size_t)q[0] * g.X + q[1]) * g.Y + q[2]) * g.Z + q[3];
+}
+
+template <int N>
+__device__ __forceinline__ void load_link(cplx<double> (&u)[N][N], const cplx<double> *U, size_t lex, int mu,
+                                          bool dag) {
+  const cplx<double> *p = U + (lex * 4 + mu) * N * N;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      const cplx<double> v = p[dag ? j * N + i : i * N + j];
+      u[i][j] = dag ? mk(v.re, -v.im) : v;
+    }
+}
+
+// acc = acc * u
+template <int N>
+__device__ __forceinline__ void mul_right(cplx<double> (&acc)[N][N], const cplx<double> (&u)[N][N]) {
+  cplx<double> r[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      cplx<double> s = mk(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = cfma(acc[i][k], u[k][j], s);
+      r[i][j] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc[i][j] = r[i][j];
+}
+
+// Leaf k of plane (mu, nu) at x as four (site offset (a_mu, b_nu), direction,
+// dagger) factors.
+struct LeafStep {
+  signed char a, b, dir, dag;   // dir 0 = mu, 1 = nu
+};
+__constant__ LeafStep kLeaf[4][4] = {
+    // U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+    {{0, 0, 0, 0}, {1, 0, 1, 0}, {0, 1, 0, 1}, {0, 0, 1, 1}},
+    // U_nu(x) U_mu(x-mu+nu)^+ U_nu(x-mu)^+ U_mu(x-mu)
+    {{0, 0, 1, 0}, {-1, 1, 0, 1}, {-1, 0, 1, 1}, {-1, 0, 0, 0}},
+    // U_mu(x-mu)^+ U_nu(x-mu-nu)^+ U_mu(x-mu-nu) U_nu(x-nu)
+    {{-1, 0, 0, 1}, {-1, -1, 1, 1}, {-1, -1, 0, 0}, {0, -1, 1, 0}},
+    // U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^+
+    {{0, -1, 1, 1}, {0, -1, 0, 0}, {1, -1, 1, 0}, {0, 0, 0, 1}},
+};
+
+// F scratch: F[p][A][B] of every site, [6][D][D][V] complex FP64.  Thread per
+// (plane, site), consecutive threads on consecutive sites.
+template <int N, int REP>
+__global__ __launch_bounds__(256) void k_clover_F(const cplx<double> *__restrict__ U, cplx<double> *__restrict__ F,
+                                                  Geom g) {
+  constexpr int D = rep_dim(N, REP);
+  const size_t V = 2 * (size_t)g.Vh;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 6 * V) return;
+  const int p = (int)(gid / V);
+  const size_t lex = gid - (size_t)p * V;
+  int mu, nu;
+  plane_dirs(p, mu, nu);
+  size_t r = lex;
+  int c[4];
+  c[3] = (int)(r % g.Z); r /= g.Z;
+  c[2] = (int)(r % g.Y); r /= g.Y;
+  c[1] = (int)(r % g.X);
+  c[0] = (int)(r / g.X);
+  cplx<double> *Fp = F + (size_t)p * D * D * V + lex;
+  for (int k = 0; k < 4; ++k) {
+    cplx<double> L[N][N];
+    for (int f = 0; f < 4; ++f) {
+      const LeafStep s = kLeaf[k][f];
+      cplx<double> u[N][N];
+      load_link<N>(u, U, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
+      if (f == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int j = 0; j < N; ++j) L[i][j] = u[i][j];
+      } else {
+        mul_right<N>(L, u);
+      }
+    }
+    // F += (R(L) - R(L)^+) / 8
+    for (int A = 0; A < D; ++A)
+      for (int B = 0; B < D; ++B) {
+        const cplx<double> rab = rep_entry<N, REP>(L, A, B), rba = rep_entry<N, REP>(L, B, A);
+        cplx<double> v = mk(0.125 * (rab.re - rba.re), 0.125 * (rab.im + rba.im));
+        const size_t o = (size_t)(A * D + B) * V;
+        if (k > 0) v = v + Fp[o];
+        Fp[o] = v;
+      }
+  }
+}
+
+// sigma blocks: S.v[p][c][s][t] = 2 x (chirality block c of sigma_mu,nu)_st for
+// plane p (the factor 2 counts the (nu, mu) term of the sum).
+struct SigmaBlocks {
+  cplx<double> v[6][2][2][2];
+};
+
+constexpr int MAXB = 2 * 6;   // largest chirality block (d_R <= 6)
+
+// Gauss-Jordan inverse with partial pivoting of the n x n matrix a (destroyed).
+template <int NB>
+__device__ void invert(cplx<double> (&a)[NB][NB], cplx<double> (&inv)[NB][NB]) {
+  for (int i = 0; i < NB; ++i)
+    for (int j = 0; j < NB; ++j) inv[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
+  for (int col = 0; col < NB; ++col) {
+    int piv = col;
+    double best = a[col][col].re * a[col][col].re + a[col][col].im * a[col][col].im;
+    for (int r = col + 1; r < NB; ++r) {
+      const double m2 = a[r][col].re * a[r][col].re + a[r][col].im * a[r][col].im;
+      if (m2 > best) {
+        best = m2;
+        piv = r;
+      }
+    }
+    if (piv != col)
+      for (int j = 0; j < NB; ++j) {
+        const cplx<double> t1 = a[col][j], t2 = inv[col][j];
+        a[col][j] = a[piv][j];
+        inv[col][j] = inv[piv][j];
+        a[piv][j] = t1;
+        inv[piv][j] = t2;
+      }
+    const cplx<double> d = a[col][col];
+    const double dn = 1.0 / (d.re * d.re + d.im * d.im);
+    const cplx<double> di = mk(d.re * dn, -d.im * dn);
+    for (int j = 0; j < NB; ++j) {
+      a[col][j] = cmul(a[col][j], di);
+      inv[col][j] = cmul(inv[col][j], di);
+    }
+    for (int r = 0; r < NB; ++r) {
+      if (r == col) continue;
+      const cplx<double> f = a[r][col];
+      for (int j = 0; j < NB; ++j) {
+        a[r][j] = a[r][j] - cmul(f, a[col][j]);
+        inv[r][j] = inv[r][j] - cmul(f, inv[col][j]);
+      }
+    }
+  }
+}
+
+// e = exp(a) by scaling and squaring of the Taylor series (a destroyed).
+template <int NB>
+__device__ void expm(cplx<double> (&a)[NB][NB], cplx<double> (&e)[NB][NB]) {
+  double nrm = 0.0;   // max column sum
+  for (int j = 0; j < NB; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < NB; ++i) s += sqrt(a[i][j].re * a[i][j].re + a[i][j].im * a[i][j].im);
+    nrm = s > nrm ? s : nrm;
+  }
+  int sq = 0;
+  while (nrm > 0.25 && sq < 60) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double sc = ldexp(1.0, -sq);
+  for (int i = 0; i < NB; ++i)
+    for (int j = 0; j < NB; ++j) a[i][j] = sc * a[i][j];
+  // Horner: e = I + a (I + a/2 (I + a/3 (... (I + a/K))))
+  constexpr int K = 18;
+  cplx<double> t[NB][NB];
+  for (int i = 0; i < NB; ++i)
+    for (int j = 0; j < NB; ++j) e[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
+  for (int k = K; k >= 1; --k) {
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) {
+        cplx<double> s = mk(0.0, 0.0);
+        for (int l = 0; l < NB; ++l) s = cfma(a[i][l], e[l][j], s);
+        t[i][j] = (1.0 / k) * s;
+      }
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) e[i][j] = t[i][j] + mk(i == j ? 1.0 : 0.0, 0.0);
+  }
+  for (int q = 0; q < sq; ++q) {
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) {
+        cplx<double> s = mk(0.0, 0.0);
+        for (int l = 0; l < NB; ++l) s = cfma(e[i][l], e[l][j], s);
+        t[i][j] = s;
+      }
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) e[i][j] = t[i][j];
+  }
+}
+
+// Thread per (site, chirality block c): assemble the block from F, add the
+// mass term (or exponentiate), invert on odd sites, store in precision T.
+// Clover field layout: [parity][c][row][col][stride] complex.
+template <int D, typename T>
+__global__ __launch_bounds__(64) void k_clover_finish(const cplx<double> *__restrict__ F, void *__restrict__ clov,
+                                                      Geom g, SigmaBlocks S, double m0, double csw, int expo) {
+  constexpr int NB = 2 * D;
+  const size_t V = 2 * (size_t)g.Vh;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 2 * V) return;
+  const int c = (int)(gid / V);
+  const size_t lex = gid - (size_t)c * V;
+  size_t r = lex;
+  const int z = (int)(r % g.Z); r /= g.Z;
+  const int y = (int)(r % g.Y); r /= g.Y;
+  const int x = (int)(r % g.X);
+  const int t = (int)(r / g.X);
+  const int par = (t + x + y + z) & 1;
+  const size_t cb = lex >> 1;
+  cplx<double> M[NB][NB];
+  // (i/4) c_sw sum_p S[p][c][s][t] F_p[a][b]
+  for (int s = 0; s < 2; ++s)
+    for (int a = 0; a < D; ++a)
+      for (int tt = 0; tt < 2; ++tt)
+        for (int b = 0; b < D; ++b) {
+          cplx<double> acc = mk(0.0, 0.0);
+          for (int p = 0; p < 6; ++p) acc = cfma(S.v[p][c][s][tt], F[((size_t)p * D * D + a * D + b) * V + lex], acc);
+          M[s * D + a][tt * D + b] = mk(-0.25 * csw * acc.im, 0.25 * csw * acc.re);   // (i/4) c_sw acc
+        }
+  cplx<double> out[NB][NB];
+  const double m4 = 4.0 + m0;
+  if (!expo) {
+    for (int i = 0; i < NB; ++i) M[i][i].re += m4;
+    if (par == 0) {
+      for (int i = 0; i < NB; ++i)
+        for (int j = 0; j < NB; ++j) out[i][j] = M[i][j];
+    } else {
+      invert<NB>(M, out);
+    }
+  } else {
+    // even: (4+m) exp(M/(4+m)); odd: exp(-M/(4+m))/(4+m)
+    const double f = (par == 0 ? 1.0 : -1.0) / m4;
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) M[i][j] = f * M[i][j];
+    expm<NB>(M, out);
+    const double sc = par == 0 ? m4 : 1.0 / m4;
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) out[i][j] = sc * out[i][j];
+  }
+  cplx<T> *dst = static_cast<cplx<T> *>(clov) + ((size_t)(par * 2 + c) * NB * NB) * g.stride + cb;
+  for (int i = 0; i < NB; ++i)
+    for (int j = 0; j < NB; ++j) dst[(size_t)(i * NB + j) * g.stride] = mk<T>((T)out[i][j].re, (T)out[i][j].im);
+}
+
+// out = M_c in on the sites of `parity` (thread per (site, rhs, block); the
+// thread reads its block's spin components before writing them, so out may
+// alias in).
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_clover_apply(cplx<T> *out, const cplx<T> *in, const cplx<T> *__restrict__ clov,
+                                                      Geom g, int parity, int nrhs) {
+  constexpr int NB = 2 * D;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int rc = blockIdx.y;   // rhs * 2 + block
+  const int rr = rc >> 1, c = rc & 1;
+  if (i >= g.Vh || rr >= nrhs) return;
+  const size_t rbase = (size_t)rr * 4 * D * g.stride + i;
+  cplx<T> v[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) v[k] = in[rbase + (size_t)(2 * c * D + k) * g.stride];
+  const cplx<T> *M = clov + ((size_t)(parity * 2 + c) * NB * NB) * g.stride + i;
+  cplx<T> w[NB];
+#pragma unroll
+  for (int a = 0; a < NB; ++a) {
+    cplx<T> s = mk<T>(0, 0);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) s = cfma(M[(size_t)(a * NB + b) * g.stride], v[b], s);
+    w[a] = s;
+  }
+#pragma unroll
+  for (int k = 0; k < NB; ++k) out[rbase + (size_t)(2 * c * D + k) * g.stride] = w[k];
+}
+
+// ------------------------------------------------------------------ launch
+template <int N, int REP>
+static hipError_t F_launch(const void *U, double *F, const Geom &g, hipStream_t st) {
+  const size_t n = 6 * 2 * (size_t)g.Vh;
+  hipLaunchKernelGGL((k_clover_F<N, REP>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                     (const cplx<double> *)U, (cplx<double> *)F, g);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t finish_launch(const double *F, void *clov, const Geom &g, const SigmaBlocks &S, double m0,
+                                double csw, int expo, int prec, hipStream_t st) {
+  const size_t n = 2 * 2 * (size_t)g.Vh;
+  const dim3 grid((unsigned)((n + 63) / 64));
+  if (prec == 0)
+    hipLaunchKernelGGL((k_clover_finish<D, double>), grid, dim3(64), 0, st, (const cplx<double> *)F, clov, g, S, m0,
+                       csw, expo);
+  else
+    hipLaunchKernelGGL((k_clover_finish<D, float>), grid, dim3(64), 0, st, (const cplx<double> *)F, clov, g, S, m0,
+                       csw, expo);
+  return hipGetLastError();
+}
+
+static SigmaBlocks sigma_blocks() {
+  // gamma_mu = [[0, e_mu], [e_mu^+, 0]], e_0 = -1, e_k = -i sigma_k (Sec. 2.2);
+  // sigma_mu,nu = i gamma_mu gamma_nu (mu != nu) = diag(i e_mu e_nu^+, i e_mu^+ e_nu).
+  cplx<double> e[4][2][2];
+  const cplx<double> z = mk(0.0, 0.0);
+  e[0][0][0] = mk(-1.0, 0.0); e[0][0][1] = z; e[0][1][0] = z; e[0][1][1] = mk(-1.0, 0.0);
+  // -i sigma_1, -i sigma_2, -i sigma_3
+  e[1][0][0] = z; e[1][0][1] = mk(0.0, -1.0); e[1][1][0] = mk(0.0, -1.0); e[1][1][1] = z;
+  e[2][0][0] = z; e[2][0][1] = mk(-1.0, 0.0); e[2][1][0] = mk(1.0, 0.0); e[2][1][1] = z;
+  e[3][0][0] = mk(0.0, -1.0); e[3][0][1] = z; e[3][1][0] = z; e[3][1][1] = mk(0.0, 1.0);
+  auto hmul = [](cplx<double> a, cplx<double> b) { return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); };
+  auto conj = [](cplx<double> a) { return mk(a.re, -a.im); };
+  SigmaBlocks S{};
+  const int pm[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  for (int p = 0; p < 6; ++p) {
+    const int mu = pm[p][0], nu = pm[p][1];
+    for (int s = 0; s < 2; ++s)
+      for (int t = 0; t < 2; ++t) {
+        cplx<double> up = z, lo = z;
+        for (int k = 0; k < 2; ++k) {
+          const cplx<double> a = hmul(e[mu][s][k], conj(e[nu][t][k]));      // (e_mu e_nu^+)_st
+          const cplx<double> b = hmul(conj(e[mu][k][s]), e[nu][k][t]);      // (e_mu^+ e_nu)_st
+          up = mk(up.re + a.re, up.im + a.im);
+          lo = mk(lo.re + b.re, lo.im + b.im);
+        }
+        // 2 i (...)
+        S.v[p][0][s][t] = mk(-2.0 * up.im, 2.0 * up.re);
+        S.v[p][1][s][t] = mk(-2.0 * lo.im, 2.0 * lo.re);
+      }
+  }
+  return S;
+}
+
+template <int N>
+static hipError_t F_launch_n(const void *U, double *F, const Geom &g, int rep, hipStream_t st) {
+  switch (rep) {
+    case 0: return F_launch<N, 0>(U, F, g, st);
+    case 1: return F_launch<N, 1>(U, F, g, st);
+    case 2: return F_launch<N, 2>(U, F, g, st);
+    case 3:
+      if constexpr (N > 2) return F_launch<N, 3>(U, F, g, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_clover_field(void *clov, const void *U, double *F, const Geom &g, int N, int rep, int d, double m0,
+                               double csw, int expo, int prec, hipStream_t st) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (N) {
+    case 2: e = F_launch_n<2>(U, F, g, rep, st); break;
+    case 3: e = F_launch_n<3>(U, F, g, rep, st); break;
+    case 4: e = F_launch_n<4>(U, F, g, rep, st); break;
+  }
+  if (e != hipSuccess) return e;
+  const SigmaBlocks S = sigma_blocks();
+  switch (d) {
+    case 2: return finish_launch<2>(F, clov, g, S, m0, csw, expo, prec, st);
+    case 3: return finish_launch<3>(F, clov, g, S, m0, csw, expo, prec, st);
+    case 4: return finish_launch<4>(F, clov, g, S, m0, csw, expo, prec, st);
+    case 6: return finish_launch<6>(F, clov, g, S, m0, csw, expo, prec, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D>
+static hipError_t apply_launch(void *out, const void *in, const void *clov, const Geom &g, int parity, int nrhs,
+                               int prec, hipStream_t st) {
+  const dim3 grid((g.Vh + 255) / 256, 2 * nrhs);
+  if (prec == 0)
+    hipLaunchKernelGGL((k_clover_apply<D, double>), grid, dim3(256), 0, st, (cplx<double> *)out,
+                       (const cplx<double> *)in, (const cplx<double> *)clov, g, parity, nrhs);
+  else
+    hipLaunchKernelGGL((k_clover_apply<D, float>), grid, dim3(256), 0, st, (cplx<float> *)out,
+                       (const cplx<float> *)in, (const cplx<float> *)clov, g, parity, nrhs);
+  return hipGetLastError();
+}
+
+hipError_t launch_clover_apply(void *out, const void *in, const void *clov, const Geom &g, int d, int parity,
+                               int nrhs, int prec, hipStream_t st) {
+  switch (d) {
+    case 2: return apply_launch<2>(out, in, clov, g, parity, nrhs, prec, st);
+    case 3: return apply_launch<3>(out, in, clov, g, parity, nrhs, prec, st);
+    case 4: return apply_launch<4>(out, in, clov, g, parity, nrhs, prec, st);
+    case 6: return apply_launch<6>(out, in, clov, g, parity, nrhs, prec, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+bool clover_supported(int d) { return d == 2 || d == 3 || d == 4 || d == 6; }
+
+}  // namespace wd

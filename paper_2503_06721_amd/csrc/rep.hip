@@ -2,75 +2,12 @@
 // into the links that cross the boundary (Sec. 6.3.1), and the packing of
 // fields between the caller's canonical layout and the structure-of-arrays
 // layout of the kernels.
-//
-// Bases (fixed conventions of this library):
-//  * fundamental generators T^a: for each pair j < k in lexicographic order
-//    (E_jk + E_kj)/2 then (-i E_jk + i E_kj)/2; then for k = 1..N-1
-//    diag(1,..,1,-k,0,..)/sqrt(2k(k+1));
-//  * ADJ: (U_R)_ab = 2 tr(T^a U T^b U^+), evaluated from the few non-zero
-//    entries of each generator;
-//  * SYM / 2AS: orthonormal basis of symmetric / antisymmetric matrices
-//    e_(ab) (a <= b / a < b, lexicographic), e_(aa) = E_aa, e_(ab) =
-//    (E_ab +- E_ba)/sqrt 2, acting as M -> U M U^T.  Expanding
-//    tr(e_(ab)^+ U e_(cd) U^T) gives the closed forms used below:
-//      SYM, a<b, c<d:   U_ac U_bd + U_ad U_bc
-//      SYM, a<b, c=d:   sqrt2 U_ac U_bc
-//      SYM, a=b, c<d:   sqrt2 U_ac U_ad
-//      SYM, a=b, c=d:   U_ac^2
-//      2AS, a<b, c<d:   U_ac U_bd - U_ad U_bc
+// The bases of the representations are fixed in wd_rep.h.
 #include "wd_common.h"
 #include "wd_kernels.h"
+#include "wd_rep.h"
 
 namespace wd {
-
-constexpr int rep_dim(int N, int rep) {
-  return rep == 0 ? N : rep == 1 ? N * N - 1 : rep == 2 ? N * (N + 1) / 2 : N * (N - 1) / 2;
-}
-
-// Non-zero entries of fundamental generator a: returns count, fills (row, col, value).
-template <int N>
-__device__ __forceinline__ int gen_nz(int a, int (&ri)[N], int (&ci)[N], cplx<double> (&v)[N]) {
-  constexpr int noff = N * (N - 1);
-  if (a < noff) {
-    int p = a >> 1, j = 0;
-    while (p >= N - 1 - j) {
-      p -= N - 1 - j;
-      ++j;
-    }
-    const int k = j + 1 + p;
-    ri[0] = j; ci[0] = k;
-    ri[1] = k; ci[1] = j;
-    if ((a & 1) == 0) {
-      v[0] = mk(0.5, 0.0);
-      v[1] = mk(0.5, 0.0);
-    } else {
-      v[0] = mk(0.0, -0.5);
-      v[1] = mk(0.0, 0.5);
-    }
-    return 2;
-  }
-  const int kk = a - noff + 1;
-  const double nrm = 1.0 / sqrt(2.0 * kk * (kk + 1));
-  for (int i = 0; i < kk; ++i) {
-    ri[i] = i; ci[i] = i;
-    v[i] = mk(nrm, 0.0);
-  }
-  ri[kk] = kk; ci[kk] = kk;
-  v[kk] = mk(-kk * nrm, 0.0);
-  return kk + 1;
-}
-
-// Index pair (a, b) of two-index basis element A (a <= b for SYM, a < b for 2AS).
-template <int N, bool SYM>
-__device__ __forceinline__ void pair_of(int A, int &a, int &b) {
-  a = 0;
-  int rem = A;
-  while (rem >= (SYM ? N - a : N - 1 - a)) {
-    rem -= SYM ? N - a : N - 1 - a;
-    ++a;
-  }
-  b = a + rem + (SYM ? 0 : 1);
-}
 
 template <typename T>
 __device__ __forceinline__ void store_entry(void *base, size_t off, cplx<double> v, double sign, bool real) {
@@ -103,53 +40,9 @@ __global__ __launch_bounds__(256) void k_rep_links(const cplx<double> *__restric
     for (int j = 0; j < N; ++j) u[i][j] = U[(size_t)gid * N * N + i * N + j];
   const size_t base = (size_t)(par * 4 + mu) * D * D * g.stride + cb;
   const size_t es = g.stride;
-  if constexpr (REP == 0) {
-#pragma unroll
-    for (int a = 0; a < N; ++a)
-#pragma unroll
-      for (int b = 0; b < N; ++b) store_entry<T>(UR, base + (a * N + b) * es, u[a][b], sign, false);
-  } else if constexpr (REP == 1) {
-    int ra[N], ca[N], rb[N], cbi[N];
-    cplx<double> va[N], vb[N];
-    for (int A = 0; A < D; ++A) {
-      const int na = gen_nz<N>(A, ra, ca, va);
-      for (int B = 0; B < D; ++B) {
-        const int nb = gen_nz<N>(B, rb, cbi, vb);
-        // 2 tr(T^A U T^B U^+) = 2 sum T^A_ij U_jk T^B_kl conj(U_il)
-        cplx<double> s = mk(0.0, 0.0);
-        for (int p = 0; p < na; ++p)
-          for (int q = 0; q < nb; ++q) {
-            const cplx<double> w = cmul(cmul(va[p], vb[q]), u[ca[p]][rb[q]]);
-            s = cfma_conj(u[ra[p]][cbi[q]], w, s);
-          }
-        store_entry<T>(UR, base + (size_t)(A * D + B) * es, mk(2.0 * s.re, 0.0), sign, true);
-      }
-    }
-  } else {
-    constexpr bool SYM = REP == 2;
-    const double rt2 = 1.4142135623730951;
-    for (int A = 0; A < D; ++A) {
-      int a, b;
-      pair_of<N, SYM>(A, a, b);
-      for (int B = 0; B < D; ++B) {
-        int cc, dd;
-        pair_of<N, SYM>(B, cc, dd);
-        cplx<double> v;
-        if (!SYM) {
-          v = cmul(u[a][cc], u[b][dd]) - cmul(u[a][dd], u[b][cc]);
-        } else if (a < b && cc < dd) {
-          v = cmul(u[a][cc], u[b][dd]) + cmul(u[a][dd], u[b][cc]);
-        } else if (a < b) {
-          v = rt2 * cmul(u[a][cc], u[b][cc]);
-        } else if (cc < dd) {
-          v = rt2 * cmul(u[a][cc], u[a][dd]);
-        } else {
-          v = cmul(u[a][cc], u[a][cc]);
-        }
-        store_entry<T>(UR, base + (size_t)(A * D + B) * es, v, sign, false);
-      }
-    }
-  }
+  for (int A = 0; A < D; ++A)
+    for (int B = 0; B < D; ++B)
+      store_entry<T>(UR, base + (size_t)(A * D + B) * es, rep_entry<N, REP>(u, A, B), sign, REP == 1);
 }
 
 template <int N, int REP>

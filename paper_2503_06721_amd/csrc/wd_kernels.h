@@ -160,6 +160,16 @@ hipError_t launch_ms_beta(MsScalars *s, const double *rr_partial, int nblk, hipS
 hipError_t launch_ms_update_xp(void *x, void *p, const void *r, const MsScalars *s, long long fstride,
                                const FieldShape &f, int nshift, hipStream_t st);
 
+// clover.hip (one lattice per call; the caller offsets the pointers).
+// Clover field: [parity][chirality block][2d][2d][stride] complex, even sites
+// holding D_ee, odd sites D_oo^{-1}.  F: scratch of 6 d^2 complex FP64 per site.
+bool clover_supported(int d);
+hipError_t launch_clover_field(void *clov, const void *U, double *F, const Geom &g, int N, int rep, int d, double m0,
+                               double csw, int expo, int prec, hipStream_t st);
+// out = D_ee in (parity 0) or D_oo^{-1} in (parity 1); out may alias in
+hipError_t launch_clover_apply(void *out, const void *in, const void *clov, const Geom &g, int d, int parity,
+                               int nrhs, int prec, hipStream_t st);
+
 // force.hip (one lattice per call; the caller offsets the pointers)
 // U nullable: if given, the output is 2i P U instead of P
 hipError_t launch_force_links(void *P, const void *X_e, const void *X_o, const void *Y_e, const void *Y_o,

@@ -24,8 +24,8 @@ OK, EINVAL, EUNSUPPORTED, EHIP, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5
 FUND, ADJ, SYM, ASYM = 0, 1, 2, 3
 F64, F32 = 0, 1
 CG_F64, CG_MIXED = 0, 1
-FIELD_HALF_SPINOR, FIELD_LINKS = 0, 1
-OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE, OP_MSHIFT = 0, 1, 2, 3, 4, 5, 6
+FIELD_HALF_SPINOR, FIELD_LINKS, FIELD_CLOVER = 0, 1, 2
+OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE, OP_MSHIFT, OP_CLOVER = 0, 1, 2, 3, 4, 5, 6, 7
 MAX_SHIFTS = 32
 (OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
  OPT_HOP_NR_F32, OPT_TILE_TBLOCK) = 0, 1, 2, 3, 4, 5, 6, 7
@@ -84,6 +84,11 @@ _SIGS = {
     'wdirac_cg_mshift_eo': (_I, [_P, _P, _P, _P, _D, ctypes.POINTER(_D), _I, _D, _I, _P, ctypes.POINTER(CgStats),
                                  _P]),
     'wdirac_axpby': (_I, [_P, _P, _D, _P, _D, _P, _I, _I, _P]),
+    'wdirac_clover_field': (_I, [_P, _P, _P, _D, _D, _I, _I, _P, _P]),
+    'wdirac_apply_clover': (_I, [_P, _P, _P, _P, _I, _I, _I, _P]),
+    'wdirac_apply_dhat_clover': (_I, [_P, _P, _P, _P, _P, _I, _I, _I, _P, _P]),
+    'wdirac_cg_eo_clover': (_I, [_P, _P, _P, _P, _P, _P, _P, _D, _I, _I, _I, _P, ctypes.POINTER(CgStats), _P]),
+    'wdirac_stream_probe': (_I, [_P, ctypes.c_size_t, _I, _I, ctypes.POINTER(_D), _P]),
     'wdirac_last_error': (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -124,6 +129,16 @@ def _ptr(t):
 def _stream(stream):
     s = torch.cuda.current_stream() if stream is None else stream
     return s.cuda_stream
+
+
+def stream_probe(elems=1 << 24, nread=7, reps=20, stream=None):
+    """GB/s of a pure streaming kernel with nread input streams and one output
+    stream of `elems` 16-byte elements (see wdirac_stream_probe)."""
+    bufs = torch.empty((nread + 1) * elems * 16, dtype=torch.uint8, device='cuda')
+    out = _D()
+    _check(_lib.wdirac_stream_probe(_ptr(bufs), elems, nread, reps, ctypes.byref(out), _stream(stream)),
+           'stream_probe')
+    return out.value
 
 
 class Lattice:
@@ -259,6 +274,35 @@ class Lattice:
         rc = _lib.wdirac_cg_eo(self._h, _ptr(x), _ptr(b), _ptr(UR64), _ptr(UR32), float(m0), float(tol),
                                int(maxit), nrhs, mode, _ptr(ws), stats, _stream(stream))
         _check(rc, 'cg_eo', allow)
+        return rc, [s.as_dict() for s in stats]
+
+    # ------------------------------------------------------------ clover
+    def new_clover(self, prec=F64):
+        return torch.empty(self.field_bytes(FIELD_CLOVER, 1, prec), dtype=torch.uint8, device='cuda')
+
+    def clover_field(self, clov, U, m0, csw, exponential=0, prec=F64, workspace=None, stream=None):
+        """Clover blocks (D_ee on even sites, D_oo^{-1} on odd sites) from the fundamental links U."""
+        ws = workspace if workspace is not None else self.new_workspace(OP_CLOVER, 1, F64)
+        _check(_lib.wdirac_clover_field(self._h, _ptr(clov), _ptr(U), float(m0), float(csw), int(exponential),
+                                        prec, _ptr(ws), _stream(stream)), 'clover_field')
+
+    def apply_clover(self, out, inp, clov, parity, nrhs=1, prec=F64, stream=None):
+        _check(_lib.wdirac_apply_clover(self._h, _ptr(out), _ptr(inp), _ptr(clov), parity, nrhs, prec,
+                                        _stream(stream)), 'apply_clover')
+
+    def apply_dhat_clover(self, out, inp, UR, clov, dagger=0, nrhs=1, prec=F64, workspace=None, stream=None):
+        ws = workspace if workspace is not None else self.new_workspace(OP_DHAT, nrhs, prec)
+        _check(_lib.wdirac_apply_dhat_clover(self._h, _ptr(out), _ptr(inp), _ptr(UR), _ptr(clov), dagger, nrhs,
+                                             prec, _ptr(ws), _stream(stream)), 'apply_dhat_clover')
+
+    def cg_eo_clover(self, x, b, UR64, clov64, tol=1e-10, maxit=10000, nrhs=1, mode=CG_F64, UR32=None, clov32=None,
+                     workspace=None, stream=None, allow=(ENOCONV, EBREAKDOWN)):
+        """Returns (status, [stats dict per system])."""
+        ws = workspace if workspace is not None else self.new_workspace(OP_CG, nrhs, mode)
+        stats = (CgStats * self.nsys(nrhs))()
+        rc = _lib.wdirac_cg_eo_clover(self._h, _ptr(x), _ptr(b), _ptr(UR64), _ptr(UR32), _ptr(clov64), _ptr(clov32),
+                                      float(tol), int(maxit), nrhs, mode, _ptr(ws), stats, _stream(stream))
+        _check(rc, 'cg_eo_clover', allow)
         return rc, [s.as_dict() for s in stats]
 
     def new_shift_fields(self, nshift):

@@ -166,3 +166,38 @@ def test_mshift_argument_checks(W):
                                  None) == W.EUNSUPPORTED
     assert L.wdirac_workspace_bytes(hb2, W.OP_MSHIFT, 2, W.F64) == 0
     L.wdirac_destroy(hb2)
+
+
+def test_stream_probe_argument_checks(W):
+    L = W._lib
+    out = ctypes.c_double()
+    dummy = ctypes.c_void_p(0x1000)
+    assert L.wdirac_stream_probe(None, 1024, 7, 1, ctypes.byref(out), None) == W.EINVAL
+    assert L.wdirac_stream_probe(dummy, 1024, 0, 1, ctypes.byref(out), None) == W.EINVAL
+    assert L.wdirac_stream_probe(dummy, 1024, 9, 1, ctypes.byref(out), None) == W.EINVAL
+    assert L.wdirac_stream_probe(dummy, 0, 7, 1, ctypes.byref(out), None) == W.EINVAL
+    assert L.wdirac_stream_probe(dummy, 1024, 7, 0, ctypes.byref(out), None) == W.EINVAL
+    assert L.wdirac_stream_probe(dummy, 1024, 7, 1, None, None) == W.EINVAL
+
+
+def test_clover_argument_checks(W):
+    rc, h = create(W, 3, 2)   # SU(3) SYM, d = 6
+    assert rc == W.OK
+    L = W._lib
+    dummy = ctypes.c_void_p(0x1000)
+    stride = 256
+    assert L.wdirac_field_bytes(h, W.FIELD_CLOVER, 1, W.F64) == 16 * 36 * stride * 16
+    assert L.wdirac_workspace_bytes(h, W.OP_CLOVER, 1, W.F64) >= 6 * 36 * 256 * 16
+    assert L.wdirac_clover_field(h, dummy, dummy, -4.0, 1.0, 0, 0, dummy, None) == W.EINVAL     # 4 + m0 = 0
+    assert L.wdirac_clover_field(h, dummy, dummy, -0.1, 1.0, 2, 0, dummy, None) == W.EINVAL     # exponential flag
+    assert L.wdirac_clover_field(h, None, dummy, -0.1, 1.0, 0, 0, dummy, None) == W.EINVAL
+    assert L.wdirac_apply_clover(h, dummy, dummy, dummy, 2, 1, 0, None) == W.EINVAL             # parity
+    assert L.wdirac_apply_dhat_clover(h, dummy, dummy, dummy, dummy, 0, 1, 0, dummy, None) == W.EINVAL  # alias
+    st = (W.CgStats * 1)()
+    assert L.wdirac_cg_eo_clover(h, dummy, ctypes.c_void_p(0x2000), dummy, None, None, None, 1e-10, 10, 1, 0, dummy,
+                                 st, None) == W.EINVAL                                          # clov64 NULL
+    L.wdirac_destroy(h)
+    rc, h = create(W, 4, 1)   # SU(4) ADJ, d = 15: no clover
+    assert L.wdirac_field_bytes(h, W.FIELD_CLOVER, 1, W.F64) == 0
+    assert L.wdirac_clover_field(h, dummy, dummy, -0.1, 1.0, 0, 0, dummy, None) == W.EUNSUPPORTED
+    L.wdirac_destroy(h)

@@ -315,3 +315,18 @@ def test_force(W, N, rep, m):
     s.lat.force_eo(G, xg, s.URg[0], m, U=s.Ug, scale=1.0)
     expG = 2j * np.einsum('...ij,...jk->...ik', exp, s.U)
     assert rel(G.cpu().numpy(), expG) < TOL[0]
+
+
+def test_stream_probe_runs(W):
+    """The roofline's streaming probe returns a finite positive bandwidth and
+    writes the sum of its input streams."""
+    import torch
+    elems, nread = 1 << 16, 3
+    bufs = torch.zeros((nread + 1) * elems * 2, dtype=torch.float64, device='cuda')
+    for s in range(nread):
+        bufs[s * elems * 2:(s + 1) * elems * 2] = float(s + 1)
+    import ctypes
+    out = ctypes.c_double()
+    assert W._lib.wdirac_stream_probe(bufs.data_ptr(), elems, nread, 3, ctypes.byref(out), None) == W.OK
+    assert out.value > 0 and np.isfinite(out.value)
+    assert torch.all(bufs[nread * elems * 2:] == 6.0)
