@@ -21,7 +21,7 @@ Readings (the section leaves these open or prints them garbled):
       D-hat = D_ee - D_eo D_oo^{-1} D_oe
   (Sec. 5.3.3 writes this general form before specialising it); for
   c_sw = 0 it equals the plain D-hat divided by (4 + m).
-* The exponential variant (Sec. 6.1.2) replaces the diagonal blocks by
+* The exponential variant (Sec. 6.1.3) replaces the diagonal blocks by
   (4 + m) exp(c_sw / (4 + m) (i/4) sum sigma F).
 """
 import numpy as np
