@@ -1,0 +1,82 @@
+"""Pins of the oracle's HMC molecular dynamics (Sec. 5.2, 5.3): the gauge
+force against central finite differences of the plaquette action, the
+integrators' energy-error scaling (leapfrog and second-order Omelyan, both
+O(eps^2) per trajectory as in the paper's table of integrators), exact
+reversibility, and unitarity of the evolved links (no GPU)."""
+import numpy as np
+import pytest
+
+from oracle import dirac as D
+from oracle import hmc as H
+from oracle import reps as R
+from paper_2503_06721_amd import synth
+
+APBC = (-1, 1, 1, 1)
+
+
+def momenta(dims, N, seed):
+    w = np.random.default_rng(seed).normal(size=tuple(dims) + (4, N * N - 1))
+    return R.algebra_to_matrix(w, N)
+
+
+def test_plaquette_of_unit_links_and_action():
+    U = synth.unit_links((2, 2, 2, 2), 3)
+    assert np.allclose(H.plaquettes(U), 1.0)
+    assert H.gauge_action(U, 5.0) == 0.0
+
+
+@pytest.mark.parametrize('N', [2, 3])
+def test_gauge_force_finite_differences(N):
+    dims = (2, 4, 2, 2)
+    U = synth.expH_links(dims, N, 0.5, 81)
+    beta = 2.3
+    Fm = H.gauge_force(U, beta)
+    g = np.einsum('kab,...ba->...k', R.fund_generators(N), Fm).real * 2.0   # components (tr T^a T^b = 1/2)
+    h = 1e-5
+    for k in range(3):
+        w = synth.algebra_directions(dims, N, 3400 + k)
+        w /= np.linalg.norm(w)
+        X = R.algebra_to_matrix(w, N)
+        fd = (H.gauge_action(H.exp_i(h * X) @ U, beta) - H.gauge_action(H.exp_i(-h * X) @ U, beta)) / (2 * h)
+        assert abs(fd - float(np.sum(w * g))) <= 1e-7 * abs(fd) + 1e-9
+
+
+def setup(dims, N, rep, seed, m=0.2, beta=2.0):
+    U = synth.expH_links(dims, N, 0.4, seed)
+    UR = R.represent(U, rep)
+    d = UR.shape[-1]
+    eta = synth.gaussian_spinor((int(np.prod(dims)) // 2, 4, d), seed + 1)
+    phi = D.Dhat_dag(eta, UR, m, APBC, dims)
+    return U, H.Action(beta, m, rep, APBC, phi), momenta(dims, N, seed + 2)
+
+
+@pytest.mark.parametrize('integrator', ['leapfrog', 'omelyan2'])
+def test_energy_error_scaling(integrator):
+    """|dH| ~ eps^2 for both second-order integrators: halving eps divides it by ~4."""
+    U, act, pi = setup((2, 2, 2, 2), 2, 'ADJ', 82)
+    tau = 0.5
+    dH = []
+    for n in (4, 8, 16):
+        _, _, H0, H1 = H.trajectory(U, pi, act, tau / n, n, integrator)
+        dH.append(abs(H1 - H0))
+    r1, r2 = dH[0] / dH[1], dH[1] / dH[2]
+    assert 3.3 < r1 < 4.8 and 3.6 < r2 < 4.4, dH
+
+
+def test_reversibility_and_unitarity():
+    U, act, pi = setup((2, 2, 2, 2), 3, 'FUND', 83)
+    U1, pi1, H0, H1 = H.trajectory(U, pi, act, 0.1, 5, 'omelyan2')
+    U2, pi2, H2, H3 = H.trajectory(U1, -pi1, act, 0.1, 5, 'omelyan2')
+    assert np.abs(U2 - U).max() < 1e-10
+    assert np.abs(pi2 + pi).max() < 1e-9
+    assert abs(H3 - H0) < 1e-9
+    I = np.eye(3)
+    assert np.abs(np.einsum('...ab,...cb->...ac', U1, np.conj(U1)) - I).max() < 1e-13
+
+
+def test_pure_gauge_limit():
+    """Without fermions the force and action reduce to the gauge parts."""
+    U, act, pi = setup((2, 2, 2, 2), 2, 'FUND', 84)
+    pg = H.Action(act.beta, act.m, act.rep, APBC, act.phi, with_fermions=False)
+    assert np.allclose(pg.force(U), H.gauge_force(U, act.beta))
+    assert pg.value(U) == H.gauge_action(U, act.beta)
