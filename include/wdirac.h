@@ -71,7 +71,8 @@ typedef enum {
   WDIRAC_OP_DOT = 4,
   WDIRAC_OP_TUNE = 5,
   WDIRAC_OP_MSHIFT = 6,  /* `nrhs` argument = number of shifts (1..32) */
-  WDIRAC_OP_CLOVER = 7   /* construction of a clover field */
+  WDIRAC_OP_CLOVER = 7,  /* construction of a clover field */
+  WDIRAC_OP_GAUGE = 8    /* gauge action and kinetic-energy reductions */
 } wdirac_op;
 
 typedef struct {
@@ -287,7 +288,7 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
                  double m0, double tol, int maxit, int nrhs, int mode, void *workspace,
                  wdirac_cg_stats *stats, void *stream);
 
-/* Clover improvement (Sec. 6.1.2).  Builds the site-diagonal blocks of the
+/* Clover improvement (Sec. 6.1.2, exponential form Sec. 6.1.3).  Builds the site-diagonal blocks of the
  * clover-improved operator from the fundamental links U (canonical complex128
  * [T][X][Y][Z][4][N][N], lattice after lattice for a batch):
  *   D_ee + D_oo = (4 + m0) + csw (i/4) sum_{mu,nu} sigma_mu,nu F_mu,nu(x),
@@ -387,6 +388,62 @@ int wdirac_force_eo(const wdirac_ctx *ctx, void *out, const void *x_e, const voi
  * Errors: EINVAL (null pointer, nread outside [1, 8], elems outside
  * [1, 2^31], reps outside [1, 1000]), EHIP. */
 int wdirac_stream_probe(void *bufs, size_t elems, int nread, int reps, double *gbps, void *stream);
+
+/* out = gamma_5 in on nrhs packed half spinors (gamma_5 = diag(1, 1, -1, -1)
+ * in the basis of Sec. 2.2); out may alias in.  Errors: EINVAL, EHIP. */
+int wdirac_gamma5(const wdirac_ctx *ctx, void *out, const void *in, int nrhs, int prec, void *stream);
+
+/* Twisted-mass operators of the even-odd preconditioned Hasenbusch
+ * factorisation (Sec. 6.2.1): out = W_sign(mu) in = (Q-hat + i sign mu) in,
+ * Q-hat = gamma_5 D-hat with the D-hat of wdirac_apply_dhat (one factor of
+ * 4 + m0 absorbed), sign = +1 or -1.  W_- = W_+^+ and W_+ W_- = D-hat^+ D-hat
+ * + mu^2, so the twisted-mass monomial is a shifted solve
+ * (wdirac_cg_mshift_eo with shift mu^2).  workspace: wdirac_workspace_bytes(
+ * ctx, WDIRAC_OP_DHAT, nrhs, prec).  out must not alias in.  Errors: EINVAL,
+ * EHIP. */
+int wdirac_apply_W(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, double m0, double mu, int sign,
+                   int nrhs, int prec, void *workspace, void *stream);
+
+/* Link derivative of a bilinear in the hopping term: for fixed full-lattice
+ * fields X = (X_e, X_o) and Y = (Y_e, Y_o) (packed FP64 half fields), the
+ * force of the functional 2 Re(Y^+ H X), in the convention of
+ * wdirac_force_eo (P, or G = 2i P U when U is given; scale, accumulate).
+ * wdirac_force_eo is the case X = (x, D_oe x), Y = (D-hat x, D_eo^+ D-hat x);
+ * other monomials (Hasenbusch, Sec. 6.2.1) combine it with other fields.
+ * Synchronises.  Errors: EINVAL, EHIP. */
+int wdirac_force_bilinear_eo(const wdirac_ctx *ctx, void *out, const void *X_e, const void *X_o, const void *Y_e,
+                             const void *Y_o, const void *UR64, const void *U, double scale, int accumulate,
+                             void *stream);
+
+/* HMC molecular-dynamics pieces (Sec. 5.2, 5.3) on the canonical fundamental
+ * links U and momenta pi, both complex128 [T][X][Y][Z][4][N][N] (lattice
+ * after lattice for a batch); momenta are Hermitian traceless matrices
+ * pi = pi^a T^a (generators of wdirac_create's basis), the molecular dynamics
+ * is dU/dtau = i pi U, dpi/dtau = -F, H = sum tr(pi^2) + S.
+ *
+ * wdirac_gauge_force: F (+)= scale * sum_a (dS_g/dw^a) T^a for the Wilson
+ *   plaquette action S_g = beta sum_x sum_{mu<nu} (1 - Re tr P_mu,nu(x)/N)
+ *   and the variation U -> exp(i w^a T^a) U (the convention of
+ *   wdirac_force_eo's P, so fermion and gauge forces add).  F must not alias
+ *   U.  Asynchronous.
+ * wdirac_gauge_action: S[l] = S_g of lattice l (host array of nlat values).
+ *   workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_GAUGE, 1, WDIRAC_F64).
+ *   Synchronises.
+ * wdirac_link_update: U <- exp(i eps pi) U on every link (exponential by
+ *   scaling and squaring of the Taylor series, FP64).  Asynchronous.
+ * wdirac_kinetic: K[l] = sum over the links of lattice l of tr(pi^2).
+ *   workspace as for the gauge action.  Synchronises.
+ * wdirac_algebra_from_components: pi = sum_a w^a T^a from the components w
+ *   (device float64 [T][X][Y][Z][4][N^2-1]; e.g. Gaussian draws for the
+ *   momentum refresh).  Asynchronous.
+ * Errors: EINVAL, EHIP. */
+int wdirac_gauge_force(const wdirac_ctx *ctx, void *F, const void *U, double beta, double scale, int accumulate,
+                       void *stream);
+int wdirac_gauge_action(const wdirac_ctx *ctx, double *S, const void *U, double beta, void *workspace,
+                        void *stream);
+int wdirac_link_update(const wdirac_ctx *ctx, void *U, const void *pi, double eps, void *stream);
+int wdirac_kinetic(const wdirac_ctx *ctx, double *K, const void *pi, void *workspace, void *stream);
+int wdirac_algebra_from_components(const wdirac_ctx *ctx, void *pi, const double *w, void *stream);
 
 /* Thread-local description of the last error (empty string if none). */
 const char *wdirac_last_error(void);

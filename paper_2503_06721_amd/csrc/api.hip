@@ -374,6 +374,11 @@ size_t wdirac_field_bytes(const wdirac_ctx *ctx, int kind, int nrhs, int prec) {
 
 size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec) {
   if (!ctx) return 0;
+  if (op == WDIRAC_OP_GAUGE) {   // reductions over links and sites
+    int mx = 0;
+    for (int l = 0; l < ctx->nlat; ++l) mx = std::max(mx, wd::kinetic_blocks(ctx->g[l]));
+    return align256((size_t)mx * sizeof(double)) + align256(sizeof(double));
+  }
   if (op == WDIRAC_OP_CLOVER) {   // scratch of the clover-field construction
     if (!wd::clover_supported(ctx->d)) return 0;
     int mx = 0;
@@ -1026,6 +1031,150 @@ int wdirac_axpby(const wdirac_ctx *ctx, void *out, double a, const void *x, doub
   WD_TRY(check_nrhs(ctx, nrhs));
   WD_TRY(check_prec(prec));
   WD_HIP(wd::launch_lincomb(out, a, x, b, y, shape(ctx, nrhs), prec, S(stream)));
+  return WDIRAC_OK;
+}
+
+// ------------------------------------------------------------- HMC pieces
+static size_t links_offset(const wdirac_ctx *c, int l) { return (size_t)c->vpre[l] * 4 * c->N * c->N * 16; }
+
+int wdirac_gauge_force(const wdirac_ctx *ctx, void *F, const void *U, double beta, double scale, int accumulate,
+                       void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(F, "F"));
+  WD_TRY(check_ptr(U, "U"));
+  if (accumulate != 0 && accumulate != 1) return fail(WDIRAC_EINVAL, "accumulate must be 0 or 1");
+  if (F == U) return fail(WDIRAC_EINVAL, "F must not alias U");
+  for (int l = 0; l < ctx->nlat; ++l)
+    WD_HIP(wd::launch_gauge_force(static_cast<const char *>(U) + links_offset(ctx, l),
+                                  static_cast<char *>(F) + links_offset(ctx, l), ctx->g[l], ctx->N, beta, scale,
+                                  accumulate, S(stream)));
+  return WDIRAC_OK;
+}
+
+// Sum of the block partials (FP64, compensated) to the host.
+static int reduce_to_host(double *out, const double *partial, int nblk, double *dtmp, hipStream_t st) {
+  WD_HIP(wd::launch_finalize_sum(dtmp, partial, nblk, wd::uniform_counts(nblk), 1, 1, st));
+  WD_HIP(hipMemcpyAsync(out, dtmp, sizeof(double), hipMemcpyDeviceToHost, st));
+  WD_HIP(hipStreamSynchronize(st));
+  return WDIRAC_OK;
+}
+
+int wdirac_gauge_action(const wdirac_ctx *ctx, double *S_out, const void *U, double beta, void *workspace,
+                        void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(S_out, "S"));
+  WD_TRY(check_ptr(U, "U"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  Carver cv{static_cast<char *>(workspace)};
+  int mx = 0;
+  for (int l = 0; l < ctx->nlat; ++l) mx = std::max(mx, wd::kinetic_blocks(ctx->g[l]));
+  double *part = static_cast<double *>(cv.take((size_t)mx * sizeof(double)));
+  double *dtmp = static_cast<double *>(cv.take(sizeof(double)));
+  for (int l = 0; l < ctx->nlat; ++l) {
+    const int nb = wd::plaquette_blocks(ctx->g[l]);
+    WD_HIP(wd::launch_plaquette_partial(static_cast<const char *>(U) + links_offset(ctx, l), part, ctx->g[l],
+                                        ctx->N, S(stream)));
+    double plaq = 0.0;
+    WD_TRY(reduce_to_host(&plaq, part, nb, dtmp, S(stream)));
+    S_out[l] = beta * (6.0 * 2.0 * ctx->g[l].Vh - plaq);
+  }
+  return WDIRAC_OK;
+}
+
+int wdirac_link_update(const wdirac_ctx *ctx, void *U, const void *pi, double eps, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(U, "U"));
+  WD_TRY(check_ptr(pi, "pi"));
+  if (U == pi) return fail(WDIRAC_EINVAL, "pi must not alias U");
+  if (!std::isfinite(eps)) return fail(WDIRAC_EINVAL, "eps must be finite");
+  for (int l = 0; l < ctx->nlat; ++l)
+    WD_HIP(wd::launch_link_update(static_cast<char *>(U) + links_offset(ctx, l),
+                                  static_cast<const char *>(pi) + links_offset(ctx, l), ctx->g[l], ctx->N, eps,
+                                  S(stream)));
+  return WDIRAC_OK;
+}
+
+int wdirac_kinetic(const wdirac_ctx *ctx, double *K, const void *pi, void *workspace, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(K, "K"));
+  WD_TRY(check_ptr(pi, "pi"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  Carver cv{static_cast<char *>(workspace)};
+  int mx = 0;
+  for (int l = 0; l < ctx->nlat; ++l) mx = std::max(mx, wd::kinetic_blocks(ctx->g[l]));
+  double *part = static_cast<double *>(cv.take((size_t)mx * sizeof(double)));
+  double *dtmp = static_cast<double *>(cv.take(sizeof(double)));
+  for (int l = 0; l < ctx->nlat; ++l) {
+    WD_HIP(wd::launch_kinetic_partial(static_cast<const char *>(pi) + links_offset(ctx, l), part, ctx->g[l], ctx->N,
+                                      S(stream)));
+    WD_TRY(reduce_to_host(&K[l], part, wd::kinetic_blocks(ctx->g[l]), dtmp, S(stream)));
+  }
+  return WDIRAC_OK;
+}
+
+int wdirac_algebra_from_components(const wdirac_ctx *ctx, void *pi, const double *w, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(pi, "pi"));
+  WD_TRY(check_ptr(w, "w"));
+  const int na = ctx->N * ctx->N - 1;
+  for (int l = 0; l < ctx->nlat; ++l)
+    WD_HIP(wd::launch_algebra(static_cast<char *>(pi) + links_offset(ctx, l), w + (size_t)ctx->vpre[l] * 4 * na,
+                              ctx->g[l], ctx->N, S(stream)));
+  return WDIRAC_OK;
+}
+
+// ---------------------------------------------- twisted mass, Hasenbusch
+int wdirac_gamma5(const wdirac_ctx *ctx, void *out, const void *in, int nrhs, int prec, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(in, "in"));
+  WD_TRY(check_nrhs(ctx, nrhs));
+  WD_TRY(check_prec(prec));
+  WD_HIP(wd::launch_gamma5_axpy(out, in, 0.0, nullptr, shape(ctx, nrhs), prec, S(stream)));
+  return WDIRAC_OK;
+}
+
+int wdirac_apply_W(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, double m0, double mu, int sign,
+                   int nrhs, int prec, void *workspace, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(in, "in"));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  WD_TRY(check_nrhs(ctx, nrhs));
+  WD_TRY(check_prec(prec));
+  if (sign != 1 && sign != -1) return fail(WDIRAC_EINVAL, "sign must be +1 or -1");
+  if (!std::isfinite(mu)) return fail(WDIRAC_EINVAL, "mu must be finite");
+  if (out == in) return fail(WDIRAC_EINVAL, "out must not alias in");
+  const hipStream_t st = S(stream);
+  WD_TRY(dhat(ctx, out, in, UR, m0, 0, nrhs, prec, workspace, nullptr, st));
+  WD_HIP(wd::launch_gamma5_axpy(out, out, sign * mu, in, shape(ctx, nrhs), prec, st));
+  return WDIRAC_OK;
+}
+
+int wdirac_force_bilinear_eo(const wdirac_ctx *ctx, void *P, const void *X_e, const void *X_o, const void *Y_e,
+                             const void *Y_o, const void *UR64, const void *U, double scale, int accumulate,
+                             void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(P, "out"));
+  WD_TRY(check_ptr(X_e, "X_e"));
+  WD_TRY(check_ptr(X_o, "X_o"));
+  WD_TRY(check_ptr(Y_e, "Y_e"));
+  WD_TRY(check_ptr(Y_o, "Y_o"));
+  WD_TRY(check_ptr(UR64, "UR64"));
+  if (accumulate != 0 && accumulate != 1) return fail(WDIRAC_EINVAL, "accumulate must be 0 or 1");
+  const hipStream_t st = S(stream);
+  const size_t el = ctx->real ? 8 : 16;
+  for (int l = 0; l < ctx->nlat; ++l) {
+    const size_t so = (size_t)4 * ctx->d * ctx->spre[l] * 16;
+    const size_t po = (size_t)ctx->vpre[l] * 4 * ctx->N * ctx->N * 16;
+    auto at = [so](const void *p) { return static_cast<const void *>(static_cast<const char *>(p) + so); };
+    WD_HIP(wd::launch_force_links(static_cast<char *>(P) + po, at(X_e), at(X_o), at(Y_e), at(Y_o),
+                                  static_cast<const char *>(UR64) + (size_t)8 * ctx->d * ctx->d * ctx->spre[l] * el,
+                                  U ? static_cast<const char *>(U) + po : nullptr, ctx->g[l], ctx->N, ctx->rep, scale,
+                                  accumulate, st));
+  }
+  WD_HIP(hipStreamSynchronize(st));
   return WDIRAC_OK;
 }
 

@@ -429,6 +429,36 @@ hipError_t launch_accum_x(void *x64, void *x32, const FieldShape &f, hipStream_t
   return hipGetLastError();
 }
 
+// out = gamma_5 x + i c y (y nullable), gamma_5 = diag(1, 1, -1, -1) on the
+// spin index (components spin * d + colour); out may alias x or y.
+template <typename T>
+__global__ __launch_bounds__(BT) void k_gamma5_axpy(void *out, const void *x, double c, const void *y,
+                                                    FieldShape f) {
+  const int i = blockIdx.x * BT + threadIdx.x, sy = blockIdx.y;
+  if (i >= f.vh[sy]) return;
+  const size_t base = (size_t)f.off[sy] + i;
+  const int d = f.ncomp / 4;
+  for (int comp = 0; comp < f.ncomp; ++comp) {
+    const size_t o = base + (size_t)comp * f.stride[sy];
+    cplx<double> v = up(ld<T>(x, o));
+    if (comp >= 2 * d) v = mk(-v.re, -v.im);
+    if (y) {
+      const cplx<double> w = up(ld<T>(y, o));
+      v.re = fma(-c, w.im, v.re);
+      v.im = fma(c, w.re, v.im);
+    }
+    st<T>(out, o, v);
+  }
+}
+
+hipError_t launch_gamma5_axpy(void *out, const void *x, double c, const void *y, const FieldShape &f, int prec,
+                              hipStream_t st) {
+  dim3 grid(blas_nblocks(f), f.nsys);
+  if (prec == 0) hipLaunchKernelGGL(k_gamma5_axpy<double>, grid, dim3(BT), 0, st, out, x, c, y, f);
+  else hipLaunchKernelGGL(k_gamma5_axpy<float>, grid, dim3(BT), 0, st, out, x, c, y, f);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ multi-shift CG
 // Recursion of the base system (smallest shift sigma0) plus, for every shift
 // k with delta_k = sigma_k - sigma0 >= 0, the collinear shifted residual

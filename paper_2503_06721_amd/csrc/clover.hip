@@ -1,4 +1,4 @@
-// Clover improvement (Sec. 6.1.2): the site-diagonal blocks
+// Clover improvement (Sec. 6.1.2; exponential form Sec. 6.1.3): the site-diagonal blocks
 //   D_ee + D_oo = (4 + m) + c_sw (i/4) sum_{mu,nu} sigma_mu,nu F_mu,nu
 // (or, exponential form, (4 + m) exp(c_sw/(4+m) (i/4) sum sigma F)), with
 // F_mu,nu = (Q_mu,nu - Q_mu,nu^+)/8 and Q the sum of the four clover leaves of
@@ -136,8 +136,6 @@ __global__ __launch_bounds__(256) void k_clover_F(const cplx<double> *__restrict
 struct SigmaBlocks {
   cplx<double> v[6][2][2][2];
 };
-
-constexpr int MAXB = 2 * 6;   // largest chirality block (d_R <= 6)
 
 // Gauss-Jordan inverse with partial pivoting of the n x n matrix a (destroyed).
 template <int NB>

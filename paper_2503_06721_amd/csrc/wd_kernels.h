@@ -90,6 +90,9 @@ hipError_t launch_finalize_sum(double *out, const double *partial, int prow, con
 // partial[s][blk] = Re sum conj(a) b, partial[nsys + s][blk] = Im sum conj(a) b
 hipError_t launch_dot_partial(double *partial, const void *a, const void *b, const FieldShape &f, int prec,
                               hipStream_t st);
+// out = gamma_5 x + i c y (y nullable); out may alias x or y
+hipError_t launch_gamma5_axpy(void *out, const void *x, double c, const void *y, const FieldShape &f, int prec,
+                              hipStream_t st);
 // convert between precisions: out (prec_out) = in (prec_in)
 hipError_t launch_convert(void *out, int prec_out, const void *in, int prec_in, const FieldShape &f,
                           hipStream_t st);
@@ -169,6 +172,16 @@ hipError_t launch_clover_field(void *clov, const void *U, double *F, const Geom 
 // out = D_ee in (parity 0) or D_oo^{-1} in (parity 1); out may alias in
 hipError_t launch_clover_apply(void *out, const void *in, const void *clov, const Geom &g, int d, int parity,
                                int nrhs, int prec, hipStream_t st);
+
+// hmc.hip (one lattice per call; canonical fundamental links and momenta)
+hipError_t launch_gauge_force(const void *U, void *F, const Geom &g, int N, double beta, double scale,
+                              int accumulate, hipStream_t st);
+int plaquette_blocks(const Geom &g);
+hipError_t launch_plaquette_partial(const void *U, double *partial, const Geom &g, int N, hipStream_t st);
+hipError_t launch_link_update(void *U, const void *pi, const Geom &g, int N, double eps, hipStream_t st);
+int kinetic_blocks(const Geom &g);
+hipError_t launch_kinetic_partial(const void *pi, double *partial, const Geom &g, int N, hipStream_t st);
+hipError_t launch_algebra(void *pi, const double *w, const Geom &g, int N, hipStream_t st);
 
 // force.hip (one lattice per call; the caller offsets the pointers)
 // U nullable: if given, the output is 2i P U instead of P

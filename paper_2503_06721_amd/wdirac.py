@@ -25,7 +25,7 @@ FUND, ADJ, SYM, ASYM = 0, 1, 2, 3
 F64, F32 = 0, 1
 CG_F64, CG_MIXED = 0, 1
 FIELD_HALF_SPINOR, FIELD_LINKS, FIELD_CLOVER = 0, 1, 2
-OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE, OP_MSHIFT, OP_CLOVER = 0, 1, 2, 3, 4, 5, 6, 7
+OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE, OP_MSHIFT, OP_CLOVER, OP_GAUGE = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MAX_SHIFTS = 32
 (OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
  OPT_HOP_NR_F32, OPT_TILE_TBLOCK) = 0, 1, 2, 3, 4, 5, 6, 7
@@ -84,6 +84,14 @@ _SIGS = {
     'wdirac_cg_mshift_eo': (_I, [_P, _P, _P, _P, _D, ctypes.POINTER(_D), _I, _D, _I, _P, ctypes.POINTER(CgStats),
                                  _P]),
     'wdirac_axpby': (_I, [_P, _P, _D, _P, _D, _P, _I, _I, _P]),
+    'wdirac_gauge_force': (_I, [_P, _P, _P, _D, _D, _I, _P]),
+    'wdirac_gauge_action': (_I, [_P, ctypes.POINTER(_D), _P, _D, _P, _P]),
+    'wdirac_link_update': (_I, [_P, _P, _P, _D, _P]),
+    'wdirac_kinetic': (_I, [_P, ctypes.POINTER(_D), _P, _P, _P]),
+    'wdirac_algebra_from_components': (_I, [_P, _P, _P, _P]),
+    'wdirac_gamma5': (_I, [_P, _P, _P, _I, _I, _P]),
+    'wdirac_apply_W': (_I, [_P, _P, _P, _P, _D, _D, _I, _I, _I, _P, _P]),
+    'wdirac_force_bilinear_eo': (_I, [_P, _P, _P, _P, _P, _P, _P, _P, _D, _I, _P]),
     'wdirac_clover_field': (_I, [_P, _P, _P, _D, _D, _I, _I, _P, _P]),
     'wdirac_apply_clover': (_I, [_P, _P, _P, _P, _I, _I, _I, _P]),
     'wdirac_apply_dhat_clover': (_I, [_P, _P, _P, _P, _P, _I, _I, _I, _P, _P]),
@@ -275,6 +283,46 @@ class Lattice:
                                int(maxit), nrhs, mode, _ptr(ws), stats, _stream(stream))
         _check(rc, 'cg_eo', allow)
         return rc, [s.as_dict() for s in stats]
+
+    # ------------------------------------------------------------ HMC pieces
+    def gauge_force(self, F, U, beta, scale=1.0, accumulate=0, stream=None):
+        _check(_lib.wdirac_gauge_force(self._h, _ptr(F), _ptr(U), float(beta), float(scale), int(accumulate),
+                                       _stream(stream)), 'gauge_force')
+
+    def gauge_action(self, U, beta, workspace=None, stream=None):
+        ws = workspace if workspace is not None else self.new_workspace(OP_GAUGE)
+        out = (_D * self.nlat)()
+        _check(_lib.wdirac_gauge_action(self._h, out, _ptr(U), float(beta), _ptr(ws), _stream(stream)),
+               'gauge_action')
+        return list(out) if self.batch else out[0]
+
+    def link_update(self, U, pi, eps, stream=None):
+        _check(_lib.wdirac_link_update(self._h, _ptr(U), _ptr(pi), float(eps), _stream(stream)), 'link_update')
+
+    def kinetic(self, pi, workspace=None, stream=None):
+        ws = workspace if workspace is not None else self.new_workspace(OP_GAUGE)
+        out = (_D * self.nlat)()
+        _check(_lib.wdirac_kinetic(self._h, out, _ptr(pi), _ptr(ws), _stream(stream)), 'kinetic')
+        return list(out) if self.batch else out[0]
+
+    def algebra_from_components(self, pi, w, stream=None):
+        _check(_lib.wdirac_algebra_from_components(self._h, _ptr(pi), _ptr(w), _stream(stream)),
+               'algebra_from_components')
+
+    # ------------------------------------------------ twisted mass, Hasenbusch
+    def gamma5(self, out, inp, nrhs=1, prec=F64, stream=None):
+        _check(_lib.wdirac_gamma5(self._h, _ptr(out), _ptr(inp), nrhs, prec, _stream(stream)), 'gamma5')
+
+    def apply_W(self, out, inp, UR, m0, mu, sign=1, nrhs=1, prec=F64, workspace=None, stream=None):
+        """out = (Q-hat + i sign mu) inp."""
+        ws = workspace if workspace is not None else self.new_workspace(OP_DHAT, nrhs, prec)
+        _check(_lib.wdirac_apply_W(self._h, _ptr(out), _ptr(inp), _ptr(UR), float(m0), float(mu), int(sign), nrhs,
+                                   prec, _ptr(ws), _stream(stream)), 'apply_W')
+
+    def force_bilinear_eo(self, out, X_e, X_o, Y_e, Y_o, UR64, U=None, scale=1.0, accumulate=0, stream=None):
+        _check(_lib.wdirac_force_bilinear_eo(self._h, _ptr(out), _ptr(X_e), _ptr(X_o), _ptr(Y_e), _ptr(Y_o),
+                                             _ptr(UR64), _ptr(U), float(scale), int(accumulate), _stream(stream)),
+               'force_bilinear_eo')
 
     # ------------------------------------------------------------ clover
     def new_clover(self, prec=F64):

@@ -1,4 +1,4 @@
-"""Clover-improved operator (Sec. 6.1.2, regular and exponential) against the
+"""Clover-improved operator (Sec. 6.1.2, and the exponential form of Sec. 6.1.3) against the
 oracle: the diagonal blocks D_ee and D_oo^{-1} built on the device from the
 fundamental links, the even-odd D-hat = D_ee - D_eo D_oo^{-1} D_oe and its
 adjoint, and the CG on D-hat^+ D-hat in FP64 and mixed precision."""
