@@ -15,8 +15,9 @@ mixed precision, and the CPU oracle timed on a bounded sample.  Once per run,
 after the timed steps: 12 point sources on SU(3) SYM 48x24^3 solved as one
 batched call and as 12 single calls (FP64 and mixed), FP64 against mixed CG on
 SU(4) 2AS 96x48^3, the three-lattice SU(3) SYM batch against separate solves,
-the force on SU(2) ADJ 32x16^3, and on the benchmark lattice a 12-shift
-multi-shift solve and the clover-improved CG.
+the force on SU(2) ADJ 32x16^3, on the benchmark lattice a 12-shift
+multi-shift solve and the clover-improved CG, and one HMC trajectory on
+SU(2) ADJ 32x16^3.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--hops H] [--no-cpu] [--no-multi]
 """
@@ -341,6 +342,33 @@ def rhmc_and_clover(W, torch, synth, name='su3_fund_32x32x32x32'):
     return {'workload': name, 'multi_shift_time_to_1e-10': ms, 'clover_cg_time_to_1e-10': cl}
 
 
+def hmc_trajectory(W, torch, synth, name='su2_adj_32x16x16x16'):
+    """One HMC trajectory (second-order Omelyan, tau = 0.5 in 5 steps, Wilson
+    plaquette beta = 2.2 plus the two-flavour adjoint pseudofermion) on SU(2)
+    ADJ 32x16^3: wall time, CG iterations, dH."""
+    from paper_2503_06721_amd.hmc import HMC
+    cfg = synth.CONFIGS[name]
+    dims, m0 = cfg['dims'], cfg['m0']
+    lat = W.Lattice(cfg['N'], cfg['rep'], dims, cfg['bc'])
+    U = torch.from_numpy(synth.links_for(cfg)).cuda()
+    hmc = HMC(lat, 2.2, m0, tol=1e-10)
+    lat.rep_links(hmc.UR, U)
+    lat.autotune(hmc.UR, W.F64, 1)
+    g = torch.Generator(device='cuda')
+    g.manual_seed(cfg['seed'] + 31)
+    w = torch.randn(tuple(dims) + (4, cfg['N'] ** 2 - 1), dtype=torch.float64, device='cuda', generator=g)
+    eta = torch.randn((1,) + tuple(dims) + (4, lat.d), dtype=torch.complex128, device='cuda', generator=g)
+    pi, phi = hmc.refresh(U, w, lat.pack_half(eta, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H0, H1 = hmc.trajectory(U, pi, phi, 0.1, 5, 'omelyan2')
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    log(f'[bench] HMC trajectory: {secs:.3f} s, dH {H1 - H0:.3e}, CG iterations {hmc.cg_iters}')
+    return {'workload': name, 'integrator': 'omelyan2', 'tau': 0.5, 'steps': 5, 'beta': 2.2,
+            'seconds': round(secs, 4), 'dH': H1 - H0, 'cg_iterations': hmc.cg_iters}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -500,6 +528,8 @@ def main():
         out['force'] = force_timing(W, torch, synth)
         torch.cuda.empty_cache()
         out['rhmc_and_clover'] = rhmc_and_clover(W, torch, synth)
+        torch.cuda.empty_cache()
+        out['hmc_trajectory'] = hmc_trajectory(W, torch, synth)
     if not args.no_cpu:
         log('[bench] timing the CPU oracle on a bounded sample')
         cb = cpu_baseline(cfg, U, psi[0])

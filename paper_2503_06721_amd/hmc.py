@@ -1,0 +1,91 @@
+"""Hybrid Monte Carlo molecular dynamics over libwdirac (Sec. 5.2, 5.3).
+
+Conventions as in the library's HMC entry points: momenta pi are Hermitian
+traceless matrices in the canonical link layout, dU/dtau = i pi U,
+dpi/dtau = -F (F the force matrix of the gauge and fermion actions),
+H = sum tr(pi^2) + S_g + S_f with the Wilson plaquette action S_g and the
+even-odd pseudofermion action S_f = phi^+ (D-hat^+ D-hat)^{-1} phi.
+Integrators: leapfrog (PQP) and second-order Omelyan (PQPQP).  Every
+computation runs in the library's kernels; this module only sequences calls.
+"""
+import torch
+
+from . import wdirac as W
+
+OMELYAN_LAMBDA = 0.1931833275037836
+
+
+class HMC:
+    def __init__(self, lat, beta, m0, tol=1e-12, maxit=20000, with_fermions=True):
+        self.lat, self.beta, self.m0 = lat, float(beta), float(m0)
+        self.tol, self.maxit, self.with_fermions = tol, maxit, with_fermions
+        self.UR = lat.new_links(W.F64)
+        self.x = lat.new_half()
+        self.ws_cg = lat.new_workspace(W.OP_CG, 1, W.CG_F64)
+        self.ws_force = lat.new_workspace(W.OP_FORCE)
+        self.ws_gauge = lat.new_workspace(W.OP_GAUGE)
+        self.cg_iters = 0
+
+    def _solve(self, U, phi):
+        self.lat.rep_links(self.UR, U, W.F64)
+        self.x.zero_()
+        rc, st = self.lat.cg_eo(self.x, phi, self.UR, self.m0, tol=self.tol, maxit=self.maxit, workspace=self.ws_cg)
+        if rc != W.OK:
+            raise W.WdiracError(rc, 'HMC solve')
+        self.cg_iters += st[0]['iters']
+
+    def action(self, U, phi):
+        s = self.lat.gauge_action(U, self.beta, workspace=self.ws_gauge)
+        if self.with_fermions:
+            self._solve(U, phi)
+            s += self.lat.dot(phi, self.x)[0].real
+        return s
+
+    def kinetic(self, pi):
+        return self.lat.kinetic(pi, workspace=self.ws_gauge)
+
+    def hamiltonian(self, U, pi, phi):
+        return self.kinetic(pi) + self.action(U, phi)
+
+    def kick(self, pi, U, phi, c):
+        """pi <- pi - c F(U)."""
+        self.lat.gauge_force(pi, U, self.beta, scale=-c, accumulate=1)
+        if self.with_fermions:
+            self._solve(U, phi)
+            self.lat.force_eo(pi, self.x, self.UR, self.m0, scale=-c, accumulate=1, workspace=self.ws_force)
+
+    def drift(self, U, pi, c):
+        """U <- exp(i c pi) U."""
+        self.lat.link_update(U, pi, c)
+
+    def leapfrog(self, U, pi, phi, eps, nsteps):
+        self.kick(pi, U, phi, 0.5 * eps)
+        for n in range(nsteps):
+            self.drift(U, pi, eps)
+            self.kick(pi, U, phi, eps if n < nsteps - 1 else 0.5 * eps)
+
+    def omelyan2(self, U, pi, phi, eps, nsteps, lam=OMELYAN_LAMBDA):
+        for _ in range(nsteps):
+            self.kick(pi, U, phi, lam * eps)
+            self.drift(U, pi, 0.5 * eps)
+            self.kick(pi, U, phi, (1.0 - 2.0 * lam) * eps)
+            self.drift(U, pi, 0.5 * eps)
+            self.kick(pi, U, phi, lam * eps)
+
+    def trajectory(self, U, pi, phi, eps, nsteps, integrator='omelyan2'):
+        """Evolves U and pi in place; returns (H0, H1)."""
+        H0 = self.hamiltonian(U, pi, phi)
+        (self.omelyan2 if integrator == 'omelyan2' else self.leapfrog)(U, pi, phi, eps, nsteps)
+        return H0, self.hamiltonian(U, pi, phi)
+
+    def refresh(self, U, w_momenta, eta):
+        """pi = w^a T^a from Gaussian components w (device float64
+        [..., 4, N^2-1]); phi = D-hat^+ eta from a Gaussian even field eta."""
+        lat = self.lat
+        pi = torch.empty(U.shape, dtype=torch.complex128, device=U.device)
+        lat.algebra_from_components(pi, w_momenta.contiguous())
+        phi = lat.new_half()
+        if self.with_fermions:
+            lat.rep_links(self.UR, U, W.F64)
+            lat.apply_dhat(phi, eta, self.UR, self.m0, dagger=1)
+        return pi, phi
