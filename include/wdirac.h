@@ -137,6 +137,13 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                      Site-parallel form: 4 (4 rhs across
  *                                      the lanes of a wavefront) when it is 4
  *                                      and divides nrhs, else 1
+ *   WDIRAC_OPT_CG_GRAPH                1 (default): the CG iterations between
+ *                                      host checks are captured once per
+ *                                      solve into a HIP graph and replayed
+ *                                      on a stream of the library's own
+ *                                      (after the caller's stream has
+ *                                      drained); 0: direct launches on the
+ *                                      caller's stream
  * Options set here apply to every nrhs except those that wdirac_autotune()
  * has tuned.  Errors: EINVAL (unknown option or value), EUNSUPPORTED. */
 typedef enum {
@@ -147,7 +154,8 @@ typedef enum {
   WDIRAC_OPT_MIXED_DELTA = 4,
   WDIRAC_OPT_HOP_NR_F64 = 5,
   WDIRAC_OPT_HOP_NR_F32 = 6,
-  WDIRAC_OPT_TILE_TBLOCK = 7
+  WDIRAC_OPT_TILE_TBLOCK = 7,
+  WDIRAC_OPT_CG_GRAPH = 8
 } wdirac_option;
 int wdirac_set_option(wdirac_ctx *ctx, int option, double value);
 

@@ -30,6 +30,8 @@ struct wdirac_ctx {
   int tblock;           // t-blocked tile order (0 = lexicographic)
   int cg_check_every;   // CG iterations between host convergence checks
   double mixed_delta;   // reliable-update trigger ||r|| < delta max||r||
+  int cg_graph;         // replay the CG iterations between checks as a HIP graph
+  mutable hipStream_t own = nullptr;   // the library's stream for graph capture (created on first use)
 };
 
 namespace {
@@ -339,6 +341,7 @@ int wdirac_create_batch(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *ge
   c->tblock = 0;
   c->cg_check_every = 4;
   c->mixed_delta = 0.1;
+  c->cg_graph = 1;
   *ctx = c;
   return WDIRAC_OK;
 }
@@ -348,6 +351,7 @@ int wdirac_create(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *geom) {
 }
 
 int wdirac_destroy(wdirac_ctx *ctx) {
+  if (ctx && ctx->own) (void)hipStreamDestroy(ctx->own);
   delete ctx;
   return WDIRAC_OK;
 }
@@ -430,6 +434,10 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
     case WDIRAC_OPT_MIXED_DELTA:
       if (!(value > 0.0 && value < 1.0)) return fail(WDIRAC_EINVAL, "delta must be in (0, 1)");
       ctx->mixed_delta = value;
+      return WDIRAC_OK;
+    case WDIRAC_OPT_CG_GRAPH:
+      if (value != 0.0 && value != 1.0) return fail(WDIRAC_EINVAL, "CG graph option must be 0 or 1");
+      ctx->cg_graph = (int)value;
       return WDIRAC_OK;
     case WDIRAC_OPT_TILE_TBLOCK:
       if (!(value >= 0 && value <= 64)) return fail(WDIRAC_EINVAL, "t-block must be in [0, 64]");
@@ -738,7 +746,17 @@ static int cg_impl(const wdirac_ctx *ctx, void *x, const void *b, const void *UR
   if (mode == WDIRAC_CG_MIXED) WD_TRY(check_ptr(UR32, "UR32"));
   if (!(tol > 0.0) || maxit < 0) return fail(WDIRAC_EINVAL, "tol must be > 0 and maxit >= 0");
   if (x == b) return fail(WDIRAC_EINVAL, "x and b must not alias");
-  const hipStream_t st = S(stream);
+  hipStream_t st = S(stream);
+  if (ctx->cg_graph) {
+    // the iterations between host checks are captured once and replayed as
+    // a graph; capture needs a stream of the library's own (the caller's may
+    // be the null stream), ordered after the caller's work
+    if (!ctx->own && hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) ctx->own = nullptr;
+    if (ctx->own) {
+      WD_HIP(hipStreamSynchronize(st));
+      st = ctx->own;
+    }
+  }
   const bool mixed = mode == WDIRAC_CG_MIXED;
   CgWork w = carve_cg(ctx, nrhs, mode, workspace);
   const wd::FieldShape f = shape(ctx, nrhs);
@@ -776,6 +794,8 @@ static int cg_impl(const wdirac_ctx *ctx, void *x, const void *b, const void *UR
   const int check = ctx->cg_check_every;
   int rc = WDIRAC_OK;
   int launched = 0;   // iterations launched since start
+  bool use_graph = ctx->cg_graph && st == ctx->own;
+  hipGraphExec_t exec = nullptr;
   for (;;) {
     WD_HIP(hipMemcpyAsync(hs.data(), w.sc, ns * sizeof(wd::CgScalars), hipMemcpyDeviceToHost, st));
     WD_HIP(hipStreamSynchronize(st));
@@ -803,19 +823,40 @@ static int cg_impl(const wdirac_ctx *ctx, void *x, const void *b, const void *UR
       break;
     }
     const int nit = std::min(check, std::max(1, maxit - max_iters));
-    for (int it = 0; it < nit; ++it) {
-      wd::Counts cnt{};
-      int prow = 0;
-      WD_TRY(dhat(ctx, u, p, UR, m0, 0, nrhs, prec, t, w.P1, st, &cnt, &prow, clov));
-      WD_HIP(wd::launch_cg_alpha(w.sc, w.P1, prow, cnt, ns, st));
-      WD_TRY(dhat(ctx, q, u, UR, m0, 1, nrhs, prec, v, nullptr, st, nullptr, nullptr, clov));
-      WD_HIP(wd::launch_cg_update_xr(xi, prec, r, p, q, w.sc, w.P2, f, prec, st));
-      WD_HIP(wd::launch_cg_beta(w.sc, w.P2, nbb, ns, delta, st));
-      WD_HIP(wd::launch_cg_update_p(p, r, w.sc, f, prec, st));
-      hop_count += 4;
-      ++launched;
+    auto launch_iters = [&](int n) -> int {
+      for (int it = 0; it < n; ++it) {
+        wd::Counts cnt{};
+        int prow = 0;
+        WD_TRY(dhat(ctx, u, p, UR, m0, 0, nrhs, prec, t, w.P1, st, &cnt, &prow, clov));
+        WD_HIP(wd::launch_cg_alpha(w.sc, w.P1, prow, cnt, ns, st));
+        WD_TRY(dhat(ctx, q, u, UR, m0, 1, nrhs, prec, v, nullptr, st, nullptr, nullptr, clov));
+        WD_HIP(wd::launch_cg_update_xr(xi, prec, r, p, q, w.sc, w.P2, f, prec, st));
+        WD_HIP(wd::launch_cg_beta(w.sc, w.P2, nbb, ns, delta, st));
+        WD_HIP(wd::launch_cg_update_p(p, r, w.sc, f, prec, st));
+      }
+      return WDIRAC_OK;
+    };
+    if (use_graph && nit == check && !exec) {
+      hipGraph_t graph = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        const int crc = launch_iters(nit);
+        const hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (crc != WDIRAC_OK || ce != hipSuccess || !graph ||
+            hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+          exec = nullptr;
+        if (graph) (void)hipGraphDestroy(graph);
+      }
+      if (!exec) {
+        use_graph = false;   // capture unavailable: launch directly from now on
+        g_err.clear();
+      }
     }
+    if (use_graph && nit == check && exec) WD_HIP(hipGraphLaunch(exec, st));
+    else WD_TRY(launch_iters(nit));
+    hop_count += 4 * nit;
+    launched += nit;
   }
+  if (exec) (void)hipGraphExecDestroy(exec);
   if (mixed) WD_HIP(wd::launch_accum_x(x, w.x32, f, st));
   // final FP64 true residual of the returned x
   WD_TRY(true_residual());

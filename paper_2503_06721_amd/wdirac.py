@@ -28,7 +28,7 @@ FIELD_HALF_SPINOR, FIELD_LINKS, FIELD_CLOVER = 0, 1, 2
 OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE, OP_MSHIFT, OP_CLOVER, OP_GAUGE = 0, 1, 2, 3, 4, 5, 6, 7, 8
 MAX_SHIFTS = 32
 (OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
- OPT_HOP_NR_F32, OPT_TILE_TBLOCK) = 0, 1, 2, 3, 4, 5, 6, 7
+ OPT_HOP_NR_F32, OPT_TILE_TBLOCK, OPT_CG_GRAPH) = 0, 1, 2, 3, 4, 5, 6, 7, 8
 HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR = 0, 1, 2
 REP_CODES = {'FUND': FUND, 'ADJ': ADJ, 'SYM': SYM, '2AS': ASYM}
 STATUS_NAMES = {OK: 'OK', EINVAL: 'EINVAL', EUNSUPPORTED: 'EUNSUPPORTED', EHIP: 'EHIP',

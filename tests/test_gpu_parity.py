@@ -330,3 +330,23 @@ def test_stream_probe_runs(W):
     assert W._lib.wdirac_stream_probe(bufs.data_ptr(), elems, nread, 3, ctypes.byref(out), None) == W.OK
     assert out.value > 0 and np.isfinite(out.value)
     assert torch.all(bufs[nread * elems * 2:] == 6.0)
+
+
+@pytest.mark.parametrize('mode', [0, 1])
+def test_cg_graph_replay_matches_direct_launches(W, mode):
+    """CG iterations replayed from a captured HIP graph (many replays per
+    solve, host checks in between) give bit-identical solutions to direct
+    launches: the same kernels in the same order."""
+    import torch
+    s = Setup(3, 'FUND', (8, 6, 8, 6), seed=290, links='expH')
+    psi = s.spinor(291, 2)
+    b = s.to_gpu_half(psi, 0)
+    out = {}
+    for graph in (0, 1):
+        s.lat.set_option(W.OPT_CG_GRAPH, graph)
+        x = s.lat.new_half(2)
+        rc, st = s.lat.cg_eo(x, b, s.URg[0], -0.3, tol=1e-10, maxit=5000, nrhs=2, mode=mode, UR32=s.URg[1])
+        assert rc == W.OK
+        out[graph] = (x.clone(), [r['iters'] for r in st])
+    assert out[0][1] == out[1][1]
+    assert torch.equal(out[0][0], out[1][0])
