@@ -131,9 +131,11 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                      b divides T and tiles do not straddle
  *                                      (t, x) rows)
  *   WDIRAC_OPT_HOP_NR_F64 / _F32       right-hand sides sharing each link load
- *                                      (1..4).  Colour-split form: the
+ *                                      (1..6).  Colour-split form: the
  *                                      largest divisor of nrhs not above it
- *                                      whose LDS staging fits is used.
+ *                                      that the form supports is used (1..4
+ *                                      within the LDS budget; 6 in the
+ *                                      unpaired form for d_R <= 4).
  *                                      Site-parallel form: 4 (4 rhs across
  *                                      the lanes of a wavefront) when it is 4
  *                                      and divides nrhs, else 1

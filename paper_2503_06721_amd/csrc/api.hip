@@ -184,14 +184,14 @@ MsWork carve_ms(const wdirac_ctx *c, int nshift, void *ws) {
   return w;
 }
 
-// Right-hand sides per colour-split block: the largest divisor of nrhs not
-// above the preference whose LDS staging fits.
+// Right-hand sides per colour-split block: the largest supported divisor of
+// nrhs not above the preference.
 int effective_nr(const wdirac_ctx *c, int pref, int nrhs, int prec, int variant) {
   // site-parallel form: 4 right-hand sides across the lanes of a wavefront, or 1
   if (variant == wd::HOP_SITE) return (pref >= 4 && nrhs % 4 == 0) ? 4 : 1;
-  int nr = std::min(pref, wd::hop_max_nr(c->d, prec, variant));
-  while (nr > 1 && nrhs % nr) --nr;
-  return std::max(nr, 1);
+  for (int nr = std::min(pref, 6); nr > 1; --nr)
+    if (nrhs % nr == 0 && wd::hop_nr_supported(c->d, prec, variant, nr)) return nr;
+  return 1;
 }
 
 // One hopping-term launch over every lattice of the context.  counts/prow
@@ -445,7 +445,7 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
       return WDIRAC_OK;
     case WDIRAC_OPT_HOP_NR_F64:
     case WDIRAC_OPT_HOP_NR_F32:
-      if (!(value >= 1 && value <= 4)) return fail(WDIRAC_EINVAL, "right-hand sides per block must be in [1, 4]");
+      if (!(value >= 1 && value <= 6)) return fail(WDIRAC_EINVAL, "right-hand sides per block must be in [1, 6]");
       ctx->hop_nr[option == WDIRAC_OPT_HOP_NR_F64 ? 0 : 1] = (int)value;
       return WDIRAC_OK;
   }
@@ -473,7 +473,7 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
     if (tb && (ctx->nlat > 1 || ctx->g[0].T % tb)) continue;
     for (int remap = 0; remap < 2; ++remap) {
       for (int v = wd::HOP_COLOUR; v <= wd::HOP_COLOUR_PAIR; ++v)
-        for (int nr = 1; nr <= 4; ++nr)
+        for (int nr : {1, 2, 3, 4, 6})
           if (effective_nr(ctx, nr, nrhs, prec, v) == nr) cands.push_back({v, nr, remap, tb});
       if (wd::hop_variant_ok(ctx->d, wd::HOP_SITE)) {
         cands.push_back({wd::HOP_SITE, 1, remap, tb});

@@ -392,7 +392,7 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
 // spills a little.)
 constexpr int cs_waves(int D, bool dbl, int NR) {
   const int w = dbl ? (D <= 3 ? 4 : D <= 8 ? 3 : 2) : (D <= 4 ? 6 : D <= 6 ? 5 : D <= 10 ? 4 : 3);
-  const int cut = NR >= 3 ? 2 : NR == 2 ? 1 : 0;
+  const int cut = NR >= 6 ? 3 : NR >= 3 ? 2 : NR == 2 ? 1 : 0;
   return w - cut > 1 ? w - cut : 1;
 }
 constexpr int sp_waves(int D, bool dbl) { return dbl ? 2 : (D <= 2 ? 4 : D <= 4 ? 2 : 3); }
@@ -403,6 +403,12 @@ constexpr int LDS_BUDGET = 160 * 1024 - 256;
 template <int D, typename T, int NR, bool PAIR>
 constexpr bool cs_fits() {
   return (PAIR ? 4 : 2) * NR * 2 * D * 64 * (int)sizeof(cplx<T>) <= LDS_BUDGET;
+}
+// Six right-hand sides per block: colour form (unpaired) with d_R <= 4 only;
+// beyond that the accumulators no longer fit in registers.
+template <int D, typename T>
+constexpr bool cs6_ok() {
+  return D <= 4 && cs_fits<D, T, 6, false>();
 }
 
 // Tile bookkeeping of a launch with tiles of ts sites: per-lattice tile
@@ -437,7 +443,7 @@ template <int D, bool REAL, typename T, bool DAG, int NR, bool NTL>
 static hipError_t launch_cs2(const HopArgs &a, int pair, hipStream_t st) {
   constexpr int W = cs_waves(D, sizeof(T) == 8, NR);
   dim3 grid(a.ntiles * a.ngroups);
-  if constexpr (cs_fits<D, T, NR, true>()) {
+  if constexpr (NR <= 4 && cs_fits<D, T, NR, true>()) {
     if (pair) {
       hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, true, NTL, W>), grid, dim3(64 * D), 0, st, a);
       return hipGetLastError();
@@ -484,6 +490,9 @@ static hipError_t launch_typed(const HopArgs &a0, int nrhs, int variant, int nr,
       return hipErrorInvalidValue;
     }
   }
+  if (nr == 6 && nrhs % 6 == 0 && !pair) {
+    if constexpr (cs6_ok<D, T>()) return launch_cs<D, REAL, T, DAG, 6>(a0, nrhs, pair, st, counts, prow);
+  }
   if (nr == 4 && nrhs % 4 == 0) {
     if constexpr (cs_fits<D, T, 4, false>()) return launch_cs<D, REAL, T, DAG, 4>(a0, nrhs, pair, st, counts, prow);
   }
@@ -526,12 +535,12 @@ hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, i
   return hipErrorInvalidValue;
 }
 
-int hop_max_nr(int d, int prec, int variant) {
-  // largest NR in {1..4} whose LDS staging fits, as in cs_fits
+bool hop_nr_supported(int d, int prec, int variant, int nr) {
+  // as cs_fits and cs6_ok
   const int cb = prec == 0 ? 16 : 8, nbuf = variant == HOP_COLOUR_PAIR ? 4 : 2;
-  int nr = 4;
-  while (nr > 1 && nbuf * nr * 2 * d * 64 * cb > LDS_BUDGET) --nr;
-  return nr;
+  if (nr < 1 || nr > 6 || nr == 5) return false;
+  if (nr == 6 && (variant != HOP_COLOUR || d > 4)) return false;
+  return nbuf * nr * 2 * d * 64 * cb <= LDS_BUDGET;
 }
 
 bool hop_variant_ok(int d, int variant) {

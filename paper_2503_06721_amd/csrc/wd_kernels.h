@@ -59,7 +59,10 @@ struct Counts {
 // *prow their row length.
 hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant, int nr,
                       hipStream_t st, Counts *counts, int *prow);
-int hop_max_nr(int d, int prec, int variant);
+// Whether the colour-split form of the given variant takes nr right-hand
+// sides per block (nr in 1..4, or 6 for the unpaired form with d_R <= 4)
+// within the LDS budget.
+bool hop_nr_supported(int d, int prec, int variant, int nr);
 bool hop_variant_ok(int d, int variant);
 
 // rep.hip (one lattice per call; the caller offsets the pointers)

@@ -96,9 +96,9 @@ def test_dslash_eo(W, N, rep, dims):
 @pytest.mark.parametrize('N,rep', [(3, 'FUND'), (3, 'SYM'), (2, 'ADJ'), (4, 'FUND'), (4, '2AS')])
 def test_dslash_rhs_groups(W, N, rep):
     """Several right-hand sides sharing each link load (1..4 per block in the
-    colour-split forms, 4 across the lanes of a wavefront in the site-parallel
-    form), with a ragged tile tail; every rhs must equal its own single-rhs
-    hop."""
+    colour-split forms, 6 in the unpaired form for d_R <= 4, 4 across the
+    lanes of a wavefront in the site-parallel form), with a ragged tile tail;
+    every rhs must equal its own single-rhs hop."""
     s = Setup(N, rep, (4, 6, 4, 6), seed=250 + N)
     for nrhs in (4, 6, 12):
         psi = s.spinor(251 + nrhs, nrhs)
@@ -106,7 +106,7 @@ def test_dslash_rhs_groups(W, N, rep):
         for prec in (0, 1):
             for variant in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR, W.HOP_SITE):
                 s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, variant)
-                for nr in (1, 2, 3, 4):
+                for nr in (1, 2, 3, 4, 6):
                     s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, nr)
                     log(f'rhs groups N={N} rep={rep} nrhs={nrhs} prec={prec} variant={variant} nr={nr}')
                     for p, dagger in ((0, 0), (1, 1)):
