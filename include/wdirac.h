@@ -72,7 +72,8 @@ typedef enum {
   WDIRAC_OP_TUNE = 5,
   WDIRAC_OP_MSHIFT = 6,  /* `nrhs` argument = number of shifts (1..32) */
   WDIRAC_OP_CLOVER = 7,  /* construction of a clover field */
-  WDIRAC_OP_GAUGE = 8    /* gauge action and kinetic-energy reductions */
+  WDIRAC_OP_GAUGE = 8,   /* gauge action and kinetic-energy reductions */
+  WDIRAC_OP_CLOVER_FORCE = 9 /* clover force and clover determinant */
 } wdirac_op;
 
 typedef struct {
@@ -340,6 +341,41 @@ int wdirac_apply_dhat_clover(const wdirac_ctx *ctx, void *out, const void *in, c
 int wdirac_cg_eo_clover(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32,
                         const void *clov64, const void *clov32, double tol, int maxit, int nrhs, int mode,
                         void *workspace, wdirac_cg_stats *stats, void *stream);
+
+/* Fermion force of S_f = phi^+ (D-hat^+ D-hat)^{-1} phi with the clover
+ * D-hat = D_ee - D_eo D_oo^{-1} D_oe (regular clover, Sec. 6.1.2, or the
+ * exponential form, Sec. 6.1.3), given x = (D-hat^+ D-hat)^{-1} phi (packed
+ * FP64 even half).  With X = (x, D_oo^{-1} D_oe x), Y = (D-hat x,
+ * D_oo^{-1} D_eo^+ D-hat x):
+ *   dS = 2 Re(Y^+ dH X) - 2 Re sum_x tr[dM(x) X(x) Y(x)^+],
+ * the hopping part as in wdirac_force_bilinear_eo and the variation of the
+ * diagonal blocks M through the clover leaves (exponential form: through the
+ * derivative of the exponential).  Link variation, output P or G = 2i P U
+ * (gradient = 1), scale and accumulate as in wdirac_force_eo.  U: canonical
+ * fundamental links; clov64: the FP64 clover field of wdirac_clover_field for
+ * the same U, m0, csw and exponential.  workspace: wdirac_workspace_bytes(ctx,
+ * WDIRAC_OP_CLOVER_FORCE, 1, WDIRAC_F64).  Synchronises.  Errors: EINVAL,
+ * EUNSUPPORTED (d_R not in {2, 3, 4, 6}), EHIP. */
+int wdirac_force_eo_clover(const wdirac_ctx *ctx, void *out, const void *x_e, const void *UR64, const void *U,
+                           const void *clov64, double m0, double csw, int exponential, double scale, int gradient,
+                           int accumulate, void *workspace, void *stream);
+
+/* Force of the odd-block determinant term S_det = -2 sum_{x odd} log|det
+ * D_oo(x)| that completes the two-flavour determinant, det D = det D_oo
+ * det D-hat (Sec. 5.3.3): dS_det = -2 Re sum_{x odd} tr[dM(x) D_oo(x)^{-1}].
+ * For the exponential form det D_oo is constant and the result vanishes up to
+ * rounding.  Arguments as in wdirac_force_eo_clover (no spinors).
+ * Synchronises.  Errors: EINVAL, EUNSUPPORTED, EHIP. */
+int wdirac_force_clover_logdet(const wdirac_ctx *ctx, void *out, const void *U, const void *clov64, double m0,
+                               double csw, int exponential, double scale, int gradient, int accumulate,
+                               void *workspace, void *stream);
+
+/* logdet[l] (host array of one value per lattice) = sum over the odd sites
+ * of lattice l of log|det D_oo(x)|, from the FP64 clover field (which stores
+ * D_oo^{-1} there); S_det = -2 logdet.  workspace: wdirac_workspace_bytes(ctx,
+ * WDIRAC_OP_CLOVER_FORCE, 1, WDIRAC_F64).  Synchronises.  Errors: EINVAL,
+ * EUNSUPPORTED, EHIP. */
+int wdirac_clover_logdet(const wdirac_ctx *ctx, double *logdet, const void *clov64, void *workspace, void *stream);
 
 /* Multi-shift conjugate gradient (the multi-shift inversion of the RHMC,
  * Sec. 5.3.2): x_k = (D-hat^+ D-hat + sigma_k)^{-1} b for the nshift shifts

@@ -282,6 +282,39 @@ int pack(const wdirac_ctx *c, void *packed, void *canon, int parity, int nrhs, i
   return WDIRAC_OK;
 }
 
+// Workspace of the clover force: the three FP64 half fields of the
+// pseudofermion force (whole batch), then the per-lattice scratch of the
+// largest lattice: F (6 d^2 V), K (12 d^2 V), leaf matrices (24 N^2 V) complex
+// FP64, and the log-det partial sums.
+struct CloverForceWs {
+  void *z_o, *y_e, *w_o;
+  double *F, *K, *G, *part, *dtmp;
+  size_t bytes;
+};
+
+CloverForceWs carve_clover_force(const wdirac_ctx *c, void *base) {
+  Carver cv{static_cast<char *>(base)};
+  CloverForceWs w;
+  const size_t h = half_bytes(c, 1, WDIRAC_F64);
+  w.z_o = cv.take(h);
+  w.y_e = cv.take(h);
+  w.w_o = cv.take(h);
+  size_t V = 0;
+  int nb = 0;
+  for (int l = 0; l < c->nlat; ++l) {
+    V = std::max(V, 2 * (size_t)c->g[l].Vh);
+    nb = std::max(nb, wd::clover_logdet_blocks(c->g[l]));
+  }
+  const size_t d2 = (size_t)c->d * c->d, n2 = (size_t)c->N * c->N;
+  w.F = static_cast<double *>(cv.take(6 * d2 * V * 16));
+  w.K = static_cast<double *>(cv.take(12 * d2 * V * 16));
+  w.G = static_cast<double *>(cv.take(24 * n2 * V * 16));
+  w.part = static_cast<double *>(cv.take((size_t)nb * sizeof(double)));
+  w.dtmp = static_cast<double *>(cv.take(sizeof(double)));
+  w.bytes = cv.off;
+  return w;
+}
+
 }  // namespace
 
 extern "C" {
@@ -388,6 +421,10 @@ size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec)
     int mx = 0;
     for (int l = 0; l < ctx->nlat; ++l) mx = std::max(mx, ctx->g[l].Vh);
     return align256((size_t)6 * ctx->d * ctx->d * 2 * mx * 16);
+  }
+  if (op == WDIRAC_OP_CLOVER_FORCE) {
+    if (!wd::clover_supported(ctx->d)) return 0;
+    return carve_clover_force(ctx, nullptr).bytes;
   }
   if (op == WDIRAC_OP_MSHIFT) {   // nrhs = number of shifts
     if (nrhs < 1 || nrhs > wd::MAXSHIFT || prec != WDIRAC_F64 || ctx->nlat != 1) return 0;
@@ -1245,6 +1282,92 @@ int wdirac_force_eo(const wdirac_ctx *ctx, void *P, const void *x_e, const void 
                                   accumulate, st));
   }
   WD_HIP(hipStreamSynchronize(st));
+  return WDIRAC_OK;
+}
+
+// ------------------------------------------------------------ clover force
+static size_t clover_offset(const wdirac_ctx *c, int l) { return (size_t)16 * c->d * c->d * c->spre[l] * 2 * 8; }
+
+static int clover_force_checks(const wdirac_ctx *ctx, const void *P, const void *U, const void *clov64, double m0,
+                               double csw, int exponential, int gradient, int accumulate, const void *workspace) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(P, "out"));
+  WD_TRY(check_ptr(U, "U"));
+  WD_TRY(check_ptr(clov64, "clov64"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  if (!wd::clover_supported(ctx->d)) return fail(WDIRAC_EUNSUPPORTED, "clover term available for d_R in {2,3,4,6}");
+  if (!std::isfinite(m0) || !std::isfinite(csw) || 4.0 + m0 == 0.0)
+    return fail(WDIRAC_EINVAL, "m0 and csw must be finite and 4 + m0 != 0");
+  if (exponential != 0 && exponential != 1) return fail(WDIRAC_EINVAL, "exponential must be 0 or 1");
+  if (gradient != 0 && gradient != 1) return fail(WDIRAC_EINVAL, "gradient must be 0 or 1");
+  if (accumulate != 0 && accumulate != 1) return fail(WDIRAC_EINVAL, "accumulate must be 0 or 1");
+  return WDIRAC_OK;
+}
+
+int wdirac_force_eo_clover(const wdirac_ctx *ctx, void *P, const void *x_e, const void *UR64, const void *U,
+                           const void *clov64, double m0, double csw, int exponential, double scale, int gradient,
+                           int accumulate, void *workspace, void *stream) {
+  WD_TRY(clover_force_checks(ctx, P, U, clov64, m0, csw, exponential, gradient, accumulate, workspace));
+  WD_TRY(check_ptr(x_e, "x_e"));
+  WD_TRY(check_ptr(UR64, "UR64"));
+  const hipStream_t st = S(stream);
+  const CloverForceWs w = carve_clover_force(ctx, workspace);
+  // z_o = D_oo^{-1} D_oe x;  y_e = D_ee x - D_eo z_o = D-hat x;  w_o = D_oo^{-1} D_eo^+ y_e
+  WD_TRY(hop(ctx, w.z_o, x_e, UR64, 1, 0, 1, 0.0, nullptr, 1.0, WDIRAC_F64, nullptr, st));
+  WD_TRY(clover_apply(ctx, w.z_o, w.z_o, clov64, 1, 1, WDIRAC_F64, st));
+  WD_TRY(clover_apply(ctx, w.y_e, x_e, clov64, 0, 1, WDIRAC_F64, st));
+  WD_TRY(hop(ctx, w.y_e, w.z_o, UR64, 0, 0, 1, 1.0, w.y_e, -1.0, WDIRAC_F64, nullptr, st));
+  WD_TRY(hop(ctx, w.w_o, w.y_e, UR64, 1, 1, 1, 0.0, nullptr, 1.0, WDIRAC_F64, nullptr, st));
+  WD_TRY(clover_apply(ctx, w.w_o, w.w_o, clov64, 1, 1, WDIRAC_F64, st));
+  const size_t el = ctx->real ? 8 : 16;
+  for (int l = 0; l < ctx->nlat; ++l) {
+    const size_t so = (size_t)4 * ctx->d * ctx->spre[l] * 16;
+    const size_t po = links_offset(ctx, l);
+    auto at = [so](const void *p) { return static_cast<const void *>(static_cast<const char *>(p) + so); };
+    const char *Ul = static_cast<const char *>(U) + po;
+    WD_HIP(wd::launch_force_links(static_cast<char *>(P) + po, at(x_e), at(w.z_o), at(w.y_e), at(w.w_o),
+                                  static_cast<const char *>(UR64) + (size_t)8 * ctx->d * ctx->d * ctx->spre[l] * el,
+                                  gradient ? Ul : nullptr, ctx->g[l], ctx->N, ctx->rep, scale, accumulate, st));
+    WD_HIP(wd::launch_clover_force(static_cast<char *>(P) + po, at(x_e), at(w.z_o), at(w.y_e), at(w.w_o), Ul,
+                                   static_cast<const char *>(clov64) + clover_offset(ctx, l), w.F, w.K, w.G,
+                                   ctx->g[l], ctx->N, ctx->rep, m0, csw, exponential, 0.0, csw / 8.0 * scale,
+                                   gradient, 1, st));
+  }
+  WD_HIP(hipStreamSynchronize(st));
+  return WDIRAC_OK;
+}
+
+int wdirac_force_clover_logdet(const wdirac_ctx *ctx, void *P, const void *U, const void *clov64, double m0,
+                               double csw, int exponential, double scale, int gradient, int accumulate,
+                               void *workspace, void *stream) {
+  WD_TRY(clover_force_checks(ctx, P, U, clov64, m0, csw, exponential, gradient, accumulate, workspace));
+  const hipStream_t st = S(stream);
+  const CloverForceWs w = carve_clover_force(ctx, workspace);
+  for (int l = 0; l < ctx->nlat; ++l) {
+    const size_t po = links_offset(ctx, l);
+    WD_HIP(wd::launch_clover_force(static_cast<char *>(P) + po, nullptr, nullptr, nullptr, nullptr,
+                                   static_cast<const char *>(U) + po,
+                                   static_cast<const char *>(clov64) + clover_offset(ctx, l), w.F, w.K, w.G,
+                                   ctx->g[l], ctx->N, ctx->rep, m0, csw, exponential, 1.0, csw / 8.0 * scale,
+                                   gradient, accumulate, st));
+  }
+  WD_HIP(hipStreamSynchronize(st));
+  return WDIRAC_OK;
+}
+
+int wdirac_clover_logdet(const wdirac_ctx *ctx, double *logdet, const void *clov64, void *workspace, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(logdet, "logdet"));
+  WD_TRY(check_ptr(clov64, "clov64"));
+  WD_TRY(check_ptr(workspace, "workspace"));
+  if (!wd::clover_supported(ctx->d)) return fail(WDIRAC_EUNSUPPORTED, "clover term available for d_R in {2,3,4,6}");
+  const hipStream_t st = S(stream);
+  const CloverForceWs w = carve_clover_force(ctx, workspace);
+  for (int l = 0; l < ctx->nlat; ++l) {
+    WD_HIP(wd::launch_clover_logdet(static_cast<const char *>(clov64) + clover_offset(ctx, l), w.part, ctx->g[l],
+                                    ctx->d, st));
+    WD_TRY(reduce_to_host(&logdet[l], w.part, wd::clover_logdet_blocks(ctx->g[l]), w.dtmp, st));
+  }
   return WDIRAC_OK;
 }
 

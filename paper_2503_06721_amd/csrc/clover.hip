@@ -417,4 +417,448 @@ hipError_t launch_clover_apply(void *out, const void *in, const void *clov, cons
 
 bool clover_supported(int d) { return d == 2 || d == 3 || d == 4 || d == 6; }
 
+// ------------------------------------------------------------ clover force
+// Link derivative of a functional whose variation is
+//   -2 Re sum_x tr[dM(x) Omega(x)]      (M: the site-diagonal blocks),
+// the form of both clover contributions to the HMC force: the pseudofermion
+// action with Omega = X Y^+ (X = (x, D_oo^{-1} D_oe x), Y = (D-hat x,
+// D_oo^{-1} D_eo^+ D-hat x)) and S_det = -2 sum_{x odd} log|det D_oo| with
+// Omega = D_oo^{-1} on the odd sites.
+//
+// With C = (i c_sw/2) sum_p sigma_p (x) F_p (p = mu < nu) and dM = dC
+// (exponential form: tr[dM Omega] = tr[dC Omega'], Omega' = L(A, Omega), the
+// Frechet derivative of exp at A = C/(4+m), which is its own adjoint for the
+// trace pairing), the variation is (c_sw/8) sum_x sum_p Im tr[dQ_p K_p] with
+//   K_p = Lam_p + Lam_p^+,  (Lam_p)_ba = sum_st (sigma_p)_st Omega'_(t b),(s a).
+// A leaf l of Q_p varied from the left, R(l) -> exp(i th^b T^b_R) R(l),
+// changes Im tr[R(l) K_p] by th^b Re tr[T^b_R R(l) K_p]; its matrix
+// g = sum_b Re tr[T^b_R R(l) K_p] T^b is formed in the fundamental by the
+// representation pull-back.  A link U inside the leaf, l = B U rest, moves it
+// by the generator B T B^+ (l = B' U^+ rest: by -(B'U^+) T (B'U^+)^+), so the
+// link's force receives +-B^+ g B with B the fundamental path from the
+// leaf's corner up to (forward) or through (dagger) the link.
+//
+// Pipeline (one lattice): insertion K per (site, chirality) -> leaf matrices
+// g per (plane, site) -> gather over the 24 (leaf, corner) pairs holding each
+// link.  Scratch: K [2][6][d][d][V], g [6][4][N][N][V] complex FP64.
+
+// e = exp(a) (discarded) and om <- L(a, om) = d/dt exp(a + t om) at t = 0:
+// scaling by 2^-s, Horner for exp(a') and its derivative along om / 2^s,
+// then s squarings (e, l) <- (e e, l e + e l).  a is destroyed.
+template <int NB>
+__device__ void expm_frechet(cplx<double> (&a)[NB][NB], cplx<double> (&om)[NB][NB]) {
+  double nrm = 0.0;
+  for (int j = 0; j < NB; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < NB; ++i) s += sqrt(a[i][j].re * a[i][j].re + a[i][j].im * a[i][j].im);
+    nrm = s > nrm ? s : nrm;
+  }
+  int sq = 0;
+  while (nrm > 0.25 && sq < 60) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double sc = ldexp(1.0, -sq);
+  for (int i = 0; i < NB; ++i)
+    for (int j = 0; j < NB; ++j) {
+      a[i][j] = sc * a[i][j];
+      om[i][j] = sc * om[i][j];
+    }
+  constexpr int K = 18;
+  cplx<double> e[NB][NB], l[NB][NB], te[NB][NB], tl[NB][NB];
+  for (int i = 0; i < NB; ++i)
+    for (int j = 0; j < NB; ++j) {
+      e[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
+      l[i][j] = mk(0.0, 0.0);
+    }
+  // e_k = 1 + a e_{k+1} / k,  l_k = (om e_{k+1} + a l_{k+1}) / k
+  for (int k = K; k >= 1; --k) {
+    const double rk = 1.0 / k;
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) {
+        cplx<double> se = mk(0.0, 0.0), sl = mk(0.0, 0.0);
+        for (int q = 0; q < NB; ++q) {
+          se = cfma(a[i][q], e[q][j], se);
+          sl = cfma(om[i][q], e[q][j], sl);
+          sl = cfma(a[i][q], l[q][j], sl);
+        }
+        te[i][j] = rk * se + mk(i == j ? 1.0 : 0.0, 0.0);
+        tl[i][j] = rk * sl;
+      }
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) {
+        e[i][j] = te[i][j];
+        l[i][j] = tl[i][j];
+      }
+  }
+  for (int s = 0; s < sq; ++s) {
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) {
+        cplx<double> se = mk(0.0, 0.0), sl = mk(0.0, 0.0);
+        for (int q = 0; q < NB; ++q) {
+          se = cfma(e[i][q], e[q][j], se);
+          sl = cfma(l[i][q], e[q][j], sl);
+          sl = cfma(e[i][q], l[q][j], sl);
+        }
+        te[i][j] = se;
+        tl[i][j] = sl;
+      }
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) {
+        e[i][j] = te[i][j];
+        l[i][j] = tl[i][j];
+      }
+  }
+  for (int i = 0; i < NB; ++i)
+    for (int j = 0; j < NB; ++j) om[i][j] = l[i][j];
+}
+
+// Thread per (site, chirality block c): Omega_c = X_c Y_c^+ (Xe non-null)
+// + cdet D_oo^{-1} (odd sites), exponential form (EXPO) Omega_c <- L(A_c, Omega_c),
+// then this block's share of Lam_p for the six planes into K[c][p][b][a][V].
+template <int D, bool EXPO>
+__global__ __launch_bounds__(64) void k_clover_insert(const cplx<double> *Xe, const cplx<double> *Xo,
+                                                      const cplx<double> *Ye, const cplx<double> *Yo,
+                                                      const cplx<double> *__restrict__ clov,
+                                                      const cplx<double> *__restrict__ F, cplx<double> *__restrict__ K,
+                                                      Geom g, SigmaBlocks S, double m0, double csw, double cdet) {
+  constexpr int NB = 2 * D;
+  const size_t V = 2 * (size_t)g.Vh;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 2 * V) return;
+  const int c = (int)(gid / V);
+  const size_t lex = gid - (size_t)c * V;
+  size_t r = lex;
+  const int z = (int)(r % g.Z); r /= g.Z;
+  const int y = (int)(r % g.Y); r /= g.Y;
+  const int x = (int)(r % g.X);
+  const int t = (int)(r / g.X);
+  const int par = (t + x + y + z) & 1;
+  const size_t cb = lex >> 1;
+  cplx<double> Om[NB][NB];
+  for (int i = 0; i < NB; ++i)
+    for (int j = 0; j < NB; ++j) Om[i][j] = mk(0.0, 0.0);
+  if (Xe) {
+    const cplx<double> *X = par ? Xo : Xe, *Y = par ? Yo : Ye;
+    cplx<double> xv[NB], yv[NB];
+    for (int sl = 0; sl < 2; ++sl)
+      for (int a = 0; a < D; ++a) {
+        const size_t o = (size_t)((2 * c + sl) * D + a) * g.stride + cb;
+        xv[sl * D + a] = X[o];
+        yv[sl * D + a] = Y[o];
+      }
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j)
+        Om[i][j] = mk(xv[i].re * yv[j].re + xv[i].im * yv[j].im, xv[i].im * yv[j].re - xv[i].re * yv[j].im);
+  }
+  if (cdet != 0.0 && par == 1) {
+    const cplx<double> *Mi = clov + (size_t)(2 + c) * NB * NB * g.stride + cb;
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) Om[i][j] = Om[i][j] + cdet * Mi[(size_t)(i * NB + j) * g.stride];
+  }
+  if constexpr (EXPO) {
+    // A = (i/4) c_sw sum_p S[p][c][s][t] F_p[a][b] / (4 + m), as in k_clover_finish
+    cplx<double> A[NB][NB];
+    const double f = 0.25 * csw / (4.0 + m0);
+    for (int s = 0; s < 2; ++s)
+      for (int a = 0; a < D; ++a)
+        for (int tt = 0; tt < 2; ++tt)
+          for (int b = 0; b < D; ++b) {
+            cplx<double> acc = mk(0.0, 0.0);
+            for (int p = 0; p < 6; ++p)
+              acc = cfma(S.v[p][c][s][tt], F[((size_t)p * D * D + a * D + b) * V + lex], acc);
+            A[s * D + a][tt * D + b] = mk(-f * acc.im, f * acc.re);
+          }
+    expm_frechet<NB>(A, Om);
+  }
+  // S.v holds 2 sigma
+  for (int p = 0; p < 6; ++p)
+    for (int b = 0; b < D; ++b)
+      for (int a = 0; a < D; ++a) {
+        cplx<double> acc = mk(0.0, 0.0);
+        for (int s = 0; s < 2; ++s)
+          for (int tt = 0; tt < 2; ++tt) acc = cfma(S.v[p][c][s][tt], Om[tt * D + b][s * D + a], acc);
+        K[(((size_t)(c * 6 + p) * D + b) * D + a) * V + lex] = 0.5 * acc;
+      }
+}
+
+// Thread per (plane p, site x): for the four leaves l of Q_p(x), the matrix
+// g = sum_b Re tr[T^b_R R(l) K_p] T^b = (H - tr(H)/N)/2 with H the Hermitian
+// part of the pull-back of R(l) K_p, into G[p][k][N][N][V].
+template <int N, int REP>
+__global__ __launch_bounds__(64) void k_clover_leafgen(const cplx<double> *__restrict__ U,
+                                                       const cplx<double> *__restrict__ K,
+                                                       cplx<double> *__restrict__ G, Geom g) {
+  constexpr int D = rep_dim(N, REP);
+  const size_t V = 2 * (size_t)g.Vh;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 6 * V) return;
+  const int p = (int)(gid / V);
+  const size_t lex = gid - (size_t)p * V;
+  int mu, nu;
+  plane_dirs(p, mu, nu);
+  size_t r = lex;
+  int c[4];
+  c[3] = (int)(r % g.Z); r /= g.Z;
+  c[2] = (int)(r % g.Y); r /= g.Y;
+  c[1] = (int)(r % g.X);
+  c[0] = (int)(r / g.X);
+  cplx<double> Kh[D][D];
+  {
+    cplx<double> lam[D][D];
+    for (int b = 0; b < D; ++b)
+      for (int a = 0; a < D; ++a)
+        lam[b][a] = K[(((size_t)p * D + b) * D + a) * V + lex] + K[(((size_t)(6 + p) * D + b) * D + a) * V + lex];
+    for (int b = 0; b < D; ++b)
+      for (int a = 0; a < D; ++a) Kh[b][a] = mk(lam[b][a].re + lam[a][b].re, lam[b][a].im - lam[a][b].im);
+  }
+  for (int k = 0; k < 4; ++k) {
+    cplx<double> L[N][N];
+    for (int f = 0; f < 4; ++f) {
+      const LeafStep s = kLeaf[k][f];
+      cplx<double> u[N][N];
+      load_link<N>(u, U, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
+      if (f == 0) {
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j) L[i][j] = u[i][j];
+      } else {
+        mul_right<N>(L, u);
+      }
+    }
+    cplx<double> R[D][D], M[D][D];
+    for (int A = 0; A < D; ++A)
+      for (int B = 0; B < D; ++B) R[A][B] = rep_entry<N, REP>(L, A, B);
+    for (int A = 0; A < D; ++A)
+      for (int B = 0; B < D; ++B) {
+        cplx<double> sum = mk(0.0, 0.0);
+        for (int C = 0; C < D; ++C) sum = cfma(R[A][C], Kh[C][B], sum);
+        M[A][B] = sum;
+      }
+    cplx<double> Z[N][N];
+    rep_pullback<N, REP>([&](int B, int A) { return M[B][A]; }, Z);
+    double tr = 0.0;
+    for (int i = 0; i < N; ++i) tr += Z[i][i].re;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        // (H - tr(H)/N) / 2, H = (Z + Z^+)/2
+        cplx<double> h = mk(0.25 * (Z[i][j].re + Z[j][i].re), 0.25 * (Z[i][j].im - Z[j][i].im));
+        if (i == j) h.re -= 0.5 * tr / N;
+        G[((size_t)(p * 4 + k) * N * N + i * N + j) * V + lex] = h;
+      }
+  }
+}
+
+// Thread per link (y, rho): P = coef sum over the planes (rho, nu) and the
+// leaf steps along rho of +-B^+ g B (see above); out as in the hopping force:
+// P, or G = 2i P U (gradient), stored or accumulated.
+template <int N>
+__global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__restrict__ U,
+                                                       const cplx<double> *__restrict__ Gl, double *P, Geom g,
+                                                       double coef, int gradient, int accumulate) {
+  const size_t V = 2 * (size_t)g.Vh;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 4 * V) return;
+  const size_t lex = gid >> 2;
+  const int rho = (int)(gid & 3);
+  size_t r = lex;
+  int cy[4];
+  cy[3] = (int)(r % g.Z); r /= g.Z;
+  cy[2] = (int)(r % g.Y); r /= g.Y;
+  cy[1] = (int)(r % g.X);
+  cy[0] = (int)(r / g.X);
+  cplx<double> acc[N][N];
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) acc[i][j] = mk(0.0, 0.0);
+  for (int nu = 0; nu < 4; ++nu) {
+    if (nu == rho) continue;
+    const int lo = rho < nu ? rho : nu, hi = rho < nu ? nu : rho;
+    const int p = lo == 0 ? hi - 1 : lo == 1 ? hi + 1 : 5;
+    const int dsel = rho == lo ? 0 : 1;
+    for (int k = 0; k < 4; ++k)
+      for (int f = 0; f < 4; ++f) {
+        const LeafStep st = kLeaf[k][f];
+        if (st.dir != dsel) continue;
+        // path from the corner x = y - a lo - b hi, links placed relative to y
+        cplx<double> B[N][N];
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j) B[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
+        const int nsteps = st.dag ? f + 1 : f;
+        for (int j = 0; j < nsteps; ++j) {
+          const LeafStep sj = kLeaf[k][j];
+          cplx<double> u[N][N];
+          load_link<N>(u, U, lex_at(g, cy, lo, sj.a - st.a, hi, sj.b - st.b), sj.dir ? hi : lo, sj.dag != 0);
+          mul_right<N>(B, u);
+        }
+        const size_t xl = lex_at(g, cy, lo, -st.a, hi, -st.b);
+        const cplx<double> *gp = Gl + (size_t)(p * 4 + k) * N * N * V + xl;
+        cplx<double> T1[N][N];
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j) {
+            cplx<double> sum = mk(0.0, 0.0);
+            for (int q = 0; q < N; ++q) sum = cfma(gp[(size_t)(i * N + q) * V], B[q][j], sum);
+            T1[i][j] = sum;
+          }
+        const double sg = st.dag ? -1.0 : 1.0;
+        for (int i = 0; i < N; ++i)
+          for (int j = 0; j < N; ++j) {
+            cplx<double> sum = mk(0.0, 0.0);
+            for (int q = 0; q < N; ++q) sum = cfma_conj(B[q][i], T1[q][j], sum);   // (B^+)_iq T1_qj
+            acc[i][j] = acc[i][j] + sg * sum;
+          }
+      }
+  }
+  cplx<double> Fo[N][N];
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) Fo[i][j] = coef * acc[i][j];
+  if (gradient) {
+    const cplx<double> *u = U + (lex * 4 + rho) * N * N;
+    cplx<double> Gm[N][N];
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        cplx<double> s = mk(0.0, 0.0);
+        for (int q = 0; q < N; ++q) s = cfma(Fo[i][q], u[q * N + j], s);
+        Gm[i][j] = mk(-2.0 * s.im, 2.0 * s.re);
+      }
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) Fo[i][j] = Gm[i][j];
+  }
+  double *out = P + (lex * 4 + rho) * N * N * 2;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      double re = Fo[i][j].re, im = Fo[i][j].im;
+      if (accumulate) {
+        re += out[2 * (i * N + j)];
+        im += out[2 * (i * N + j) + 1];
+      }
+      out[2 * (i * N + j)] = re;
+      out[2 * (i * N + j) + 1] = im;
+    }
+}
+
+// log|det D_oo(x)| summed over the odd sites: thread per (odd site, block),
+// Gaussian elimination with partial pivoting of the stored inverse block
+// (log|det D_oo| = -log|det D_oo^{-1}|), block partial sums.
+template <int D>
+__global__ __launch_bounds__(64) void k_clover_logdet(const cplx<double> *__restrict__ clov, double *partial,
+                                                      Geom g) {
+  constexpr int NB = 2 * D;
+  __shared__ double sh[1];
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (gid < 2 * (size_t)g.Vh) {
+    const int c = (int)(gid / g.Vh);
+    const size_t cb = gid - (size_t)c * g.Vh;
+    const cplx<double> *Mi = clov + (size_t)(2 + c) * NB * NB * g.stride + cb;
+    cplx<double> a[NB][NB];
+    for (int i = 0; i < NB; ++i)
+      for (int j = 0; j < NB; ++j) a[i][j] = Mi[(size_t)(i * NB + j) * g.stride];
+    double ld = 0.0;
+    for (int col = 0; col < NB; ++col) {
+      int piv = col;
+      double best = a[col][col].re * a[col][col].re + a[col][col].im * a[col][col].im;
+      for (int rr = col + 1; rr < NB; ++rr) {
+        const double m2 = a[rr][col].re * a[rr][col].re + a[rr][col].im * a[rr][col].im;
+        if (m2 > best) {
+          best = m2;
+          piv = rr;
+        }
+      }
+      if (piv != col)
+        for (int j = 0; j < NB; ++j) {
+          const cplx<double> tmp = a[col][j];
+          a[col][j] = a[piv][j];
+          a[piv][j] = tmp;
+        }
+      ld += 0.5 * log(best);
+      const cplx<double> d = a[col][col];
+      const double dn = 1.0 / best;
+      const cplx<double> di = mk(d.re * dn, -d.im * dn);
+      for (int rr = col + 1; rr < NB; ++rr) {
+        const cplx<double> fct = cmul(a[rr][col], di);
+        for (int j = col; j < NB; ++j) a[rr][j] = a[rr][j] - cmul(fct, a[col][j]);
+      }
+    }
+    v = -ld;
+  }
+  const double s = block_sum(v, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+constexpr bool clover_rep_ok(int N, int REP) {
+  return (REP != 3 || N > 2) && (rep_dim(N, REP) == 2 || rep_dim(N, REP) == 3 || rep_dim(N, REP) == 4 ||
+                                 rep_dim(N, REP) == 6);
+}
+
+template <int N, int REP>
+static hipError_t clover_force_nr(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo,
+                                  const void *U, const void *clov, double *F, double *K, double *Gl, const Geom &g,
+                                  double m0, double csw, int expo, double cdet, double coef, int gradient,
+                                  int accumulate, hipStream_t st) {
+  if constexpr (clover_rep_ok(N, REP)) {
+    constexpr int D = rep_dim(N, REP);
+    const size_t V = 2 * (size_t)g.Vh;
+    if (expo) {
+      hipError_t e = F_launch<N, REP>(U, F, g, st);
+      if (e != hipSuccess) return e;
+    }
+    const SigmaBlocks S = sigma_blocks();
+    const dim3 ig((unsigned)((2 * V + 63) / 64));
+    if (expo)
+      hipLaunchKernelGGL((k_clover_insert<D, true>), ig, dim3(64), 0, st, (const cplx<double> *)Xe,
+                         (const cplx<double> *)Xo, (const cplx<double> *)Ye, (const cplx<double> *)Yo,
+                         (const cplx<double> *)clov, (const cplx<double> *)F, (cplx<double> *)K, g, S, m0, csw, cdet);
+    else
+      hipLaunchKernelGGL((k_clover_insert<D, false>), ig, dim3(64), 0, st, (const cplx<double> *)Xe,
+                         (const cplx<double> *)Xo, (const cplx<double> *)Ye, (const cplx<double> *)Yo,
+                         (const cplx<double> *)clov, (const cplx<double> *)F, (cplx<double> *)K, g, S, m0, csw, cdet);
+    hipLaunchKernelGGL((k_clover_leafgen<N, REP>), dim3((unsigned)((6 * V + 63) / 64)), dim3(64), 0, st,
+                       (const cplx<double> *)U, (const cplx<double> *)K, (cplx<double> *)Gl, g);
+    hipLaunchKernelGGL((k_clover_gather<N>), dim3((unsigned)((4 * V + 127) / 128)), dim3(128), 0, st,
+                       (const cplx<double> *)U, (const cplx<double> *)Gl, (double *)P, g, coef, gradient, accumulate);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int N>
+static hipError_t clover_force_n(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo,
+                                 const void *U, const void *clov, double *F, double *K, double *Gl, const Geom &g,
+                                 int rep, double m0, double csw, int expo, double cdet, double coef, int gradient,
+                                 int accumulate, hipStream_t st) {
+  switch (rep) {
+    case 0: return clover_force_nr<N, 0>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 1: return clover_force_nr<N, 1>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 2: return clover_force_nr<N, 2>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 3: return clover_force_nr<N, 3>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_clover_force(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo, const void *U,
+                               const void *clov, double *F, double *K, double *Gl, const Geom &g, int N, int rep,
+                               double m0, double csw, int expo, double cdet, double coef, int gradient, int accumulate,
+                               hipStream_t st) {
+  switch (N) {
+    case 2: return clover_force_n<2>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, rep, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 3: return clover_force_n<3>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, rep, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 4: return clover_force_n<4>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, rep, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+int clover_logdet_blocks(const Geom &g) { return (int)((2 * (size_t)g.Vh + 63) / 64); }
+
+hipError_t launch_clover_logdet(const void *clov, double *partial, const Geom &g, int d, hipStream_t st) {
+  const dim3 grid((unsigned)clover_logdet_blocks(g));
+  switch (d) {
+    case 2: hipLaunchKernelGGL(k_clover_logdet<2>, grid, dim3(64), 0, st, (const cplx<double> *)clov, partial, g); break;
+    case 3: hipLaunchKernelGGL(k_clover_logdet<3>, grid, dim3(64), 0, st, (const cplx<double> *)clov, partial, g); break;
+    case 4: hipLaunchKernelGGL(k_clover_logdet<4>, grid, dim3(64), 0, st, (const cplx<double> *)clov, partial, g); break;
+    case 6: hipLaunchKernelGGL(k_clover_logdet<6>, grid, dim3(64), 0, st, (const cplx<double> *)clov, partial, g); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace wd

@@ -175,6 +175,17 @@ hipError_t launch_clover_field(void *clov, const void *U, double *F, const Geom 
 // out = D_ee in (parity 0) or D_oo^{-1} in (parity 1); out may alias in
 hipError_t launch_clover_apply(void *out, const void *in, const void *clov, const Geom &g, int d, int parity,
                                int nrhs, int prec, hipStream_t st);
+// Clover contribution to the link force of a functional with variation
+// -2 Re sum_x tr[dM Omega], Omega = X Y^+ (Xe non-null) + cdet D_oo^{-1} on odd
+// sites; P (+)= coef * force (or its gradient form).  F: 6 d^2 V, K: 12 d^2 V,
+// Gl: 24 N^2 V complex FP64 scratch (F only for the exponential form).
+hipError_t launch_clover_force(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo, const void *U,
+                               const void *clov, double *F, double *K, double *Gl, const Geom &g, int N, int rep,
+                               double m0, double csw, int expo, double cdet, double coef, int gradient, int accumulate,
+                               hipStream_t st);
+// Partial sums of log|det D_oo(x)| over the odd sites (clover_logdet_blocks of them).
+int clover_logdet_blocks(const Geom &g);
+hipError_t launch_clover_logdet(const void *clov, double *partial, const Geom &g, int d, hipStream_t st);
 
 // hmc.hip (one lattice per call; canonical fundamental links and momenta)
 hipError_t launch_gauge_force(const void *U, void *F, const Geom &g, int N, double beta, double scale,

@@ -103,4 +103,70 @@ __device__ __forceinline__ cplx<double> rep_entry(const cplx<double> (&u)[N][N],
   }
 }
 
+// Non-zero entries of two-index basis element A (SYM or 2AS): count, and
+// (row, col, value) of each.
+template <int N, bool SYM>
+__device__ __forceinline__ int two_index_nz(int A, int (&ri)[2], int (&ci)[2], double (&v)[2]) {
+  int a, b;
+  pair_of<N, SYM>(A, a, b);
+  if (a == b) {
+    ri[0] = a; ci[0] = a; v[0] = 1.0;
+    return 1;
+  }
+  const double s = 0.70710678118654752440;
+  ri[0] = a; ci[0] = b; v[0] = s;
+  ri[1] = b; ci[1] = a; v[1] = SYM ? s : -s;
+  return 2;
+}
+
+// Pull-back of a d_R x d_R matrix M to an N x N matrix Z with
+// tr(T^a_R M) = tr(T^a Z) for every generator a.  Mel(B, A) returns M_BA.
+//   FUND: Z = M.
+//   ADJ: (T^a_R)_bc = 2 tr(T^a [T^c, T^b]), so Z = 2 sum_bc M_cb [T^c, T^b].
+//   two-index: T^a_R e = T^a e + e T^aT gives, for every non-zero (e_A)_ij
+//   and (e_B)_kl, Z_ki += conj(e_A)_ij (e_B)_kj M_BA (l = j) and
+//   Z_lj += conj(e_A)_ij (e_B)_il M_BA (k = i); the bases are real.
+template <int N, int REP, typename MF>
+__device__ __forceinline__ void rep_pullback(MF Mel, cplx<double> (&Z)[N][N]) {
+  constexpr int D = rep_dim(N, REP);
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) Z[i][j] = mk(0.0, 0.0);
+  if constexpr (REP == 0) {
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) Z[i][j] = Mel(i, j);
+  } else if constexpr (REP == 1) {
+    int rb[N], cb[N], rc[N], cc[N];
+    cplx<double> vb[N], vc[N];
+    for (int c = 0; c < D; ++c) {
+      const int nc = gen_nz<N>(c, rc, cc, vc);
+      for (int b = 0; b < D; ++b) {
+        const int nb = gen_nz<N>(b, rb, cb, vb);
+        const cplx<double> m = 2.0 * Mel(c, b);
+        for (int p = 0; p < nc; ++p)
+          for (int q = 0; q < nb; ++q) {
+            if (cc[p] == rb[q]) Z[rc[p]][cb[q]] = cfma(m, cmul(vc[p], vb[q]), Z[rc[p]][cb[q]]);
+            if (cb[q] == rc[p]) Z[rb[q]][cc[p]] = cfma(mk(-m.re, -m.im), cmul(vb[q], vc[p]), Z[rb[q]][cc[p]]);
+          }
+      }
+    }
+  } else {
+    constexpr bool SYM = REP == 2;
+    int ra[2], ca[2], rb[2], cb[2];
+    double va[2], vb[2];
+    for (int A = 0; A < D; ++A) {
+      const int na = two_index_nz<N, SYM>(A, ra, ca, va);
+      for (int B = 0; B < D; ++B) {
+        const int nb = two_index_nz<N, SYM>(B, rb, cb, vb);
+        const cplx<double> m = Mel(B, A);
+        for (int p = 0; p < na; ++p)
+          for (int q = 0; q < nb; ++q) {
+            const cplx<double> c = (va[p] * vb[q]) * m;
+            if (cb[q] == ca[p]) Z[rb[q]][ra[p]] = Z[rb[q]][ra[p]] + c;
+            if (rb[q] == ra[p]) Z[cb[q]][ca[p]] = Z[cb[q]][ca[p]] + c;
+          }
+      }
+    }
+  }
+}
+
 }  // namespace wd

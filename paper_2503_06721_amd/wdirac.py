@@ -25,7 +25,8 @@ FUND, ADJ, SYM, ASYM = 0, 1, 2, 3
 F64, F32 = 0, 1
 CG_F64, CG_MIXED = 0, 1
 FIELD_HALF_SPINOR, FIELD_LINKS, FIELD_CLOVER = 0, 1, 2
-OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE, OP_MSHIFT, OP_CLOVER, OP_GAUGE = 0, 1, 2, 3, 4, 5, 6, 7, 8
+(OP_DHAT, OP_CG, OP_FORCE, OP_NORM, OP_DOT, OP_TUNE, OP_MSHIFT, OP_CLOVER, OP_GAUGE,
+ OP_CLOVER_FORCE) = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9
 MAX_SHIFTS = 32
 (OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
  OPT_HOP_NR_F32, OPT_TILE_TBLOCK, OPT_CG_GRAPH) = 0, 1, 2, 3, 4, 5, 6, 7, 8
@@ -96,6 +97,9 @@ _SIGS = {
     'wdirac_apply_clover': (_I, [_P, _P, _P, _P, _I, _I, _I, _P]),
     'wdirac_apply_dhat_clover': (_I, [_P, _P, _P, _P, _P, _I, _I, _I, _P, _P]),
     'wdirac_cg_eo_clover': (_I, [_P, _P, _P, _P, _P, _P, _P, _D, _I, _I, _I, _P, ctypes.POINTER(CgStats), _P]),
+    'wdirac_force_eo_clover': (_I, [_P, _P, _P, _P, _P, _P, _D, _D, _I, _D, _I, _I, _P, _P]),
+    'wdirac_force_clover_logdet': (_I, [_P, _P, _P, _P, _D, _D, _I, _D, _I, _I, _P, _P]),
+    'wdirac_clover_logdet': (_I, [_P, ctypes.POINTER(_D), _P, _P, _P]),
     'wdirac_stream_probe': (_I, [_P, ctypes.c_size_t, _I, _I, ctypes.POINTER(_D), _P]),
     'wdirac_last_error': (ctypes.c_char_p, []),
 }
@@ -352,6 +356,29 @@ class Lattice:
                                       float(tol), int(maxit), nrhs, mode, _ptr(ws), stats, _stream(stream))
         _check(rc, 'cg_eo_clover', allow)
         return rc, [s.as_dict() for s in stats]
+
+    def force_eo_clover(self, out, x_e, UR64, U, clov64, m0, csw, exponential=0, scale=1.0, gradient=0,
+                        accumulate=0, workspace=None, stream=None):
+        """Pseudofermion force with the clover D-hat: out = scale * P (or its gradient form 2i P U)."""
+        ws = workspace if workspace is not None else self.new_workspace(OP_CLOVER_FORCE, 1, F64)
+        _check(_lib.wdirac_force_eo_clover(self._h, _ptr(out), _ptr(x_e), _ptr(UR64), _ptr(U), _ptr(clov64),
+                                           float(m0), float(csw), int(exponential), float(scale), int(gradient),
+                                           int(accumulate), _ptr(ws), _stream(stream)), 'force_eo_clover')
+
+    def force_clover_logdet(self, out, U, clov64, m0, csw, exponential=0, scale=1.0, gradient=0, accumulate=0,
+                            workspace=None, stream=None):
+        """Force of S_det = -2 sum_{x odd} log|det D_oo(x)|."""
+        ws = workspace if workspace is not None else self.new_workspace(OP_CLOVER_FORCE, 1, F64)
+        _check(_lib.wdirac_force_clover_logdet(self._h, _ptr(out), _ptr(U), _ptr(clov64), float(m0), float(csw),
+                                               int(exponential), float(scale), int(gradient), int(accumulate),
+                                               _ptr(ws), _stream(stream)), 'force_clover_logdet')
+
+    def clover_logdet(self, clov64, workspace=None, stream=None):
+        """sum_{x odd} log|det D_oo(x)| (per lattice for a batch)."""
+        ws = workspace if workspace is not None else self.new_workspace(OP_CLOVER_FORCE, 1, F64)
+        out = (_D * self.nlat)()
+        _check(_lib.wdirac_clover_logdet(self._h, out, _ptr(clov64), _ptr(ws), _stream(stream)), 'clover_logdet')
+        return list(out) if self.batch else out[0]
 
     def new_shift_fields(self, nshift):
         """Output buffer of cg_mshift_eo: nshift packed FP64 even fields, one after the other."""

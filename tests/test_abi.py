@@ -104,7 +104,7 @@ def test_null_and_range_checks(W):
     assert L.wdirac_set_option(h, 99, 1.0) == W.EINVAL
     assert L.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_SITE) == W.OK
     assert L.wdirac_field_bytes(h, 9, 1, 0) == 0
-    assert L.wdirac_workspace_bytes(h, 9, 1, 0) == 0
+    assert L.wdirac_workspace_bytes(h, 10, 1, 0) == 0
     assert L.wdirac_destroy(h) == W.OK
 
 
@@ -196,8 +196,24 @@ def test_clover_argument_checks(W):
     st = (W.CgStats * 1)()
     assert L.wdirac_cg_eo_clover(h, dummy, ctypes.c_void_p(0x2000), dummy, None, None, None, 1e-10, 10, 1, 0, dummy,
                                  st, None) == W.EINVAL                                          # clov64 NULL
+    # clover force: workspace holds three half fields and the leaf scratch
+    V = 4 * 4 * 4 * 4
+    assert L.wdirac_workspace_bytes(h, W.OP_CLOVER_FORCE, 1, W.F64) >= (18 * 36 + 24 * 9) * V * 16
+    assert L.wdirac_force_eo_clover(h, dummy, dummy, dummy, dummy, dummy, -4.0, 1.0, 0, 1.0, 0, 0, dummy,
+                                    None) == W.EINVAL                                          # 4 + m0 = 0
+    assert L.wdirac_force_eo_clover(h, dummy, dummy, dummy, dummy, dummy, 0.1, 1.0, 0, 1.0, 2, 0, dummy,
+                                    None) == W.EINVAL                                          # gradient flag
+    assert L.wdirac_force_eo_clover(h, dummy, None, dummy, dummy, dummy, 0.1, 1.0, 0, 1.0, 0, 0, dummy,
+                                    None) == W.EINVAL                                          # x_e NULL
+    assert L.wdirac_force_clover_logdet(h, dummy, None, dummy, 0.1, 1.0, 0, 1.0, 0, 0, dummy, None) == W.EINVAL
+    assert L.wdirac_force_clover_logdet(h, dummy, dummy, dummy, 0.1, 1.0, 0, 1.0, 0, 3, dummy, None) == W.EINVAL
+    ld = (ctypes.c_double * 1)()
+    assert L.wdirac_clover_logdet(h, ld, None, dummy, None) == W.EINVAL
     L.wdirac_destroy(h)
     rc, h = create(W, 4, 1)   # SU(4) ADJ, d = 15: no clover
     assert L.wdirac_field_bytes(h, W.FIELD_CLOVER, 1, W.F64) == 0
+    assert L.wdirac_workspace_bytes(h, W.OP_CLOVER_FORCE, 1, W.F64) == 0
     assert L.wdirac_clover_field(h, dummy, dummy, -0.1, 1.0, 0, 0, dummy, None) == W.EUNSUPPORTED
+    assert L.wdirac_force_clover_logdet(h, dummy, dummy, dummy, 0.1, 1.0, 0, 1.0, 0, 0, dummy, None) == W.EUNSUPPORTED
+    assert L.wdirac_clover_logdet(h, ld, dummy, dummy, None) == W.EUNSUPPORTED
     L.wdirac_destroy(h)
