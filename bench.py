@@ -286,7 +286,8 @@ def rhmc_and_clover(W, torch, synth, name='su3_fund_32x32x32x32'):
     """On the benchmark lattice: 12 shifts (a zero shift and 11 from 1e-4 to
     5.9) in one multi-shift call against 12 one-shift calls; and the
     clover-improved operator (c_sw = 1) -- clover field construction, FP64 and
-    mixed CG to 1e-10 on D-hat^+ D-hat with the clover D-hat."""
+    mixed CG to 1e-10 on D-hat^+ D-hat with the clover D-hat, and the clover
+    force (pseudofermion and determinant terms, regular and exponential)."""
     cfg = synth.CONFIGS[name]
     dims, m0 = cfg['dims'], cfg['m0']
     lat = W.Lattice(cfg['N'], cfg['rep'], dims, cfg['bc'])
@@ -339,6 +340,34 @@ def rhmc_and_clover(W, torch, synth, name='su3_fund_32x32x32x32'):
                    'true_rel_resid': stc[0]['true_rel_resid'], 'status': W.STATUS_NAMES.get(rc)}
     cl['mixed_speedup'] = round(cl['f64']['seconds'] / cl['mixed']['seconds'], 3)
     log(f'[bench] clover CG: {cl}')
+    del cg_ws, c32
+
+    def timed_ms(fn):
+        fn()   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return round((time.perf_counter() - t0) * 1e3, 3)
+
+    # clover force at the CG solution: pseudofermion force (3 hops, 3 clover
+    # applications, hopping links, clover insertion, leaves, gather), the
+    # odd-block determinant force and its action; regular then exponential
+    N = cfg['N']
+    P = torch.zeros(tuple(dims) + (4, N, N), dtype=torch.complex128, device='cuda')
+    fws = lat.new_workspace(W.OP_CLOVER_FORCE, 1, W.F64)
+    cws = lat.new_workspace(W.OP_CLOVER, 1, W.F64)
+    forces = {}
+    for expo, key in ((0, 'regular'), (1, 'exponential')):
+        lat.clover_field(c64, U, m0, csw, expo, W.F64, workspace=cws)
+        forces[key] = {
+            'pseudofermion_force_ms': timed_ms(lambda: lat.force_eo_clover(P, xc, UR64, U, c64, m0, csw, expo,
+                                                                           workspace=fws)),
+            'logdet_force_ms': timed_ms(lambda: lat.force_clover_logdet(P, U, c64, m0, csw, expo, accumulate=1,
+                                                                        workspace=fws)),
+            'logdet_ms': timed_ms(lambda: lat.clover_logdet(c64, workspace=fws))}
+    cl['force'] = forces
+    log(f'[bench] clover force: {forces}')
     return {'workload': name, 'multi_shift_time_to_1e-10': ms, 'clover_cg_time_to_1e-10': cl}
 
 

@@ -15,14 +15,19 @@ and error scaling in its table of integrators but not the equations):
   dS_g/dw^a_mu(x) = (beta / N) Im tr(T^a U_mu(x) A_mu(x));
 * pseudofermion S_f = phi^+ (D-hat^+ D-hat)^{-1} phi with its force from
   oracle.force; phi = D-hat^+ eta for Gaussian eta at the start;
+* with a clover term (c_sw given): the clover D-hat of oracle.clover, and
+  S_det = -2 sum_{x odd} log det D_oo added to the action, both with their
+  forces from oracle.clover_force;
 * integrators: leapfrog (PQP) and second-order Omelyan (PQPQP, lambda =
   0.1931833275037836), nsteps steps of size eps over the trajectory.
 """
 import numpy as np
 
+from . import clover as CL
+from . import clover_force as CF
 from . import force as F
 from . import reps
-from .cg import cg_eo
+from .cg import cg, cg_eo
 from .reductions import inner
 
 
@@ -97,18 +102,30 @@ def kinetic(pi):
 
 
 class Action:
-    """S_g + S_f for fermions in representation rep; phi the pseudofermion."""
+    """S_g + S_f for fermions in representation rep; phi the pseudofermion.
+    csw: clover coefficient (None: unimproved Wilson); exponential: the
+    exponential clover form."""
 
-    def __init__(self, beta, m, rep, bc, phi_e, tol=1e-13, with_fermions=True):
+    def __init__(self, beta, m, rep, bc, phi_e, tol=1e-13, with_fermions=True, csw=None, exponential=False):
         self.beta, self.m, self.rep, self.bc = beta, m, rep, bc
         self.phi, self.tol, self.with_fermions = phi_e, tol, with_fermions
+        self.csw, self.exponential = csw, exponential
+
+    def _solve(self, UR, dims):
+        if self.csw is None:
+            return cg_eo(self.phi, UR, self.m, self.bc, dims, self.tol, 50000)[0]
+        def A(v):
+            return CL.normal_op_clover(v, UR, self.m, self.csw, self.bc, dims, self.exponential)
+        return cg(A, self.phi, self.tol, 50000)[0]
 
     def value(self, U):
         s = gauge_action(U, self.beta)
         if self.with_fermions:
             UR = reps.represent(U, self.rep)
-            x, _, _ = cg_eo(self.phi, UR, self.m, self.bc, U.shape[:4], self.tol, 50000)
-            s += inner(self.phi, x).real
+            dims = U.shape[:4]
+            s += inner(self.phi, self._solve(UR, dims)).real
+            if self.csw is not None:
+                s += CF.det_action(U, self.rep, self.m, self.csw, dims, self.exponential)
         return s
 
     def force(self, U):
@@ -117,8 +134,14 @@ class Action:
             N = U.shape[-1]
             UR = reps.represent(U, self.rep)
             dims = U.shape[:4]
-            x, _, _ = cg_eo(self.phi, UR, self.m, self.bc, dims, self.tol, 50000)
-            Fm = Fm + F.force(x, UR, self.m, self.bc, dims, N, self.rep)
+            x = self._solve(UR, dims)
+            if self.csw is None:
+                Fm = Fm + F.force(x, UR, self.m, self.bc, dims, N, self.rep)
+            else:
+                g = (CF.pseudofermion_force_components(x, U, self.rep, self.m, self.csw, self.bc, dims,
+                                                       self.exponential)
+                     + CF.det_force_components(U, self.rep, self.m, self.csw, dims, self.exponential))
+                Fm = Fm + reps.algebra_to_matrix(g, N)
         return Fm
 
 

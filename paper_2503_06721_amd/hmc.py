@@ -4,7 +4,10 @@ Conventions as in the library's HMC entry points: momenta pi are Hermitian
 traceless matrices in the canonical link layout, dU/dtau = i pi U,
 dpi/dtau = -F (F the force matrix of the gauge and fermion actions),
 H = sum tr(pi^2) + S_g + S_f with the Wilson plaquette action S_g and the
-even-odd pseudofermion action S_f = phi^+ (D-hat^+ D-hat)^{-1} phi.
+even-odd pseudofermion action S_f = phi^+ (D-hat^+ D-hat)^{-1} phi; with a
+clover term (csw given; regular, Sec. 6.1.2, or exponential, Sec. 6.1.3) the
+clover D-hat = D_ee - D_eo D_oo^{-1} D_oe and the odd-block determinant term
+S_det = -2 sum_{x odd} log|det D_oo| (det D = det D_oo det D-hat).
 Integrators: leapfrog (PQP) and second-order Omelyan (PQPQP).  Every
 computation runs in the library's kernels; this module only sequences calls.
 """
@@ -16,20 +19,36 @@ OMELYAN_LAMBDA = 0.1931833275037836
 
 
 class HMC:
-    def __init__(self, lat, beta, m0, tol=1e-12, maxit=20000, with_fermions=True):
+    def __init__(self, lat, beta, m0, tol=1e-12, maxit=20000, with_fermions=True, csw=None, exponential=0):
         self.lat, self.beta, self.m0 = lat, float(beta), float(m0)
         self.tol, self.maxit, self.with_fermions = tol, maxit, with_fermions
+        self.csw, self.exponential = (None if csw is None else float(csw)), int(exponential)
         self.UR = lat.new_links(W.F64)
         self.x = lat.new_half()
         self.ws_cg = lat.new_workspace(W.OP_CG, 1, W.CG_F64)
         self.ws_force = lat.new_workspace(W.OP_FORCE)
         self.ws_gauge = lat.new_workspace(W.OP_GAUGE)
+        if self.csw is not None:
+            self.clov = lat.new_clover(W.F64)
+            self.ws_clov = lat.new_workspace(W.OP_CLOVER, 1, W.F64)
+            self.ws_cforce = lat.new_workspace(W.OP_CLOVER_FORCE, 1, W.F64)
         self.cg_iters = 0
 
-    def _solve(self, U, phi):
+    def _operator(self, U):
+        """Represented links (and clover field) of U."""
         self.lat.rep_links(self.UR, U, W.F64)
+        if self.csw is not None:
+            self.lat.clover_field(self.clov, U, self.m0, self.csw, self.exponential, W.F64, workspace=self.ws_clov)
+
+    def _solve(self, U, phi):
+        self._operator(U)
         self.x.zero_()
-        rc, st = self.lat.cg_eo(self.x, phi, self.UR, self.m0, tol=self.tol, maxit=self.maxit, workspace=self.ws_cg)
+        if self.csw is None:
+            rc, st = self.lat.cg_eo(self.x, phi, self.UR, self.m0, tol=self.tol, maxit=self.maxit,
+                                    workspace=self.ws_cg)
+        else:
+            rc, st = self.lat.cg_eo_clover(self.x, phi, self.UR, self.clov, tol=self.tol, maxit=self.maxit,
+                                           workspace=self.ws_cg)
         if rc != W.OK:
             raise W.WdiracError(rc, 'HMC solve')
         self.cg_iters += st[0]['iters']
@@ -39,6 +58,8 @@ class HMC:
         if self.with_fermions:
             self._solve(U, phi)
             s += self.lat.dot(phi, self.x)[0].real
+            if self.csw is not None:
+                s += -2.0 * self.lat.clover_logdet(self.clov, workspace=self.ws_cforce)
         return s
 
     def kinetic(self, pi):
@@ -52,7 +73,13 @@ class HMC:
         self.lat.gauge_force(pi, U, self.beta, scale=-c, accumulate=1)
         if self.with_fermions:
             self._solve(U, phi)
-            self.lat.force_eo(pi, self.x, self.UR, self.m0, scale=-c, accumulate=1, workspace=self.ws_force)
+            if self.csw is None:
+                self.lat.force_eo(pi, self.x, self.UR, self.m0, scale=-c, accumulate=1, workspace=self.ws_force)
+            else:
+                self.lat.force_eo_clover(pi, self.x, self.UR, U, self.clov, self.m0, self.csw, self.exponential,
+                                         scale=-c, accumulate=1, workspace=self.ws_cforce)
+                self.lat.force_clover_logdet(pi, U, self.clov, self.m0, self.csw, self.exponential, scale=-c,
+                                             accumulate=1, workspace=self.ws_cforce)
 
     def drift(self, U, pi, c):
         """U <- exp(i c pi) U."""
@@ -86,6 +113,9 @@ class HMC:
         lat.algebra_from_components(pi, w_momenta.contiguous())
         phi = lat.new_half()
         if self.with_fermions:
-            lat.rep_links(self.UR, U, W.F64)
-            lat.apply_dhat(phi, eta, self.UR, self.m0, dagger=1)
+            self._operator(U)
+            if self.csw is None:
+                lat.apply_dhat(phi, eta, self.UR, self.m0, dagger=1)
+            else:
+                lat.apply_dhat_clover(phi, eta, self.UR, self.clov, dagger=1)
         return pi, phi

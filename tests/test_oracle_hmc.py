@@ -1,11 +1,14 @@
 """Pins of the oracle's HMC molecular dynamics (Sec. 5.2, 5.3): the gauge
 force against central finite differences of the plaquette action, the
 integrators' energy-error scaling (leapfrog and second-order Omelyan, both
-O(eps^2) per trajectory as in the paper's table of integrators), exact
-reversibility, and unitarity of the evolved links (no GPU)."""
+O(eps^2) per trajectory as in the paper's table of integrators; also with a
+clover term, where the scaling holds only if the clover and determinant
+forces are the exact gradients of their actions), exact reversibility, and
+unitarity of the evolved links (no GPU)."""
 import numpy as np
 import pytest
 
+from oracle import clover as CL
 from oracle import dirac as D
 from oracle import hmc as H
 from oracle import reps as R
@@ -80,3 +83,20 @@ def test_pure_gauge_limit():
     pg = H.Action(act.beta, act.m, act.rep, APBC, act.phi, with_fermions=False)
     assert np.allclose(pg.force(U), H.gauge_force(U, act.beta))
     assert pg.value(U) == H.gauge_action(U, act.beta)
+
+
+@pytest.mark.parametrize('expo', [False, True])
+def test_energy_error_scaling_clover(expo):
+    dims, N, rep, m, csw = (2, 2, 2, 4), 2, 'FUND', 0.2, 1.8
+    U = synth.expH_links(dims, N, 0.4, 85)
+    UR = R.represent(U, rep)
+    eta = synth.gaussian_spinor((16, 4, 2), 86)
+    phi = CL.Dhat_clover(eta, UR, m, csw, APBC, dims, expo, dagger=True)
+    act = H.Action(2.0, m, rep, APBC, phi, csw=csw, exponential=expo)
+    pi = momenta(dims, N, 87)
+    dH = []
+    for n in (4, 8, 16):
+        _, _, H0, H1 = H.trajectory(U, pi, act, 0.5 / n, n, 'leapfrog')
+        dH.append(abs(H1 - H0))
+    r1, r2 = dH[0] / dH[1], dH[1] / dH[2]
+    assert 3.3 < r1 < 4.8 and 3.6 < r2 < 4.4, dH
