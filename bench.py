@@ -75,9 +75,10 @@ def device_copy_gbps(torch, n=1 << 28, reps=3):
     return ms, 2 * n * 8 / ms / 1e6
 
 
-def measured_traffic(launch_bytes):
+def measured_traffic(launch_bytes, shape):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if the hop kernel source changed since the counters were taken."""
+    None if the hop kernel source changed since the counters were taken or
+    the autotuner picked another launch shape than the one they were taken on."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -85,7 +86,10 @@ def measured_traffic(launch_bytes):
             h = hashlib.sha256(f.read()).hexdigest()
         if rec.get('hop_source_sha256') != h:
             return None
-        return rec['hbm_bytes_per_launch']
+        for row in rec.get('per_launch_shape', []):
+            if all(shape.get(k) == v for k, v in row['launch_shape'].items()):
+                return row['hbm_bytes_per_launch']
+        return None
     except (OSError, KeyError, ValueError):
         return None
 
@@ -115,6 +119,16 @@ def cpu_baseline(cfg, U, psi, seconds_target=15.0):
             'seconds_per_hop': t_hop / n}
 
 
+FORM_NAMES = {0: 'site-parallel', 1: 'colour-split', 2: 'colour-split, paired directions',
+              3: 'colour-split, compact links', 4: 'colour-split, compact links, paired directions'}
+
+
+def tuned_form(best):
+    """Readable launch shape from an autotune result."""
+    return {'form': FORM_NAMES.get(best['variant'], str(best['variant'])), 'rhs_per_block': best['nr'],
+            'xcd_remap': best['xcd_remap'], 't_block': best['tblock']}
+
+
 def multi_rhs_cg(W, torch, synth, name='su3_sym_48x24x24x24'):
     """Time-to-1e-10 of the even-odd CG for 12 point sources on one gauge
     field: all 12 in one batched solve (every hop streams each link once for
@@ -136,13 +150,15 @@ def multi_rhs_cg(W, torch, synth, name='su3_sym_48x24x24x24'):
     lat.eo_source(bp, eta_e, eta_o, UR64, m0, nrhs)
     lat.apply_dhat(b, bp, UR64, m0, dagger=1, nrhs=nrhs)
     del bp, eta_e, eta_o
-    for prec, UR in ((W.F64, UR64), (W.F32, UR32)):
-        lat.autotune(UR, prec, nrhs)
-        lat.autotune(UR, prec, 1)
+    forms = {}
+    for prec, UR, key in ((W.F64, UR64, 'f64'), (W.F32, UR32, 'f32')):
+        forms[f'{key}_{nrhs}rhs'] = tuned_form(lat.autotune(UR, prec, nrhs))
+        forms[f'{key}_1rhs'] = tuned_form(lat.autotune(UR, prec, 1))
     ws = lat.new_workspace(W.OP_CG, nrhs, W.CG_MIXED)
     x = lat.new_half(nrhs)
     per = x.numel() // nrhs
-    out = {'workload': name, 'sources': f'{nrhs} point sources (spin k%4, colour k//4) at the origin'}
+    out = {'workload': name, 'sources': f'{nrhs} point sources (spin k%4, colour k//4) at the origin',
+           'hop_forms': forms}
     for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
         x.zero_()
         rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, nrhs=nrhs, mode=mode, UR32=UR32, workspace=ws)
@@ -188,11 +204,10 @@ def mixed_cg_large(W, torch, synth, name='su4_2as_96x48x48x48'):
     b = lat.new_half()
     lat.apply_dhat(b, eta_e, UR64, m0, dagger=1)
     del eta_e
-    lat.autotune(UR64, W.F64, 1)
-    lat.autotune(UR32, W.F32, 1)
+    forms = {'f64': tuned_form(lat.autotune(UR64, W.F64, 1)), 'f32': tuned_form(lat.autotune(UR32, W.F32, 1))}
     ws = lat.new_workspace(W.OP_CG, 1, W.CG_MIXED)
     x = lat.new_half()
-    out = {'workload': name, 'source': 'D-hat^+ eta, eta Gaussian'}
+    out = {'workload': name, 'source': 'D-hat^+ eta, eta Gaussian', 'hop_forms': forms}
     for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
         x.zero_()
         rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, mode=mode, UR32=UR32, workspace=ws)
@@ -395,7 +410,9 @@ def hmc_trajectory(W, torch, synth, name='su2_adj_32x16x16x16'):
     secs = time.perf_counter() - t0
     log(f'[bench] HMC trajectory: {secs:.3f} s, dH {H1 - H0:.3e}, CG iterations {hmc.cg_iters}')
     return {'workload': name, 'integrator': 'omelyan2', 'tau': 0.5, 'steps': 5, 'beta': 2.2,
-            'seconds': round(secs, 4), 'dH': H1 - H0, 'cg_iterations': hmc.cg_iters}
+            'seconds': round(secs, 4), 'dH': H1 - H0, 'cg_iterations': hmc.cg_iters,
+            'start': 'synthetic exp(i 0.3 H) links, far from equilibrium at this beta, so |dH| is large; '
+                     'energy conservation is checked in the tests (dH ~ eps^2)'}
 
 
 def main():
@@ -409,6 +426,9 @@ def main():
     ap.add_argument('--no-multi', action='store_true',
                     help='skip the one-off solver comparisons (12 sources batched vs single, SU(4) 2AS mixed vs '
                          'FP64, three-lattice batch) and the force timing')
+    ap.add_argument('--traffic-shapes', action='store_true',
+                    help='profiling aid: 6 hop launches (the benchmark pattern) for every FP64 launch shape the '
+                         'autotuner may pick, in the order printed, to take HBM counters per shape')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='run only a device copy of 2 GiB (x3), the known-size kernel that calibrates the '
                          'FETCH_SIZE / WRITE_SIZE counters, and print its bandwidth')
@@ -454,6 +474,22 @@ def main():
     stream = torch.cuda.current_stream()
 
     bytes_per_launch = hop_bytes_per_site(d, lat.real, 8) * lat.Vh
+    if args.traffic_shapes:
+        shapes = []
+        for variant in (W.HOP_SITE, W.HOP_COLOUR, W.HOP_COLOUR_PAIR):
+            for remap in (0, 1):
+                for tb in (0, 2, 4, 8):
+                    lat.set_option(W.OPT_HOP_VARIANT_F64, variant)
+                    lat.set_option(W.OPT_XCD_REMAP, remap)
+                    lat.set_option(W.OPT_TILE_TBLOCK, tb)
+                    lat.set_option(W.OPT_HOP_NR_F64, 1)
+                    for k in range(6):
+                        src, dst = (halves[0], halves[1]) if k % 2 == 0 else (halves[1], halves[2])
+                        lat.dslash_eo(dst, src, UR64, 0 if k % 2 == 0 else 1)
+                    shapes.append({'variant': variant, 'xcd_remap': remap, 'tblock': tb, 'nr': 1})
+        torch.cuda.synchronize()
+        print(json.dumps({'launches_per_shape': 6, 'shapes': shapes}))
+        return
     # the library's autotuner picks the hop launch shape for both precisions
     tuned = {'f64': lat.autotune(UR64, W.F64, 1), 'f32': lat.autotune(UR32, W.F32, 1)}
     log(f'[bench] autotuned hop shapes: {tuned}')
@@ -466,7 +502,7 @@ def main():
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for k in range(args.hops):
-            # alternate D_eo and D_oe so that every launch reads a fresh input
+            # alternate D_eo (h0 -> h1) and D_oe (h1 -> h2): every other launch reads the output just written
             src, dst = (halves[0], halves[1]) if k % 2 == 0 else (halves[1], halves[2])
             lat.dslash_eo(dst, src, UR64, 0 if k % 2 == 0 else 1)
         e1.record(stream)
@@ -502,7 +538,7 @@ def main():
     # the library's streaming probe with the hop's read:write mix (7:1)
     stream_gbs = round(W.stream_probe(1 << 24, 7, 20), 1)
     gbs = bytes_per_launch / (hop_ms * 1e-3) / 1e9
-    traffic = measured_traffic(bytes_per_launch)
+    traffic = measured_traffic(bytes_per_launch, tuned['f64'])
     out = {
         'metric': 'Dslash GB/s & % HBM roofline; CG time-to-1e-10 (FP64 vs mixed/multi-RHS)',
         'value': round(gbs, 2),

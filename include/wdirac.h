@@ -119,7 +119,12 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                          64-site tile (default),
  *                                      2 = as 1 with the forward and backward
  *                                          hop of each direction staged
- *                                          together (half the barriers)
+ *                                          together (half the barriers),
+ *                                      3, 4 = as 1, 2 reading the compact
+ *                                          fundamental links and rebuilding
+ *                                          the entries of U_R in registers
+ *                                          (SYM for N = 2..4, 2AS for N = 4;
+ *                                          1 or 2 rhs per block)
  *   WDIRAC_OPT_XCD_REMAP               1 (default) = give each XCD a
  *                                      contiguous range of site tiles
  *   WDIRAC_OPT_CG_CHECK_EVERY          CG iterations between host checks of
@@ -175,9 +180,11 @@ typedef struct {
 
 /* Autotuner: times every available launch shape of the hopping kernel
  * (variant x right-hand sides per block x XCD tile mapping x tile order) for
- * nrhs right-hand sides in precision prec on the links UR (HIP events: 3
+ * nrhs right-hand sides in precision prec on the links UR (HIP events: 4
  * warm-up and 10 timed launches each, then the four fastest again in three
- * interleaved rounds of 20, each keeping its fastest round), and makes the
+ * interleaved rounds of 20, each keeping its fastest round; launches
+ * alternate D_eo and D_oe over three fields so that every other launch reads
+ * the output just written, as between the hops of a solver), and makes the
  * fastest the one used for this (prec, nrhs) by every later call on ctx (CG
  * included).  Results never change
  * beyond rounding.  workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_TUNE,
@@ -217,7 +224,12 @@ int wdirac_unpack_spinor(const wdirac_ctx *ctx, void *canon, const void *packed,
  * 6.3.1 applies the antiperiodic sign to one slice of the represented field).
  * Bases of R: generalised Gell-Mann generators, ADJ (U_R)_ab =
  * 2 tr(T^a U T^b U^+), SYM/2AS on the orthonormal (anti)symmetric basis
- * matrices in lexicographic pair order.  Errors: EINVAL, EHIP. */
+ * matrices in lexicographic pair order.  For SYM with N = 2, 3, 4 and 2AS
+ * with N = 4 the field also holds, after U_R, a compact copy of the
+ * fundamental links (N^2 instead of d_R^2 entries per link; i U on the links
+ * whose phase is -1, since the two-index maps are quadratic) from which the
+ * compact hop forms rebuild U_R in registers; wdirac_field_bytes(
+ * WDIRAC_FIELD_LINKS) counts both.  Errors: EINVAL, EHIP. */
 int wdirac_rep_links(const wdirac_ctx *ctx, void *UR, const void *U, int prec, void *stream);
 
 /* Unpack packed links `UR` (precision `prec`) to the canonical represented

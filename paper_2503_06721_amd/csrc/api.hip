@@ -23,7 +23,7 @@ struct wdirac_ctx {
   wd::Geom g[wd::MAXLAT];
   long long spre[wd::MAXLAT + 1];  // prefix sums of the packed row strides (sites)
   long long vpre[wd::MAXLAT + 1];  // prefix sums of the lattice volumes (canonical sites)
-  int hop_variant[2];   // per precision (F64, F32): wd::HOP_SITE, HOP_COLOUR or HOP_COLOUR_PAIR
+  int hop_variant[2];   // per precision (F64, F32): one of the wd::HOP_* forms
   int hop_nr[2];        // preferred right-hand sides per colour-split block
   wdirac_tuned tuned[2][13];   // autotuned shape per (precision, nrhs)
   int xcd_remap;
@@ -184,6 +184,17 @@ MsWork carve_ms(const wdirac_ctx *c, int nshift, void *ws) {
   return w;
 }
 
+// Bytes of the represented links of the whole context in precision prec; the
+// compact fundamental copy (two-index representations with compact forms)
+// follows them in the same links field.
+size_t rep_links_bytes(const wdirac_ctx *c, int prec) {
+  return (size_t)8 * c->d * c->d * c->spre[c->nlat] * (prec == WDIRAC_F64 ? 8 : 4) * (c->real ? 1 : 2);
+}
+size_t compact_links_bytes(const wdirac_ctx *c, int prec) {
+  if (!wd::compact_links_ok(c->N, c->rep)) return 0;
+  return (size_t)8 * c->N * c->N * c->spre[c->nlat] * (prec == WDIRAC_F64 ? 16 : 8);
+}
+
 // Right-hand sides per colour-split block: the largest supported divisor of
 // nrhs not above the preference.
 int effective_nr(const wdirac_ctx *c, int pref, int nrhs, int prec, int variant) {
@@ -211,6 +222,7 @@ int hop(const wdirac_ctx *c, void *out, const void *in, const void *UR, int out_
   a.out = out;
   a.in = in;
   a.links = UR;
+  a.flinks = wd::compact_links_ok(c->N, c->rep) ? static_cast<const char *>(UR) + rep_links_bytes(c, prec) : nullptr;
   a.xadd = xadd;
   a.nlat = c->nlat;
   for (int l = 0; l < c->nlat; ++l) {
@@ -218,6 +230,7 @@ int hop(const wdirac_ctx *c, void *out, const void *in, const void *UR, int out_
     a.lat[l].tile0 = a.lat[l].ntiles = 0;
     a.lat[l].soff = c->nlat == 1 ? 0 : (long long)4 * c->d * c->spre[l];
     a.lat[l].loff = (long long)8 * c->d * c->d * c->spre[l];
+    a.lat[l].floff = (long long)8 * c->N * c->N * c->spre[l];
   }
   a.parity = out_parity;
   a.xcd_remap = remap;
@@ -229,8 +242,8 @@ int hop(const wdirac_ctx *c, void *out, const void *in, const void *UR, int out_
   a.tiles_per_tx = 0;
   wd::Counts cnt{};
   int pr = 0;
-  WD_HIP(wd::launch_hop(a, c->d, c->real, prec, dagger, nrhs, variant, effective_nr(c, pref, nrhs, prec, variant),
-                        st, &cnt, &pr));
+  WD_HIP(wd::launch_hop(a, c->N, c->rep, c->d, c->real, prec, dagger, nrhs, variant,
+                        effective_nr(c, pref, nrhs, prec, variant), st, &cnt, &pr));
   if (counts) *counts = cnt;
   if (prow) *prow = pr;
   return WDIRAC_OK;
@@ -403,7 +416,7 @@ size_t wdirac_field_bytes(const wdirac_ctx *ctx, int kind, int nrhs, int prec) {
     if (nrhs < 1 || nrhs > 12) return 0;
     return half_bytes(ctx, nrhs, prec);
   }
-  if (kind == WDIRAC_FIELD_LINKS) return (size_t)8 * ctx->d * ctx->d * ctx->spre[ctx->nlat] * el * (ctx->real ? 1 : 2);
+  if (kind == WDIRAC_FIELD_LINKS) return rep_links_bytes(ctx, prec) + compact_links_bytes(ctx, prec);
   if (kind == WDIRAC_FIELD_CLOVER)
     return wd::clover_supported(ctx->d) ? (size_t)16 * ctx->d * ctx->d * ctx->spre[ctx->nlat] * 2 * el : 0;
   return 0;
@@ -445,7 +458,7 @@ size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec)
       return align256(partial_doubles(ctx, nrhs) * sizeof(double)) + align256(2 * wd::MAXSYS * sizeof(double));
     case WDIRAC_OP_TUNE:
       if (prec != WDIRAC_F64 && prec != WDIRAC_F32) return 0;
-      return 2 * align256(half_bytes(ctx, nrhs, prec));
+      return 3 * align256(half_bytes(ctx, nrhs, prec));
   }
   return 0;
 }
@@ -456,7 +469,7 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
     case WDIRAC_OPT_HOP_VARIANT_F64:
     case WDIRAC_OPT_HOP_VARIANT_F32: {
       const int v = (int)value;
-      if (v < wd::HOP_SITE || v > wd::HOP_COLOUR_PAIR || !wd::hop_variant_ok(ctx->d, v))
+      if (v < wd::HOP_SITE || v > wd::HOP_COMPACT_PAIR || !wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, v))
         return fail(WDIRAC_EUNSUPPORTED, "hop variant not available for this representation");
       ctx->hop_variant[option == WDIRAC_OPT_HOP_VARIANT_F64 ? 0 : 1] = v;
       return WDIRAC_OK;
@@ -499,8 +512,10 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
   const hipStream_t st = S(stream);
   Carver cv{static_cast<char *>(workspace)};
   const size_t hb = half_bytes(ctx, nrhs, prec);
-  void *in = cv.take(hb), *out = cv.take(hb);
-  WD_HIP(hipMemsetAsync(in, 0, hb, st));
+  void *f0 = cv.take(hb), *f1 = cv.take(hb), *f2 = cv.take(hb);
+  WD_HIP(hipMemsetAsync(f0, 0, hb, st));
+  WD_HIP(hipMemsetAsync(f1, 0, hb, st));
+  WD_HIP(hipMemsetAsync(f2, 0, hb, st));
   struct Cand {
     int variant, nr, remap, tblock;
   };
@@ -509,10 +524,12 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
   for (int tb : tbs) {
     if (tb && (ctx->nlat > 1 || ctx->g[0].T % tb)) continue;
     for (int remap = 0; remap < 2; ++remap) {
-      for (int v = wd::HOP_COLOUR; v <= wd::HOP_COLOUR_PAIR; ++v)
+      for (int v = wd::HOP_COLOUR; v <= wd::HOP_COMPACT_PAIR; ++v) {
+        if (!wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, v)) continue;
         for (int nr : {1, 2, 3, 4, 6})
           if (effective_nr(ctx, nr, nrhs, prec, v) == nr) cands.push_back({v, nr, remap, tb});
-      if (wd::hop_variant_ok(ctx->d, wd::HOP_SITE)) {
+      }
+      if (wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, wd::HOP_SITE)) {
         cands.push_back({wd::HOP_SITE, 1, remap, tb});
         if (nrhs % 4 == 0) cands.push_back({wd::HOP_SITE, 4, remap, tb});
       }
@@ -523,13 +540,18 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
   WD_HIP(hipEventCreate(&e1));
   wdirac_tuned &slot = ctx->tuned[prec][nrhs];
   int rc = WDIRAC_OK;
-  // Mean time of `reps` back-to-back launches of candidate cd (after 3 untimed).
+  // Mean time of `reps` back-to-back launches of candidate cd (after 4
+  // untimed), alternating D_eo f0 -> f1 and D_oe f1 -> f2: every other
+  // launch reads the output just written, as between the hops of a solver.
   auto time_cand = [&](const Cand &cd, int reps, float *ms) {
     slot = wdirac_tuned{1, cd.variant, cd.nr, cd.remap, cd.tblock};
-    for (int k = 0; k < 3 && rc == WDIRAC_OK; ++k) rc = hop(ctx, out, in, UR, 0, 0, nrhs, 0.0, nullptr, 1.0, prec, nullptr, st);
+    auto launch = [&](int k) {
+      return hop(ctx, (k & 1) ? f2 : f1, (k & 1) ? f1 : f0, UR, k & 1, 0, nrhs, 0.0, nullptr, 1.0, prec, nullptr,
+                 st);
+    };
+    for (int k = 0; k < 4 && rc == WDIRAC_OK; ++k) rc = launch(k);
     if (rc == WDIRAC_OK && hipEventRecord(e0, st) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventRecord");
-    for (int k = 0; k < reps && rc == WDIRAC_OK; ++k)
-      rc = hop(ctx, out, in, UR, k & 1, 0, nrhs, 0.0, nullptr, 1.0, prec, nullptr, st);
+    for (int k = 0; k < reps && rc == WDIRAC_OK; ++k) rc = launch(k);
     if (rc == WDIRAC_OK && hipEventRecord(e1, st) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventRecord");
     if (rc == WDIRAC_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventSynchronize");
     *ms = 0.0f;
@@ -611,7 +633,11 @@ int wdirac_rep_links(const wdirac_ctx *ctx, void *UR, const void *U, int prec, v
   for (int l = 0; l < ctx->nlat; ++l) {
     const char *Ul = static_cast<const char *>(U) + (size_t)ctx->vpre[l] * 4 * ctx->N * ctx->N * 16;
     char *URl = static_cast<char *>(UR) + (size_t)8 * ctx->d * ctx->d * ctx->spre[l] * el;
-    WD_HIP(wd::launch_rep_links(Ul, URl, ctx->g[l], ctx->N, ctx->rep, prec, S(stream)));
+    char *Fl = nullptr;
+    if (wd::compact_links_ok(ctx->N, ctx->rep))
+      Fl = static_cast<char *>(UR) + rep_links_bytes(ctx, prec) +
+           (size_t)8 * ctx->N * ctx->N * ctx->spre[l] * (prec == WDIRAC_F64 ? 16 : 8);
+    WD_HIP(wd::launch_rep_links(Ul, URl, Fl, ctx->g[l], ctx->N, ctx->rep, prec, S(stream)));
   }
   return WDIRAC_OK;
 }

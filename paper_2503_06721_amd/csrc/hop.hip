@@ -19,6 +19,7 @@
 //    for large representations.
 #include "wd_common.h"
 #include "wd_kernels.h"
+#include "wd_rep.h"
 
 namespace wd {
 
@@ -226,16 +227,76 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W))) void k
 // Stage: this lane's link entries (row `row` of U for a forward hop, column
 // `row` of U for a backward hop, whose U^+ row is the conjugated column) and
 // colour component `row` of the neighbour spinor, spin-projected into LDS.
-template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, int NR, bool NTL>
+//
+// Compact form (FLY = 2 SYM, 3 2AS): the entries are rebuilt from the
+// fundamental link, (U_R)_AB = n_A n_B (U_ac U_bd +- U_ad U_bc) with
+// (a, b) = pair(A), (c, d) = pair(B), n = 1/sqrt2 on the diagonal pairs of
+// SYM and 1 otherwise -- the closed forms of wd_rep.h.  Row `row` of U_R needs
+// the fundamental rows a, b; column `row` (backward hop) the columns a, b.
+// The boundary phase is stored as i U (the maps are quadratic).
+template <int D, bool SYM>
+constexpr int two_index_n() {
+  return SYM ? (D == 3 ? 2 : D == 6 ? 3 : 4) : (D == 3 ? 3 : D == 6 ? 4 : 5);
+}
+
+// First and second index of two-index basis element A, at compile time.
+constexpr int pair_first(int N, bool SYM, int A) {
+  int a = 0, rem = A;
+  while (rem >= (SYM ? N - a : N - 1 - a)) {
+    rem -= SYM ? N - a : N - 1 - a;
+    ++a;
+  }
+  return a;
+}
+constexpr int pair_second(int N, bool SYM, int A) {
+  int a = 0, rem = A;
+  while (rem >= (SYM ? N - a : N - 1 - a)) {
+    rem -= SYM ? N - a : N - 1 - a;
+    ++a;
+  }
+  return a + rem + (SYM ? 0 : 1);
+}
+
+// u[B] = nA nB (x[c] y[d] +- x[d] y[c]), (c, d) = pair(B), unrolled over B so
+// that every register index is a constant.
+template <int D, int N, bool SYM, typename T, int B = 0>
+__device__ __forceinline__ void rebuild_row(cplx<T> (&u)[D], const cplx<T> (&xr)[N], const cplx<T> (&yr)[N], T na) {
+  if constexpr (B < D) {
+    constexpr int c = pair_first(N, SYM, B), d = pair_second(N, SYM, B);
+    const T nn = (SYM && c == d) ? na * (T)0.70710678118654752440 : na;
+    const cplx<T> p = cmul(xr[c], yr[d]), q = cmul(xr[d], yr[c]);
+    u[B] = SYM ? mk<T>(nn * (p.re + q.re), nn * (p.im + q.im)) : mk<T>(nn * (p.re - q.re), nn * (p.im - q.im));
+    rebuild_row<D, N, SYM, T, B + 1>(u, xr, yr, na);
+  }
+}
+
+template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, int NR, bool NTL, int FLY>
 __device__ __forceinline__ void cs_stage(typename LinkT<T, REAL>::type (&u)[D], cplx<T> (*hs)[2][D][64],
                                          const Geom &g, int parity, const typename LinkT<T, REAL>::type *links,
-                                         const cplx<T> *in0, size_t rstride, int nb, int lsite, int row, int lane) {
+                                         const cplx<T> *flinks, const cplx<T> *in0, size_t rstride, int nb,
+                                         int lsite, int row, int lane) {
   using L = typename LinkT<T, REAL>::type;
   const int stride = g.stride;
   const int lpar = BWD ? 1 - parity : parity;
-  const L *lk = links + (size_t)(lpar * 4 + MU) * D * D * stride;
+  if constexpr (FLY != 0) {
+    constexpr bool SYM = FLY == 2;
+    constexpr int N = two_index_n<D, SYM>();
+    const cplx<T> *fk = flinks + (size_t)(lpar * 4 + MU) * N * N * stride + lsite;
+    int a1, a2;
+    pair_of<N, SYM>(row, a1, a2);
+    cplx<T> xr[N], yr[N];
 #pragma unroll
-  for (int b = 0; b < D; ++b) u[b] = ld_stream<NTL>(lk + (size_t)(BWD ? b * D + row : row * D + b) * stride + lsite);
+    for (int c = 0; c < N; ++c) {
+      xr[c] = ld_stream<NTL>(fk + (size_t)(BWD ? c * N + a1 : a1 * N + c) * stride);
+      yr[c] = ld_stream<NTL>(fk + (size_t)(BWD ? c * N + a2 : a2 * N + c) * stride);
+    }
+    rebuild_row<D, N, SYM, T>(u, xr, yr, (SYM && a1 == a2) ? (T)0.70710678118654752440 : (T)1);
+  } else {
+    const L *lk = links + (size_t)(lpar * 4 + MU) * D * D * stride;
+#pragma unroll
+    for (int b = 0; b < D; ++b)
+      u[b] = ld_stream<NTL>(lk + (size_t)(BWD ? b * D + row : row * D + b) * stride + lsite);
+  }
 #pragma unroll
   for (int k = 0; k < NR; ++k) {
     const cplx<T> *in = in0 + k * rstride;
@@ -273,26 +334,31 @@ __device__ __forceinline__ void cs_compute(cplx<T> (&acc)[NR][4], const typename
 // phases (LDS buffers 0 and 1).  PAIR = true: both are staged before a single
 // barrier (LDS buffers 2*(MU&1) and 2*(MU&1)+1), which halves the barriers and
 // doubles the loads in flight per phase at the cost of twice the LDS.
-template <int D, bool REAL, typename T, int MU, int SF, int NR, bool PAIR, bool NTL, int NB>
+template <int D, bool REAL, typename T, int MU, int SF, int NR, bool PAIR, bool NTL, int NB, int FLY>
 __device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64], const Geom &g, int parity,
-                                      const typename LinkT<T, REAL>::type *links, const cplx<T> *in0, size_t rstride,
-                                      int t, int x, int y, int z, int is, int row, int lane) {
+                                      const typename LinkT<T, REAL>::type *links, const cplx<T> *flinks,
+                                      const cplx<T> *in0, size_t rstride, int t, int x, int y, int z, int is, int row,
+                                      int lane) {
   using L = typename LinkT<T, REAL>::type;
   const int nbf = nb_index(g, t, x, y, z, MU, 1);
   const int nbb = nb_index(g, t, x, y, z, MU, 0);
   L uf[D], ub[D];
   if constexpr (PAIR) {
     constexpr int B0 = 2 * (MU & 1);
-    cs_stage<D, REAL, T, MU, SF, false, NR, NTL>(uf, hs[B0], g, parity, links, in0, rstride, nbf, is, row, lane);
-    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL>(ub, hs[B0 + 1], g, parity, links, in0, rstride, nbb, nbb, row, lane);
+    cs_stage<D, REAL, T, MU, SF, false, NR, NTL, FLY>(uf, hs[B0], g, parity, links, flinks, in0, rstride, nbf, is,
+                                                      row, lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL, FLY>(ub, hs[B0 + 1], g, parity, links, flinks, in0, rstride, nbb,
+                                                      nbb, row, lane);
     __syncthreads();
     cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[B0], lane);
     cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[B0 + 1], lane);
   } else {
-    cs_stage<D, REAL, T, MU, SF, false, NR, NTL>(uf, hs[0], g, parity, links, in0, rstride, nbf, is, row, lane);
+    cs_stage<D, REAL, T, MU, SF, false, NR, NTL, FLY>(uf, hs[0], g, parity, links, flinks, in0, rstride, nbf, is,
+                                                      row, lane);
     __syncthreads();
     cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[0], lane);
-    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL>(ub, hs[1], g, parity, links, in0, rstride, nbb, nbb, row, lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL, FLY>(ub, hs[1], g, parity, links, flinks, in0, rstride, nbb, nbb,
+                                                      row, lane);
     __syncthreads();
     cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[1], lane);
   }
@@ -300,7 +366,7 @@ __device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2
 
 // NTL: links read with streaming loads (set when the launch has a single
 // group of right-hand sides, so that no other block re-reads them).
-template <int D, bool REAL, typename T, bool DAG, int NR, bool PAIR, bool NTL, int W>
+template <int D, bool REAL, typename T, bool DAG, int NR, bool PAIR, bool NTL, int W, int FLY>
 __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) void k_hop_cs(HopArgs a) {
   constexpr int NB = PAIR ? 4 : 2;   // LDS buffers
   __shared__ cplx<T> hs[NB][NR][2][D][64];
@@ -327,6 +393,7 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
   const size_t fbase = (size_t)a.lat[l].soff + r0 * rstride;
   const cplx<T> *in0 = static_cast<const cplx<T> *>(a.in) + fbase;
   const L *links = static_cast<const L *>(a.links) + a.lat[l].loff;
+  const cplx<T> *flinks = FLY ? static_cast<const cplx<T> *>(a.flinks) + a.lat[l].floff : nullptr;
   int t, x, y, z;
   cb_coords(g, is, a.parity, t, x, y, z);
   cplx<T> acc[NR][4];
@@ -335,10 +402,14 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[k][s] = mk<T>(0, 0);
   constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
-  cs_mu<D, REAL, T, 0, SF, NR, PAIR, NTL, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
-  cs_mu<D, REAL, T, 1, SF, NR, PAIR, NTL, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
-  cs_mu<D, REAL, T, 2, SF, NR, PAIR, NTL, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
-  cs_mu<D, REAL, T, 3, SF, NR, PAIR, NTL, NB>(acc, hs, g, a.parity, links, in0, rstride, t, x, y, z, is, row, lane);
+  cs_mu<D, REAL, T, 0, SF, NR, PAIR, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+                                                     is, row, lane);
+  cs_mu<D, REAL, T, 1, SF, NR, PAIR, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+                                                     is, row, lane);
+  cs_mu<D, REAL, T, 2, SF, NR, PAIR, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+                                                     is, row, lane);
+  cs_mu<D, REAL, T, 3, SF, NR, PAIR, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+                                                     is, row, lane);
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
   // Two straight-line epilogues (with and without x_add): every accumulator
   // is used on both paths, so no arithmetic is sunk behind a branch.  The
@@ -439,31 +510,61 @@ static void set_tiles(HopArgs &a, int ts, int nrhs, Counts *counts, int *prow) {
   }
 }
 
-template <int D, bool REAL, typename T, bool DAG, int NR, bool NTL>
+// The compact forms hold the fundamental rows besides the rebuilt entries:
+// one wave per SIMD fewer for the paired form and for several rhs, so that
+// they compile without spills.
+constexpr int cs_waves_form(int D, bool dbl, int NR, bool pair, int fly) {
+  const int w = cs_waves(D, dbl, NR) - (fly ? (pair ? 1 : 0) + (NR > 1 ? 1 : 0) : 0);
+  return w > 1 ? w : 1;
+}
+
+template <int D, bool REAL, typename T, bool DAG, int NR, bool NTL, int FLY>
 static hipError_t launch_cs2(const HopArgs &a, int pair, hipStream_t st) {
-  constexpr int W = cs_waves(D, sizeof(T) == 8, NR);
+  constexpr int WU = cs_waves_form(D, sizeof(T) == 8, NR, false, FLY);
+  constexpr int WP = cs_waves_form(D, sizeof(T) == 8, NR, true, FLY);
   dim3 grid(a.ntiles * a.ngroups);
   if constexpr (NR <= 4 && cs_fits<D, T, NR, true>()) {
     if (pair) {
-      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, true, NTL, W>), grid, dim3(64 * D), 0, st, a);
+      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, true, NTL, WP, FLY>), grid, dim3(64 * D), 0, st, a);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, false, NTL, W>), grid, dim3(64 * D), 0, st, a);
+  hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, false, NTL, WU, FLY>), grid, dim3(64 * D), 0, st, a);
   return hipGetLastError();
 }
 
 // Links are streamed when one block group covers all right-hand sides (with
 // several groups the groups of a tile re-read the links from L2).  Only the
 // one-rhs-per-block kernels carry the streaming form.
-template <int D, bool REAL, typename T, bool DAG, int NR>
+template <int D, bool REAL, typename T, bool DAG, int NR, int FLY = 0>
 static hipError_t launch_cs(HopArgs a, int nrhs, int pair, hipStream_t st, Counts *counts, int *prow) {
   set_tiles(a, 64, nrhs, counts, prow);
   a.ngroups = nrhs / NR;
   if constexpr (NR == 1) {
-    if (a.ngroups == 1) return launch_cs2<D, REAL, T, DAG, 1, true>(a, pair, st);
+    if (a.ngroups == 1) return launch_cs2<D, REAL, T, DAG, 1, true, FLY>(a, pair, st);
   }
-  return launch_cs2<D, REAL, T, DAG, NR, false>(a, pair, st);
+  return launch_cs2<D, REAL, T, DAG, NR, false, FLY>(a, pair, st);
+}
+
+// Compact forms: 1 or 2 right-hand sides per block (more spill registers).
+template <int D, typename T, bool DAG, int FLY>
+static hipError_t launch_compact(const HopArgs &a0, int nrhs, int pair, int nr, hipStream_t st, Counts *counts,
+                                 int *prow) {
+  if (nr >= 2 && nrhs % 2 == 0) {
+    if constexpr (cs_fits<D, T, 2, false>())
+      return launch_cs<D, false, T, DAG, 2, FLY>(a0, nrhs, pair, st, counts, prow);
+  }
+  return launch_cs<D, false, T, DAG, 1, FLY>(a0, nrhs, pair, st, counts, prow);
+}
+
+template <int D, int FLY>
+static hipError_t compact_d(const HopArgs &a, int prec, int dagger, int nrhs, int pair, int nr, hipStream_t st,
+                            Counts *c, int *prow) {
+  if (prec == 0)
+    return dagger ? launch_compact<D, double, true, FLY>(a, nrhs, pair, nr, st, c, prow)
+                  : launch_compact<D, double, false, FLY>(a, nrhs, pair, nr, st, c, prow);
+  return dagger ? launch_compact<D, float, true, FLY>(a, nrhs, pair, nr, st, c, prow)
+                : launch_compact<D, float, false, FLY>(a, nrhs, pair, nr, st, c, prow);
 }
 
 template <int D, bool REAL, typename T, bool DAG>
@@ -515,8 +616,16 @@ static hipError_t launch_d(const HopArgs &a, int prec, int dagger, int nrhs, int
                 : launch_typed<D, REAL, float, false>(a, nrhs, variant, nr, st, c, prow);
 }
 
-hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant, int nr,
-                      hipStream_t st, Counts *counts, int *prow) {
+hipError_t launch_hop(const HopArgs &a, int N, int rep, int d, int real, int prec, int dagger, int nrhs, int variant,
+                      int nr, hipStream_t st, Counts *counts, int *prow) {
+  if (variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR) {
+    const int pair = variant == HOP_COMPACT_PAIR;
+    if (rep == 2 && N == 2) return compact_d<3, 2>(a, prec, dagger, nrhs, pair, nr, st, counts, prow);
+    if (rep == 2 && N == 3) return compact_d<6, 2>(a, prec, dagger, nrhs, pair, nr, st, counts, prow);
+    if (rep == 2 && N == 4) return compact_d<10, 2>(a, prec, dagger, nrhs, pair, nr, st, counts, prow);
+    if (rep == 3 && N == 4) return compact_d<6, 3>(a, prec, dagger, nrhs, pair, nr, st, counts, prow);
+    return hipErrorInvalidValue;
+  }
   if (real) {
     switch (d) {
       case 3: return launch_d<3, true>(a, prec, dagger, nrhs, variant, nr, st, counts, prow);
@@ -536,15 +645,20 @@ hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, i
 }
 
 bool hop_nr_supported(int d, int prec, int variant, int nr) {
-  // as cs_fits and cs6_ok
-  const int cb = prec == 0 ? 16 : 8, nbuf = variant == HOP_COLOUR_PAIR ? 4 : 2;
+  // as cs_fits, cs6_ok and launch_compact
+  const int cb = prec == 0 ? 16 : 8;
+  const int nbuf = (variant == HOP_COLOUR_PAIR || variant == HOP_COMPACT_PAIR) ? 4 : 2;
   if (nr < 1 || nr > 6 || nr == 5) return false;
   if (nr == 6 && (variant != HOP_COLOUR || d > 4)) return false;
+  if ((variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR) && nr > 2) return false;
   return nbuf * nr * 2 * d * 64 * cb <= LDS_BUDGET;
 }
 
-bool hop_variant_ok(int d, int variant) {
+bool compact_links_ok(int N, int rep) { return (rep == 2 && N >= 2 && N <= 4) || (rep == 3 && N == 4); }
+
+bool hop_variant_ok(int N, int rep, int d, int variant) {
   if (variant == HOP_SITE) return d <= 6;
+  if (variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR) return compact_links_ok(N, rep);
   return variant == HOP_COLOUR || variant == HOP_COLOUR_PAIR;
 }
 

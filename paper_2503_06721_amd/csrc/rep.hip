@@ -17,7 +17,7 @@ __device__ __forceinline__ void store_entry(void *base, size_t off, cplx<double>
 
 template <int N, int REP, typename T>
 __global__ __launch_bounds__(256) void k_rep_links(const cplx<double> *__restrict__ U, void *__restrict__ UR,
-                                                    Geom g) {
+                                                    void *__restrict__ F, Geom g) {
   constexpr int D = rep_dim(N, REP);
   const int V = 2 * g.Vh;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,36 +43,48 @@ __global__ __launch_bounds__(256) void k_rep_links(const cplx<double> *__restric
   for (int A = 0; A < D; ++A)
     for (int B = 0; B < D; ++B)
       store_entry<T>(UR, base + (size_t)(A * D + B) * es, rep_entry<N, REP>(u, A, B), sign, REP == 1);
+  if (F) {
+    // compact fundamental copy: i U where the phase is -1
+    const size_t fb = (size_t)(par * 4 + mu) * N * N * g.stride + cb;
+    cplx<T> *f = static_cast<cplx<T> *>(F);
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        const cplx<double> v = u[i][j];
+        f[fb + (size_t)(i * N + j) * es] = sign < 0.0 ? mk<T>((T)(-v.im), (T)v.re) : mk<T>((T)v.re, (T)v.im);
+      }
+  }
 }
 
 template <int N, int REP>
-static hipError_t rep_launch(const void *U, void *UR, const Geom &g, int prec, hipStream_t st) {
+static hipError_t rep_launch(const void *U, void *UR, void *F, const Geom &g, int prec, hipStream_t st) {
   const int n = 8 * g.Vh;
   dim3 grid((n + 255) / 256);
   if (prec == 0)
-    hipLaunchKernelGGL((k_rep_links<N, REP, double>), grid, dim3(256), 0, st, (const cplx<double> *)U, UR, g);
+    hipLaunchKernelGGL((k_rep_links<N, REP, double>), grid, dim3(256), 0, st, (const cplx<double> *)U, UR, F, g);
   else
-    hipLaunchKernelGGL((k_rep_links<N, REP, float>), grid, dim3(256), 0, st, (const cplx<double> *)U, UR, g);
+    hipLaunchKernelGGL((k_rep_links<N, REP, float>), grid, dim3(256), 0, st, (const cplx<double> *)U, UR, F, g);
   return hipGetLastError();
 }
 
 template <int N>
-static hipError_t rep_launch_n(const void *U, void *UR, const Geom &g, int rep, int prec, hipStream_t st) {
+static hipError_t rep_launch_n(const void *U, void *UR, void *F, const Geom &g, int rep, int prec,
+                               hipStream_t st) {
   switch (rep) {
-    case 0: return rep_launch<N, 0>(U, UR, g, prec, st);
-    case 1: return rep_launch<N, 1>(U, UR, g, prec, st);
-    case 2: return rep_launch<N, 2>(U, UR, g, prec, st);
+    case 0: return rep_launch<N, 0>(U, UR, F, g, prec, st);
+    case 1: return rep_launch<N, 1>(U, UR, F, g, prec, st);
+    case 2: return rep_launch<N, 2>(U, UR, F, g, prec, st);
     case 3:
-      if constexpr (N > 2) return rep_launch<N, 3>(U, UR, g, prec, st);
+      if constexpr (N > 2) return rep_launch<N, 3>(U, UR, F, g, prec, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_rep_links(const void *U, void *UR, const Geom &g, int N, int rep, int prec, hipStream_t st) {
+hipError_t launch_rep_links(const void *U, void *UR, void *F, const Geom &g, int N, int rep, int prec,
+                            hipStream_t st) {
   switch (N) {
-    case 2: return rep_launch_n<2>(U, UR, g, rep, prec, st);
-    case 3: return rep_launch_n<3>(U, UR, g, rep, prec, st);
-    case 4: return rep_launch_n<4>(U, UR, g, rep, prec, st);
+    case 2: return rep_launch_n<2>(U, UR, F, g, rep, prec, st);
+    case 3: return rep_launch_n<3>(U, UR, F, g, rep, prec, st);
+    case 4: return rep_launch_n<4>(U, UR, F, g, rep, prec, st);
   }
   return hipErrorInvalidValue;
 }

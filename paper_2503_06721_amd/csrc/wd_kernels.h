@@ -17,7 +17,10 @@ namespace wd {
 constexpr int MAXSYS = 12;
 constexpr int MAXLAT = 8;
 
-enum { HOP_SITE = 0, HOP_COLOUR = 1, HOP_COLOUR_PAIR = 2 };
+// HOP_COMPACT / HOP_COMPACT_PAIR: the colour-split forms reading the
+// fundamental links and rebuilding the two-index represented entries in
+// registers (SYM and 2AS only, where N^2 < d_R^2).
+enum { HOP_SITE = 0, HOP_COLOUR = 1, HOP_COLOUR_PAIR = 2, HOP_COMPACT = 3, HOP_COMPACT_PAIR = 4 };
 
 // One lattice of a launch.
 struct LatDesc {
@@ -26,6 +29,7 @@ struct LatDesc {
   int ntiles;       // tiles of this lattice (set by the launcher)
   long long soff;   // offset of this lattice in packed half spinors, complex elements
   long long loff;   // offset of this lattice in packed links, link elements
+  long long floff;  // offset of this lattice in the compact fundamental links, complex elements
 };
 
 // Arguments of one hopping-term launch.  Pointers are device memory; fields
@@ -34,6 +38,7 @@ struct HopArgs {
   void *out;
   const void *in;
   const void *links;
+  const void *flinks; // compact fundamental links (HOP_COMPACT forms), boundary phase folded as sqrt(bc)
   const void *xadd;   // nullable
   int nlat;
   LatDesc lat[MAXLAT];
@@ -57,16 +62,23 @@ struct Counts {
 // across the lanes of each wavefront).  On return counts->n[s] holds the
 // number of partial sums written for system s (the tiles of its lattice) and
 // *prow their row length.
-hipError_t launch_hop(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int variant, int nr,
-                      hipStream_t st, Counts *counts, int *prow);
+hipError_t launch_hop(const HopArgs &a, int N, int rep, int d, int real, int prec, int dagger, int nrhs, int variant,
+                      int nr, hipStream_t st, Counts *counts, int *prow);
 // Whether the colour-split form of the given variant takes nr right-hand
 // sides per block (nr in 1..4, or 6 for the unpaired form with d_R <= 4)
 // within the LDS budget.
 bool hop_nr_supported(int d, int prec, int variant, int nr);
-bool hop_variant_ok(int d, int variant);
+bool hop_variant_ok(int N, int rep, int d, int variant);
+// Whether the compact forms exist for (N, rep): SYM for N = 2, 3, 4 and 2AS
+// for N = 4 (where they read fewer bytes than the represented links).
+bool compact_links_ok(int N, int rep);
 
 // rep.hip (one lattice per call; the caller offsets the pointers)
-hipError_t launch_rep_links(const void *U, void *UR, const Geom &g, int N, int rep, int prec, hipStream_t st);
+// F (nullable): also write the compact fundamental links [parity][mu][N*N][stride]
+// complex, multiplied by i where the boundary phase is -1 (the two-index maps
+// are quadratic, so R(i U) = -R(U)).
+hipError_t launch_rep_links(const void *U, void *UR, void *F, const Geom &g, int N, int rep, int prec,
+                            hipStream_t st);
 hipError_t launch_unpack_links(void *canon, const void *UR, const Geom &g, int d, int real, int prec,
                                hipStream_t st);
 hipError_t launch_pack_spinor(void *packed, const void *canon, const Geom &g, int d, int parity, int nrhs,

@@ -30,7 +30,7 @@ FIELD_HALF_SPINOR, FIELD_LINKS, FIELD_CLOVER = 0, 1, 2
 MAX_SHIFTS = 32
 (OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
  OPT_HOP_NR_F32, OPT_TILE_TBLOCK, OPT_CG_GRAPH) = 0, 1, 2, 3, 4, 5, 6, 7, 8
-HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR = 0, 1, 2
+HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR, HOP_COMPACT, HOP_COMPACT_PAIR = 0, 1, 2, 3, 4
 REP_CODES = {'FUND': FUND, 'ADJ': ADJ, 'SYM': SYM, '2AS': ASYM}
 STATUS_NAMES = {OK: 'OK', EINVAL: 'EINVAL', EUNSUPPORTED: 'EUNSUPPORTED', EHIP: 'EHIP',
                 ENOCONV: 'ENOCONV', EBREAKDOWN: 'EBREAKDOWN'}
@@ -174,6 +174,7 @@ class Lattice:
         h = _P()
         _check(_lib.wdirac_create_batch(ctypes.byref(h), self.N, self.rep, geoms, len(shapes)), 'create')
         self._h = h
+        self._destroy = _lib.wdirac_destroy   # kept: module globals may be gone when __del__ runs at exit
         d, real = _I(), _I()
         _check(_lib.wdirac_rep_info(h, ctypes.byref(d), ctypes.byref(real)), 'rep_info')
         self.d, self.real = d.value, bool(real.value)
@@ -182,6 +183,8 @@ class Lattice:
         self.V = sum(self.volumes)
         self.Vh = self.V // 2
         self.nlat = len(shapes)
+        # compact hop forms (fundamental links rebuilt into U_R in registers)
+        self.compact = (self.rep_name == 'SYM' and 2 <= self.N <= 4) or (self.rep_name == '2AS' and self.N == 4)
 
     def nsys(self, nrhs=1):
         """Independent systems of a call: the right-hand sides, or the lattices of a batch."""
@@ -190,7 +193,7 @@ class Lattice:
     def __del__(self):
         h = getattr(self, '_h', None)
         if h:
-            _lib.wdirac_destroy(h)
+            self._destroy(h)
             self._h = None
 
     # ------------------------------------------------------------ sizes

@@ -58,7 +58,10 @@ def test_create_and_rep_info(W, N, rep, d, real):
     Vh, stride = 128, 256
     assert W._lib.wdirac_field_bytes(h, W.FIELD_HALF_SPINOR, 1, W.F64) == 4 * d * stride * 16
     assert W._lib.wdirac_field_bytes(h, W.FIELD_HALF_SPINOR, 3, W.F32) == 3 * 4 * d * stride * 8
-    assert W._lib.wdirac_field_bytes(h, W.FIELD_LINKS, 1, W.F64) == 8 * d * d * stride * 8 * (1 if real else 2)
+    # two-index representations with compact hop forms also hold the fundamental links
+    compact = (rep == 2 and N >= 2) or (rep == 3 and N == 4)
+    assert W._lib.wdirac_field_bytes(h, W.FIELD_LINKS, 1, W.F64) == (8 * d * d * stride * 8 * (1 if real else 2)
+                                                                     + (8 * N * N * stride * 16 if compact else 0))
     assert W._lib.wdirac_workspace_bytes(h, W.OP_CG, 2, W.CG_MIXED) > W._lib.wdirac_workspace_bytes(h, W.OP_CG, 2,
                                                                                                      W.CG_F64)
     assert Vh * 2 == 256
@@ -128,7 +131,7 @@ def test_batch_sizes_and_rejects(W):
     assert rc == W.OK
     strides = [((dd[0] * dd[1] * dd[2] * dd[3] // 2 + 255) // 256) * 256 for dd in shapes]
     assert W._lib.wdirac_field_bytes(h, W.FIELD_HALF_SPINOR, 1, W.F64) == 4 * 6 * sum(strides) * 16
-    assert W._lib.wdirac_field_bytes(h, W.FIELD_LINKS, 1, W.F32) == 8 * 36 * sum(strides) * 8
+    assert W._lib.wdirac_field_bytes(h, W.FIELD_LINKS, 1, W.F32) == (8 * 36 + 8 * 9) * sum(strides) * 8
     dummy = ctypes.c_void_p(0x1000)
     # a batch carries one right-hand side per lattice
     assert W._lib.wdirac_dslash_eo(h, dummy, ctypes.c_void_p(0x2000), dummy, 0, 0, 2, 0.0, None, 1.0, 0,

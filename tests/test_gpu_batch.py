@@ -75,7 +75,8 @@ def test_batch_links_and_hops(W, N, rep):
             assert rel(got[o:o + v].reshape(exp.shape), exp) < TOL[prec]
             o += v
     psi = b.spinors(901)
-    for variant in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR, W.HOP_SITE):
+    for variant in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR, W.HOP_SITE) + (
+            (W.HOP_COMPACT, W.HOP_COMPACT_PAIR) if b.lat.compact else ()):
         for prec in (0, 1):
             b.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, variant)
             for p, dagger in ((0, 0), (1, 1), (0, 1)):

@@ -72,7 +72,8 @@ def hop_expect(s, psi_full, p, dagger, alpha, beta, xadd_full):
 @pytest.mark.parametrize('N,rep', PAIRS)
 def test_dslash_eo(W, N, rep, dims):
     s = Setup(N, rep, dims, seed=200 + N)
-    variants = [W.HOP_COLOUR] + ([W.HOP_SITE] if s.d <= 6 else [])
+    variants = ([W.HOP_COLOUR] + ([W.HOP_SITE] if s.d <= 6 else [])
+                + ([W.HOP_COMPACT, W.HOP_COMPACT_PAIR] if s.lat.compact else []))
     nrhs = 2
     psi = s.spinor(201, nrhs)
     xadd = s.spinor(202, nrhs)
@@ -104,7 +105,8 @@ def test_dslash_rhs_groups(W, N, rep):
         psi = s.spinor(251 + nrhs, nrhs)
         exp = {(p, dagger): hop_expect(s, psi, p, dagger, 0.0, 1.0, None) for p, dagger in ((0, 0), (1, 1))}
         for prec in (0, 1):
-            for variant in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR, W.HOP_SITE):
+            for variant in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR, W.HOP_SITE) + (
+                    (W.HOP_COMPACT, W.HOP_COMPACT_PAIR) if s.lat.compact else ()):
                 s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, variant)
                 for nr in (1, 2, 3, 4, 6):
                     s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, nr)
@@ -278,6 +280,31 @@ def test_cg_modes_and_multi_rhs(W, N, rep, m):
             for k in range(nrhs):
                 _, it_or, _ = OCG.cg(lambda v: D.normal_op(v, s.UR, m, s.bc, s.dims), bs[k], 1e-10, 20000)
                 assert abs(st[k]['iters'] - it_or) <= 2, (k, st[k]['iters'], it_or)
+
+
+@pytest.mark.parametrize('N,rep,m', [(3, 'SYM', -0.4), (4, '2AS', -0.3), (2, 'SYM', -0.2)])
+def test_cg_compact_links(W, N, rep, m):
+    """CG with the compact hop forms (U_R rebuilt from the fundamental links
+    in registers) in FP64 and mixed precision, two right-hand sides."""
+    log(f'cg compact N={N} rep={rep}')
+    s = Setup(N, rep, (4, 6, 4, 6), seed=640 + N, links='expH')
+    assert s.lat.compact
+    bs = [solve_problem(s, m, 650 + k) for k in range(2)]
+    full = np.concatenate([_embed(s, b) for b in bs])
+    for pair in (0, 1):
+        for prec in (0, 1):
+            s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32,
+                             W.HOP_COMPACT_PAIR if pair else W.HOP_COMPACT)
+        for mode in (W.CG_F64, W.CG_MIXED):
+            xg = s.lat.new_half(2)
+            rc, st = s.lat.cg_eo(xg, s.to_gpu_half(full, 0), s.URg[0], m, tol=1e-10, maxit=20000, nrhs=2, mode=mode,
+                                 UR32=s.URg[1])
+            assert rc == W.OK, st
+            xs = s.from_gpu_half(xg, 0, 2)
+            for k in range(2):
+                res = oracle_true_residual(s, xs[k], bs[k], m)
+                log(f'  pair {pair} mode {mode} rhs {k}: iters {st[k]["iters"]} res {res:.3e}')
+                assert res <= 1.05e-10, (pair, mode, k, res)
 
 
 def test_cg_zero_rhs_and_maxit(W):
