@@ -95,20 +95,28 @@ def test_dslash_full_size_sampled(W, name, prec, nrhs):
     g.manual_seed(cfg['seed'] + 7)
     dt = torch.complex128 if prec == 0 else torch.complex64
     psi = torch.randn((nrhs,) + tuple(dims) + (4, lat.d), dtype=dt, device='cuda', generator=g)
-    for p, dagger in ((0, 0), (1, 1)):
-        log(f'  parity {p} dagger {dagger}')
-        inp = lat.pack_half(psi, 1 - p, nrhs, prec)
-        out = lat.new_half(nrhs, prec)
-        lat.dslash_eo(out, inp, UR, p, dagger, nrhs, 0.0, None, 1.0, prec)
-        res = lat.unpack_half(out, p, nrhs, prec)
-        coords = sample_sites(dims, p, NSAMPLE, cfg['seed'] + p)
-        for r in range(0, nrhs, max(1, nrhs // 3)):
-            exp = oracle_hop_sampled(U, psi[r], coords, rep, bc, dims, dagger=bool(dagger))
-            got = gather(res[r], coords).astype(np.complex128)
-            err = rel(got, exp)
-            log(f'    rhs {r}: sampled relative error {err:.2e}')
-            assert err < TOL[prec], err
-        del inp, out, res
+    # the compact forms explicitly (two-index representations), then the
+    # shape the autotuner picks -- the one the benchmark times
+    shapes = [W.HOP_COMPACT, W.HOP_COMPACT_PAIR] if lat.compact and nrhs <= 2 else []
+    for shape in shapes + ['tuned']:
+        if shape == 'tuned':
+            log(f'  autotuned: {lat.autotune(UR, prec, nrhs)}')
+        else:
+            lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, shape)
+        for p, dagger in ((0, 0), (1, 1)):
+            log(f'  shape {shape} parity {p} dagger {dagger}')
+            inp = lat.pack_half(psi, 1 - p, nrhs, prec)
+            out = lat.new_half(nrhs, prec)
+            lat.dslash_eo(out, inp, UR, p, dagger, nrhs, 0.0, None, 1.0, prec)
+            res = lat.unpack_half(out, p, nrhs, prec)
+            coords = sample_sites(dims, p, NSAMPLE, cfg['seed'] + p)
+            for r in range(0, nrhs, max(1, nrhs // 3)):
+                exp = oracle_hop_sampled(U, psi[r], coords, rep, bc, dims, dagger=bool(dagger))
+                got = gather(res[r], coords).astype(np.complex128)
+                err = rel(got, exp)
+                log(f'    rhs {r}: sampled relative error {err:.2e}')
+                assert err < TOL[prec], (shape, err)
+            del inp, out, res
     del U, UR, psi
     torch.cuda.empty_cache()
 
@@ -131,6 +139,8 @@ def test_cg_su4_2as_mixed_vs_f64(W):
     del eta
     b = lat.new_half()
     lat.apply_dhat(b, eta_e, UR64, cfg['m0'], dagger=1)
+    # the launch shapes the benchmark tunes to
+    log(f'  autotuned: {lat.autotune(UR64, W.F64, 1)}, {lat.autotune(UR32, W.F32, 1)}')
     ws = lat.new_workspace(W.OP_CG, 1, W.CG_MIXED)
     out = {}
     for mode in (W.CG_F64, W.CG_MIXED):
