@@ -87,7 +87,9 @@ typedef struct {
   int32_t hops;             /* hopping-term applications issued for this solve       */
   int32_t status;           /* wdirac_status of this right-hand side                 */
   double true_rel_resid;    /* ||b - A x|| / ||b|| recomputed in FP64 at the end      */
-  double seconds;           /* wall time of the whole call                           */
+  double seconds;           /* wall time of the solve: from the point where the work
+                               queued on the stream before the call has finished to
+                               the return                                            */
 } wdirac_cg_stats;
 
 /* Create a context for SU(Ng) fermions in representation `rep` on the lattice

@@ -797,7 +797,6 @@ int wdirac_dot(const wdirac_ctx *ctx, double *out, const void *a, const void *b,
 static int cg_impl(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, const void *UR32,
                    const void *clov64, const void *clov32, double m0, double tol, int maxit, int nrhs, int mode,
                    void *workspace, wdirac_cg_stats *stats, void *stream) {
-  const auto t0 = std::chrono::steady_clock::now();
   WD_TRY(check_ctx(ctx));
   WD_TRY(check_ptr(x, "x"));
   WD_TRY(check_ptr(b, "b"));
@@ -810,15 +809,16 @@ static int cg_impl(const wdirac_ctx *ctx, void *x, const void *b, const void *UR
   if (!(tol > 0.0) || maxit < 0) return fail(WDIRAC_EINVAL, "tol must be > 0 and maxit >= 0");
   if (x == b) return fail(WDIRAC_EINVAL, "x and b must not alias");
   hipStream_t st = S(stream);
+  // the solve starts once the caller's queued work is done: the reported
+  // time is that of the solve alone
+  WD_HIP(hipStreamSynchronize(st));
+  const auto t0 = std::chrono::steady_clock::now();
   if (ctx->cg_graph) {
     // the iterations between host checks are captured once and replayed as
     // a graph; capture needs a stream of the library's own (the caller's may
-    // be the null stream), ordered after the caller's work
+    // be the null stream), ordered after the caller's work (drained above)
     if (!ctx->own && hipStreamCreateWithFlags(&ctx->own, hipStreamNonBlocking) != hipSuccess) ctx->own = nullptr;
-    if (ctx->own) {
-      WD_HIP(hipStreamSynchronize(st));
-      st = ctx->own;
-    }
+    if (ctx->own) st = ctx->own;
   }
   const bool mixed = mode == WDIRAC_CG_MIXED;
   CgWork w = carve_cg(ctx, nrhs, mode, workspace);
@@ -1029,7 +1029,6 @@ int wdirac_cg_eo_clover(const wdirac_ctx *ctx, void *x, const void *b, const voi
 int wdirac_cg_mshift_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64, double m0,
                         const double *shifts, int nshift, double tol, int maxit, void *workspace,
                         wdirac_cg_stats *stats, void *stream) {
-  const auto t0 = std::chrono::steady_clock::now();
   WD_TRY(check_ctx(ctx));
   WD_TRY(check_ptr(x, "x"));
   WD_TRY(check_ptr(b, "b"));
@@ -1051,6 +1050,8 @@ int wdirac_cg_mshift_eo(const wdirac_ctx *ctx, void *x, const void *b, const voi
     if (bs + hb > xs && bs < xs + (size_t)nshift * hb) return fail(WDIRAC_EINVAL, "x and b must not overlap");
   }
   const hipStream_t st = S(stream);
+  WD_HIP(hipStreamSynchronize(st));   // time the solve alone
+  const auto t0 = std::chrono::steady_clock::now();
   MsWork w = carve_ms(ctx, nshift, workspace);
   const wd::FieldShape f = shape(ctx, 1);
   const int nbb = wd::blas_nblocks(f);
