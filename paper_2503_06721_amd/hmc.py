@@ -8,9 +8,13 @@ even-odd pseudofermion action S_f = phi^+ (D-hat^+ D-hat)^{-1} phi; with a
 clover term (csw given; regular, Sec. 6.1.2, or exponential, Sec. 6.1.3) the
 clover D-hat = D_ee - D_eo D_oo^{-1} D_oe and the odd-block determinant term
 S_det = -2 sum_{x odd} log|det D_oo| (det D = det D_oo det D-hat).
-Integrators: leapfrog (PQP) and second-order Omelyan (PQPQP).  Every
+Integrators: leapfrog (PQP) and second-order Omelyan (PQPQP).  An HMC
+update (Sec. 5.3) draws the momenta and the pseudofermion noise, integrates a
+trajectory and accepts it with probability min(1, exp(-dH)).  Every
 computation runs in the library's kernels; this module only sequences calls.
 """
+import math
+
 import torch
 
 from . import wdirac as W
@@ -119,3 +123,30 @@ class HMC:
             else:
                 lat.apply_dhat_clover(phi, eta, self.UR, self.clov, dagger=1)
         return pi, phi
+
+    def update(self, U, eps, nsteps, generator, integrator='omelyan2'):
+        """One HMC update of the single-lattice field U (in place): momenta
+        with components pi^a ~ N(0, 1) (kinetic term sum tr pi^2 =
+        sum_a (pi^a)^2 / 2), pseudofermion phi = D-hat^+ eta with complex
+        Gaussian eta, E|eta_i|^2 = 1 (so that S_f(phi) = eta^+ eta), one
+        trajectory, and the Metropolis test against a uniform draw.  The
+        draws come from `generator` (a seeded torch.Generator on the GPU).
+        Returns (dH, accepted)."""
+        lat = self.lat
+        N = lat.N
+        dims = tuple(U.shape[:4])
+        w = torch.randn(dims + (4, N * N - 1), dtype=torch.float64, device=U.device, generator=generator)
+        eta_e = None
+        if self.with_fermions:
+            re = torch.randn((1,) + dims + (4, lat.d), dtype=torch.float64, device=U.device, generator=generator)
+            im = torch.randn((1,) + dims + (4, lat.d), dtype=torch.float64, device=U.device, generator=generator)
+            eta_e = lat.pack_half(torch.complex(re, im) * (0.5 ** 0.5), 0)
+        pi, phi = self.refresh(U, w, eta_e)
+        U0 = U.clone()
+        H0, H1 = self.trajectory(U, pi, phi, eps, nsteps, integrator)
+        dH = H1 - H0
+        r = torch.rand((1,), dtype=torch.float64, device=U.device, generator=generator).item()
+        accepted = dH <= 0.0 or r < math.exp(-dH)
+        if not accepted:
+            U.copy_(U0)
+        return dH, accepted

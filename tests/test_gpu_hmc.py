@@ -4,7 +4,9 @@ whole Omelyan trajectory with fermions against the oracle's trajectory from
 the same inputs; and, on an 8^4 lattice, reversibility and the O(eps^2)
 energy-error scaling of both integrators (the paper's table of integrators);
 the same with a clover term (regular and exponential), against the oracle's
-clover trajectory and, on 8^4, in its energy-error scaling."""
+clover trajectory and, on 8^4, in its energy-error scaling; and the
+algorithmic tests of Sec. 7 (Creutz equality, acceptance rate) on a
+thermalised SU(2) adjoint ensemble."""
 import numpy as np
 import pytest
 import torch
@@ -159,3 +161,40 @@ def test_clover_energy_error_scaling_8x8x8x8(W, expo):
         dH.append(abs(H1 - H0))
     log(f'  clover expo={expo}: |dH| {dH}')
     assert 3.3 < dH[0] / dH[1] < 4.8 and 3.6 < dH[1] / dH[2] < 4.4
+
+
+def test_creutz_equality_and_acceptance(W):
+    """The algorithmic tests of Sec. 7 on SU(2) with two adjoint flavours
+    (4^4, beta = 2.2): after thermalisation, the Creutz equality
+    <exp(-dH)> = 1, a positive <dH>, and the acceptance rate against
+    erfc(sqrt(<dH^2>/8)), each within four standard errors."""
+    from paper_2503_06721_amd.hmc import HMC
+    dims, N, rep = (4, 4, 4, 4), 2, 'ADJ'
+    lat = W.Lattice(N, rep, dims, APBC)
+    hmc = HMC(lat, 2.2, -0.5, tol=1e-12)
+    U = torch.from_numpy(synth.expH_links(dims, N, 0.3, 860)).cuda()
+    g = torch.Generator(device='cuda')
+    g.manual_seed(861)
+    # step size for an acceptance near 85%: dH is large enough for the tests
+    # to bite, and exp(-dH) has no heavy tail that a finite sample misses
+    for _ in range(60):
+        hmc.update(U, 0.25, 4, g)
+    dH, acc = [], []
+    for _ in range(300):
+        d, a = hmc.update(U, 0.25, 4, g)
+        dH.append(d)
+        acc.append(a)
+    dH = np.array(dH)
+    n = len(dH)
+    e = np.exp(-dH)
+    creutz, se = e.mean(), e.std(ddof=1) / np.sqrt(n)
+    p_obs = float(np.mean(acc))
+    from scipy.special import erfc
+    p_exp = float(erfc(np.sqrt(np.mean(dH ** 2) / 8.0)))
+    sp = np.sqrt(p_exp * (1 - p_exp) / n)
+    log(f'  <exp(-dH)> = {creutz:.4f} +- {se:.4f}; <dH> = {dH.mean():.4f} +- {dH.std(ddof=1) / np.sqrt(n):.4f}; '
+        f'acceptance {p_obs:.3f} (erfc prediction {p_exp:.3f} +- {sp:.3f}); CG iterations {hmc.cg_iters}')
+    assert 0.6 < p_obs < 0.97, 'step size outside the range the test is meant for'
+    assert abs(creutz - 1.0) < 4 * se
+    assert dH.mean() > -4 * dH.std(ddof=1) / np.sqrt(n)
+    assert abs(p_obs - p_exp) < 4 * sp + 1.0 / n
