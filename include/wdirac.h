@@ -325,7 +325,9 @@ int wdirac_cg_eo(const wdirac_ctx *ctx, void *x, const void *b, const void *UR64
  * packed clover field (wdirac_field_bytes(ctx, WDIRAC_FIELD_CLOVER, 1, prec)
  * bytes, precision prec) holds, per site, the two 2d x 2d chirality blocks:
  * D_ee on the even sites and D_oo^{-1} on the odd sites, which is what
- * D-hat = D_ee - D_eo D_oo^{-1} D_oe (Sec. 5.3.3) applies.  Computed in FP64.
+ * D-hat = D_ee - D_eo D_oo^{-1} D_oe (Sec. 5.3.3) applies.  The blocks are
+ * Hermitian and only their upper triangles (d(2d+1) complex entries each)
+ * are stored.  Computed in FP64.
  * workspace: wdirac_workspace_bytes(ctx, WDIRAC_OP_CLOVER, 1, WDIRAC_F64).
  * Errors: EINVAL, EUNSUPPORTED (d_R not in {2, 3, 4, 6}), EHIP. */
 int wdirac_clover_field(const wdirac_ctx *ctx, void *clov, const void *U, double m0, double csw, int exponential,

@@ -256,7 +256,7 @@ int clover_apply(const wdirac_ctx *c, void *out, const void *in, const void *clo
   const size_t cb = prec == WDIRAC_F64 ? 16 : 8;
   for (int l = 0; l < c->nlat; ++l) {
     const size_t so = (size_t)4 * c->d * c->spre[l] * cb;
-    const size_t co = (size_t)16 * c->d * c->d * c->spre[l] * cb;
+    const size_t co = (size_t)4 * c->d * (2 * c->d + 1) * c->spre[l] * cb;
     WD_HIP(wd::launch_clover_apply(static_cast<char *>(out) + so, static_cast<const char *>(in) + so,
                                    static_cast<const char *>(clov) + co, c->g[l], c->d, parity, nrhs, prec, st));
   }
@@ -418,7 +418,7 @@ size_t wdirac_field_bytes(const wdirac_ctx *ctx, int kind, int nrhs, int prec) {
   }
   if (kind == WDIRAC_FIELD_LINKS) return rep_links_bytes(ctx, prec) + compact_links_bytes(ctx, prec);
   if (kind == WDIRAC_FIELD_CLOVER)
-    return wd::clover_supported(ctx->d) ? (size_t)16 * ctx->d * ctx->d * ctx->spre[ctx->nlat] * 2 * el : 0;
+    return wd::clover_supported(ctx->d) ? (size_t)4 * ctx->d * (2 * ctx->d + 1) * ctx->spre[ctx->nlat] * 2 * el : 0;
   return 0;
 }
 
@@ -979,7 +979,7 @@ int wdirac_clover_field(const wdirac_ctx *ctx, void *clov, const void *U, double
   const size_t el = prec == WDIRAC_F64 ? 8 : 4;
   for (int l = 0; l < ctx->nlat; ++l) {
     const char *Ul = static_cast<const char *>(U) + (size_t)ctx->vpre[l] * 4 * ctx->N * ctx->N * 16;
-    char *cl = static_cast<char *>(clov) + (size_t)16 * ctx->d * ctx->d * ctx->spre[l] * 2 * el;
+    char *cl = static_cast<char *>(clov) + (size_t)4 * ctx->d * (2 * ctx->d + 1) * ctx->spre[l] * 2 * el;
     WD_HIP(wd::launch_clover_field(cl, Ul, static_cast<double *>(workspace), ctx->g[l], ctx->N, ctx->rep, ctx->d, m0,
                                    csw, exponential, prec, S(stream)));
   }
@@ -1313,7 +1313,9 @@ int wdirac_force_eo(const wdirac_ctx *ctx, void *P, const void *x_e, const void 
 }
 
 // ------------------------------------------------------------ clover force
-static size_t clover_offset(const wdirac_ctx *c, int l) { return (size_t)16 * c->d * c->d * c->spre[l] * 2 * 8; }
+static size_t clover_offset(const wdirac_ctx *c, int l) {
+  return (size_t)4 * c->d * (2 * c->d + 1) * c->spre[l] * 2 * 8;
+}
 
 static int clover_force_checks(const wdirac_ctx *ctx, const void *P, const void *U, const void *clov64, double m0,
                                double csw, int exponential, int gradient, int accumulate, const void *workspace) {

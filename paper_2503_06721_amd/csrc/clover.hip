@@ -12,7 +12,9 @@
 // diag(1,1,-1,-1), so each site holds two 2d x 2d chirality blocks (spins
 // {0,1} and {2,3}).  Stored per parity: the even sites keep the blocks
 // (D_ee), the odd sites their inverses (D_oo^{-1}), which is what the
-// even-odd operator D-hat = D_ee - D_eo D_oo^{-1} D_oe applies.
+// even-odd operator D-hat = D_ee - D_eo D_oo^{-1} D_oe applies.  All these
+// blocks are Hermitian, so only the upper triangle (row-major, diagonal
+// included: 2d(2d+1)/2 complex entries) is stored.
 #include "wd_common.h"
 #include "wd_kernels.h"
 #include "wd_rep.h"
@@ -23,6 +25,18 @@ namespace wd {
 __device__ __forceinline__ void plane_dirs(int p, int &mu, int &nu) {
   mu = p < 3 ? 0 : p < 5 ? 1 : 2;
   nu = p < 3 ? p + 1 : p < 5 ? p - 1 : 3;
+}
+
+// Position of entry (i, j), i <= j, of the packed upper triangle of an
+// NB x NB Hermitian block; entry (j, i) is its conjugate.
+__host__ __device__ constexpr int tri_index(int NB, int i, int j) { return i * NB - i * (i - 1) / 2 + (j - i); }
+
+// Entry (i, j) of a packed Hermitian block (any i, j).
+template <typename T>
+__device__ __forceinline__ cplx<T> herm_entry(const cplx<T> *P, size_t es, int NB, int i, int j) {
+  if (i <= j) return P[(size_t)tri_index(NB, i, j) * es];
+  const cplx<T> v = P[(size_t)tri_index(NB, j, i) * es];
+  return mk<T>(v.re, -v.im);
 }
 
 // Lexicographic index of c + a e_mu + b e_nu (periodic wrap).
@@ -271,9 +285,14 @@ __global__ __launch_bounds__(64) void k_clover_finish(const cplx<double> *__rest
     for (int i = 0; i < NB; ++i)
       for (int j = 0; j < NB; ++j) out[i][j] = sc * out[i][j];
   }
-  cplx<T> *dst = static_cast<cplx<T> *>(clov) + ((size_t)(par * 2 + c) * NB * NB) * g.stride + cb;
+  constexpr int NT = NB * (NB + 1) / 2;
+  cplx<T> *dst = static_cast<cplx<T> *>(clov) + ((size_t)(par * 2 + c) * NT) * g.stride + cb;
   for (int i = 0; i < NB; ++i)
-    for (int j = 0; j < NB; ++j) dst[(size_t)(i * NB + j) * g.stride] = mk<T>((T)out[i][j].re, (T)out[i][j].im);
+    for (int j = i; j < NB; ++j) {
+      // the computed block is Hermitian up to rounding: store the mean of (i,j) and conj(j,i)
+      const double re = 0.5 * (out[i][j].re + out[j][i].re), im = 0.5 * (out[i][j].im - out[j][i].im);
+      dst[(size_t)tri_index(NB, i, j) * g.stride] = mk<T>((T)re, (T)(i == j ? 0.0 : im));
+    }
 }
 
 // out = M_c in on the sites of `parity` (thread per (site, rhs, block); the
@@ -291,14 +310,22 @@ __global__ __launch_bounds__(256) void k_clover_apply(cplx<T> *out, const cplx<T
   cplx<T> v[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) v[k] = in[rbase + (size_t)(2 * c * D + k) * g.stride];
-  const cplx<T> *M = clov + ((size_t)(parity * 2 + c) * NB * NB) * g.stride + i;
+  constexpr int NT = NB * (NB + 1) / 2;
+  const cplx<T> *M = clov + ((size_t)(parity * 2 + c) * NT) * g.stride + i;
   cplx<T> w[NB];
 #pragma unroll
-  for (int a = 0; a < NB; ++a) {
-    cplx<T> s = mk<T>(0, 0);
+  for (int a = 0; a < NB; ++a) w[a] = mk<T>(0, 0);
+  // each stored entry (a, b), a <= b, serves (a, b) and, conjugated, (b, a)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) s = cfma(M[(size_t)(a * NB + b) * g.stride], v[b], s);
-    w[a] = s;
+  for (int a = 0; a < NB; ++a) {
+    const cplx<T> d = M[(size_t)tri_index(NB, a, a) * g.stride];
+    w[a] = cfma(d, v[a], w[a]);
+#pragma unroll
+    for (int b = a + 1; b < NB; ++b) {
+      const cplx<T> m = M[(size_t)tri_index(NB, a, b) * g.stride];
+      w[a] = cfma(m, v[b], w[a]);
+      w[b] = cfma_conj(m, v[a], w[b]);
+    }
   }
 #pragma unroll
   for (int k = 0; k < NB; ++k) out[rbase + (size_t)(2 * c * D + k) * g.stride] = w[k];
@@ -552,9 +579,9 @@ __global__ __launch_bounds__(64) void k_clover_insert(const cplx<double> *Xe, co
         Om[i][j] = mk(xv[i].re * yv[j].re + xv[i].im * yv[j].im, xv[i].im * yv[j].re - xv[i].re * yv[j].im);
   }
   if (cdet != 0.0 && par == 1) {
-    const cplx<double> *Mi = clov + (size_t)(2 + c) * NB * NB * g.stride + cb;
+    const cplx<double> *Mi = clov + (size_t)(2 + c) * (NB * (NB + 1) / 2) * g.stride + cb;
     for (int i = 0; i < NB; ++i)
-      for (int j = 0; j < NB; ++j) Om[i][j] = Om[i][j] + cdet * Mi[(size_t)(i * NB + j) * g.stride];
+      for (int j = 0; j < NB; ++j) Om[i][j] = Om[i][j] + cdet * herm_entry(Mi, g.stride, NB, i, j);
   }
   if constexpr (EXPO) {
     // A = (i/4) c_sw sum_p S[p][c][s][t] F_p[a][b] / (4 + m), as in k_clover_finish
@@ -748,10 +775,10 @@ __global__ __launch_bounds__(64) void k_clover_logdet(const cplx<double> *__rest
   if (gid < 2 * (size_t)g.Vh) {
     const int c = (int)(gid / g.Vh);
     const size_t cb = gid - (size_t)c * g.Vh;
-    const cplx<double> *Mi = clov + (size_t)(2 + c) * NB * NB * g.stride + cb;
+    const cplx<double> *Mi = clov + (size_t)(2 + c) * (NB * (NB + 1) / 2) * g.stride + cb;
     cplx<double> a[NB][NB];
     for (int i = 0; i < NB; ++i)
-      for (int j = 0; j < NB; ++j) a[i][j] = Mi[(size_t)(i * NB + j) * g.stride];
+      for (int j = 0; j < NB; ++j) a[i][j] = herm_entry(Mi, g.stride, NB, i, j);
     double ld = 0.0;
     for (int col = 0; col < NB; ++col) {
       int piv = col;

@@ -179,8 +179,10 @@ hipError_t launch_ms_update_xp(void *x, void *p, const void *r, const MsScalars 
                                const FieldShape &f, int nshift, hipStream_t st);
 
 // clover.hip (one lattice per call; the caller offsets the pointers).
-// Clover field: [parity][chirality block][2d][2d][stride] complex, even sites
-// holding D_ee, odd sites D_oo^{-1}.  F: scratch of 6 d^2 complex FP64 per site.
+// Clover field: [parity][chirality block][d(2d+1)][stride] complex, the upper
+// triangle (row-major, diagonal included) of the Hermitian 2d x 2d block; even
+// sites holding D_ee, odd sites D_oo^{-1}.  F: scratch of 6 d^2 complex FP64
+// per site.
 bool clover_supported(int d);
 hipError_t launch_clover_field(void *clov, const void *U, double *F, const Geom &g, int N, int rep, int d, double m0,
                                double csw, int expo, int prec, hipStream_t st);

@@ -189,7 +189,8 @@ def test_clover_argument_checks(W):
     L = W._lib
     dummy = ctypes.c_void_p(0x1000)
     stride = 256
-    assert L.wdirac_field_bytes(h, W.FIELD_CLOVER, 1, W.F64) == 16 * 36 * stride * 16
+    # two chirality blocks per site and parity, upper triangles of 12 x 12
+    assert L.wdirac_field_bytes(h, W.FIELD_CLOVER, 1, W.F64) == 4 * 78 * stride * 16
     assert L.wdirac_workspace_bytes(h, W.OP_CLOVER, 1, W.F64) >= 6 * 36 * 256 * 16
     assert L.wdirac_clover_field(h, dummy, dummy, -4.0, 1.0, 0, 0, dummy, None) == W.EINVAL     # 4 + m0 = 0
     assert L.wdirac_clover_field(h, dummy, dummy, -0.1, 1.0, 2, 0, dummy, None) == W.EINVAL     # exponential flag
