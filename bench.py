@@ -415,6 +415,10 @@ def hmc_trajectory(W, torch, synth, name='su2_adj_32x16x16x16'):
                      'energy conservation is checked in the tests (dH ~ eps^2)'}
 
 
+SECTIONS = {'multi_rhs': multi_rhs_cg, 'mixed_large': mixed_cg_large, 'lattice_batch': lattice_batch_cg,
+            'force': force_timing, 'rhmc_clover': rhmc_and_clover, 'hmc': hmc_trajectory}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -426,6 +430,8 @@ def main():
     ap.add_argument('--no-multi', action='store_true',
                     help='skip the one-off solver comparisons (12 sources batched vs single, SU(4) 2AS mixed vs '
                          'FP64, three-lattice batch) and the force timing')
+    ap.add_argument('--only', choices=sorted(SECTIONS),
+                    help='profiling aid: run one of the one-off sections alone and print its JSON')
     ap.add_argument('--traffic-shapes', action='store_true',
                     help='profiling aid: 6 hop launches (the benchmark pattern) for every FP64 launch shape the '
                          'autotuner may pick, in the order printed, to take HBM counters per shape')
@@ -450,6 +456,10 @@ def main():
 
     from paper_2503_06721_amd import synth
     from paper_2503_06721_amd import wdirac as W
+
+    if args.only:
+        print(json.dumps(SECTIONS[args.only](W, torch, synth)), flush=True)
+        return
 
     cfg = synth.CONFIGS[WORKLOAD]
     dims, N, rep, m0, bc = cfg['dims'], cfg['N'], cfg['rep'], cfg['m0'], cfg['bc']
