@@ -132,7 +132,7 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *   WDIRAC_OPT_CG_CHECK_EVERY          CG iterations between host checks of
  *                                      convergence (default 4, 1..1000)
  *   WDIRAC_OPT_MIXED_DELTA             reliable-update trigger of mixed CG,
- *                                      ||r|| < delta max ||r|| (default 0.1)
+ *                                      ||r|| < delta max ||r|| (default 0.01)
  *   WDIRAC_OPT_TILE_TBLOCK             0 (default) = site tiles in lexicographic
  *                                      order; b > 0 = in t-blocks of b slices
  *                                      (t-neighbours close in time; used when

@@ -386,7 +386,7 @@ int wdirac_create_batch(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *ge
   c->xcd_remap = 1;
   c->tblock = 0;
   c->cg_check_every = 4;
-  c->mixed_delta = 0.1;
+  c->mixed_delta = 0.01;
   c->cg_graph = 1;
   *ctx = c;
   return WDIRAC_OK;
