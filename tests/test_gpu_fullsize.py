@@ -4,8 +4,8 @@ output sites one by one from their gathered neighbourhoods (links and spinors
 copied back from the device inputs), and whole-lattice properties (true
 residuals, agreement of solver modes) are checked where sampling cannot reach.
 
-Sizes: SU(3) FUND 32^4, SU(4) 2AS 96x48^3, SU(3) SYM 48x24^3 (12 right-hand
-sides), SU(2) ADJ 32x16^3."""
+Sizes: SU(3) FUND 32^4 (also with the clover term), SU(4) 2AS 96x48^3,
+SU(3) SYM 48x24^3 (12 right-hand sides), SU(2) ADJ 32x16^3."""
 import numpy as np
 import pytest
 import torch
@@ -155,3 +155,43 @@ def test_cg_su4_2as_mixed_vs_f64(W):
         f'{out[W.CG_F64][1]["seconds"] / out[W.CG_MIXED][1]["seconds"]:.2f}x')
     # both solve to 1e-10; their difference is bounded by cond(A) * 2e-10
     assert rdiff < 1e-4
+
+
+@pytest.mark.parametrize('expo', [0, 1])
+def test_clover_full_size_sampled(W, expo):
+    """SU(3) FUND 32^4, c_sw = 1 (the benchmark's clover workload): D_ee psi on
+    sampled even sites and D_oo^{-1} psi on sampled odd sites, against the
+    oracle's clover blocks built from the 3^4 patch of links around each site
+    (every link of the site's clover leaves lies in that patch)."""
+    from oracle import clover as OC
+    cfg = synth.CONFIGS['su3_fund_32x32x32x32']
+    dims, N, rep, bc, m = cfg['dims'], cfg['N'], cfg['rep'], cfg['bc'], cfg['m0']
+    csw = 1.0
+    U = gen_links(cfg)
+    lat = W.Lattice(N, rep, dims, bc)
+    clov = lat.new_clover(0)
+    lat.clover_field(clov, U, m, csw, expo, 0)
+    g = torch.Generator(device='cuda')
+    g.manual_seed(cfg['seed'] + 17)
+    psi = torch.randn((1,) + tuple(dims) + (4, lat.d), dtype=torch.complex128, device='cuda', generator=g)
+    off = np.array([[a, b, c, d] for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1) for d in (-1, 0, 1)])
+    for p in (0, 1):
+        inp = lat.pack_half(psi, p)
+        out = lat.new_half()
+        lat.apply_clover(out, inp, clov, p)
+        res = lat.unpack_half(out, p)
+        coords = sample_sites(dims, p, 48, cfg['seed'] + 20 + p)
+        got = gather(res[0], coords)
+        for k, c in enumerate(coords):
+            patch = (c[None, :] + off) % np.array(dims)
+            Up = gather(U, patch).reshape(3, 3, 3, 3, 4, N, N)
+            M = OC.diagonal_blocks(R.represent(Up, rep), m, csw, bool(expo))[1, 1, 1, 1]
+            if p == 1:
+                M = np.linalg.inv(M)
+            v = gather(psi[0], c[None, :])[0].reshape(-1)
+            exp = (M @ v).reshape(4, lat.d)
+            err = np.linalg.norm(got[k] - exp) / np.linalg.norm(exp)
+            assert err < TOL[0], (p, k, err)
+        log(f'  expo={expo} parity {p}: {len(coords)} sampled sites within {TOL[0]}')
+    del U, clov, psi
+    torch.cuda.empty_cache()
