@@ -11,67 +11,15 @@
 //    spin-projected two-spinor of the hopping kernel; Sigma is a sum of four
 //    colour outer products and U_R Sigma = sum_j (U_R h_j) k_j^+.
 //  * for every representation tr(T^a_R M) = tr(T^a Z) for an N x N matrix
-//    Z(M) (FUND: Z = M; ADJ: Z = 2 sum_bc M_cb [T^c, T^b]; two-index: from
-//    T^a_R e = T^a e + e T^aT, Z_ki += conj(e_A)_ij (e_B)_kj M_BA and
-//    Z_lj += conj(e_A)_ij (e_B)_il M_BA), and
+//    Z(M), the pull-back of wd_rep.h, and
 //    sum_a Im tr(T^a Z) T^a = 1/2 (A - tr(A)/N) with A = (Z - Z^+)/(2i)
 //    (completeness of the generators, tr T^a T^b = delta/2).
 // The boundary phase is already folded into U_R, so neighbours are periodic.
 #include "wd_common.h"
 #include "wd_kernels.h"
+#include "wd_rep.h"
 
 namespace wd {
-
-constexpr int frep_dim(int N, int rep) {
-  return rep == 0 ? N : rep == 1 ? N * N - 1 : rep == 2 ? N * (N + 1) / 2 : N * (N - 1) / 2;
-}
-
-// Non-zero entries of fundamental generator a (same basis as rep.hip).
-template <int N>
-__device__ __forceinline__ int fgen_nz(int a, int (&ri)[N], int (&ci)[N], cplx<double> (&v)[N]) {
-  constexpr int noff = N * (N - 1);
-  if (a < noff) {
-    int p = a >> 1, j = 0;
-    while (p >= N - 1 - j) {
-      p -= N - 1 - j;
-      ++j;
-    }
-    const int k = j + 1 + p;
-    ri[0] = j; ci[0] = k;
-    ri[1] = k; ci[1] = j;
-    v[0] = (a & 1) ? mk(0.0, -0.5) : mk(0.5, 0.0);
-    v[1] = (a & 1) ? mk(0.0, 0.5) : mk(0.5, 0.0);
-    return 2;
-  }
-  const int kk = a - noff + 1;
-  const double nrm = 1.0 / sqrt(2.0 * kk * (kk + 1));
-  for (int i = 0; i < kk; ++i) {
-    ri[i] = i; ci[i] = i;
-    v[i] = mk(nrm, 0.0);
-  }
-  ri[kk] = kk; ci[kk] = kk;
-  v[kk] = mk(-kk * nrm, 0.0);
-  return kk + 1;
-}
-
-// Non-zero entries of two-index basis element A.
-template <int N, bool SYM>
-__device__ __forceinline__ int basis_nz(int A, int (&ri)[2], int (&ci)[2], double (&v)[2]) {
-  int a = 0, rem = A;
-  while (rem >= (SYM ? N - a : N - 1 - a)) {
-    rem -= SYM ? N - a : N - 1 - a;
-    ++a;
-  }
-  const int b = a + rem + (SYM ? 0 : 1);
-  if (a == b) {
-    ri[0] = a; ci[0] = a; v[0] = 1.0;
-    return 1;
-  }
-  const double s = 0.70710678118654752440;
-  ri[0] = a; ci[0] = b; v[0] = s;
-  ri[1] = b; ci[1] = a; v[1] = SYM ? s : -s;
-  return 2;
-}
 
 template <int D, int MU, int SIG>
 __device__ __forceinline__ void project(const cplx<double> *__restrict__ f, int stride, int site,
@@ -91,7 +39,7 @@ __device__ void force_link(double *__restrict__ P, const cplx<double> *Xe, const
                            const cplx<double> *Ye, const cplx<double> *Yo, const void *UR,
                            const cplx<double> *__restrict__ U, const Geom &g, int lex,
                            int par, int cb, int t, int x, int y, int z, double scale, int accumulate) {
-  constexpr int D = frep_dim(N, REP);
+  constexpr int D = rep_dim(N, REP);
   constexpr bool REAL = REP == 1;
   const int nb = nb_index(g, t, x, y, z, MU, 1);
   const cplx<double> *Xh = par ? Xo : Xe, *Yh = par ? Yo : Ye;   // own parity
@@ -142,47 +90,7 @@ __device__ void force_link(double *__restrict__ P, const cplx<double> *Xe, const
     return m;
   };
   cplx<double> Z[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) Z[i][j] = mk(0.0, 0.0);
-  if constexpr (REP == 0) {
-    for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) Z[i][j] = Mel(i, j);
-  } else if constexpr (REP == 1) {
-    int rb[N], cbn[N], rc[N], cc[N];
-    cplx<double> vb[N], vc[N];
-    for (int c = 0; c < D; ++c) {
-      const int nc = fgen_nz<N>(c, rc, cc, vc);
-      for (int b = 0; b < D; ++b) {
-        const int nbz = fgen_nz<N>(b, rb, cbn, vb);
-        const cplx<double> m = 2.0 * Mel(c, b);
-        // Z += m (T^c T^b - T^b T^c)
-        for (int p = 0; p < nc; ++p)
-          for (int q = 0; q < nbz; ++q) {
-            if (cc[p] == rb[q]) Z[rc[p]][cbn[q]] = cfma(m, cmul(vc[p], vb[q]), Z[rc[p]][cbn[q]]);
-            if (cbn[q] == rc[p]) Z[rb[q]][cc[p]] = cfma(mk(-m.re, -m.im), cmul(vb[q], vc[p]), Z[rb[q]][cc[p]]);
-          }
-      }
-    }
-  } else {
-    constexpr bool SYM = REP == 2;
-    int ra[2], ca[2], rb[2], cbn[2];
-    double va[2], vb[2];
-    for (int A = 0; A < D; ++A) {
-      const int na = basis_nz<N, SYM>(A, ra, ca, va);
-      for (int B = 0; B < D; ++B) {
-        const int nbz = basis_nz<N, SYM>(B, rb, cbn, vb);
-        const cplx<double> m = Mel(B, A);
-        for (int p = 0; p < na; ++p)
-          for (int q = 0; q < nbz; ++q) {
-            const cplx<double> c = (va[p] * vb[q]) * m;
-            if (cbn[q] == ca[p]) Z[rb[q]][ra[p]] = Z[rb[q]][ra[p]] + c;   // (e_B)_{k j}, e_A (i, j)
-            if (rb[q] == ra[p]) Z[cbn[q]][ca[p]] = Z[cbn[q]][ca[p]] + c;  // (e_B)_{i l}, e_A (i, j)
-          }
-      }
-    }
-  }
+  rep_pullback<N, REP>(Mel, Z);
   // A = (Z - Z^+)/(2i);  P = (A - tr(A)/N) / 2
   cplx<double> Am[N][N];
   double trA = 0.0;
