@@ -120,7 +120,8 @@ def cpu_baseline(cfg, U, psi, seconds_target=15.0):
 
 
 FORM_NAMES = {0: 'site-parallel', 1: 'colour-split', 2: 'colour-split, paired directions',
-              3: 'colour-split, compact links', 4: 'colour-split, compact links, paired directions'}
+              3: 'colour-split, compact links', 4: 'colour-split, compact links, paired directions',
+              5: 'colour-split, two directions per phase'}
 
 
 def tuned_form(best):
@@ -486,7 +487,7 @@ def main():
     bytes_per_launch = hop_bytes_per_site(d, lat.real, 8) * lat.Vh
     if args.traffic_shapes:
         shapes = []
-        for variant in (W.HOP_SITE, W.HOP_COLOUR, W.HOP_COLOUR_PAIR):
+        for variant in (W.HOP_SITE, W.HOP_COLOUR, W.HOP_COLOUR_PAIR, W.HOP_COLOUR_QUAD):
             for remap in (0, 1):
                 for tb in (0, 2, 4, 8):
                     lat.set_option(W.OPT_HOP_VARIANT_F64, variant)
@@ -504,7 +505,8 @@ def main():
     tuned = {'f64': lat.autotune(UR64, W.F64, 1), 'f32': lat.autotune(UR32, W.F32, 1)}
     log(f'[bench] autotuned hop shapes: {tuned}')
     variant_name = {W.HOP_SITE: 'k_hop_sp (lane per site)', W.HOP_COLOUR: 'k_hop_cs (colour-split)',
-                    W.HOP_COLOUR_PAIR: 'k_hop_cs (colour-split, paired directions)'}
+                    W.HOP_COLOUR_PAIR: 'k_hop_cs (colour-split, paired directions)',
+                    W.HOP_COLOUR_QUAD: 'k_hop_cs (colour-split, two directions per phase)'}
 
     def step(record):
         lat.rep_links(UR64, Ug, W.F64)

@@ -127,6 +127,9 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                          the entries of U_R in registers
  *                                          (SYM for N = 2..4, 2AS for N = 4;
  *                                          1 or 2 rhs per block)
+ *                                      5 = as 1 with two directions (four
+ *                                          hops) staged per barrier phase
+ *                                          (d_R <= 4; 1 rhs per block)
  *   WDIRAC_OPT_XCD_REMAP               1 (default) = give each XCD a
  *                                      contiguous range of site tiles
  *   WDIRAC_OPT_CG_CHECK_EVERY          CG iterations between host checks of
@@ -171,7 +174,7 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value);
 
 /* Launch shape of the hopping kernel chosen by wdirac_autotune(). */
 typedef struct {
-  int32_t variant;    /* 0 = one lane per site, 1 = colour-split, 2 = paired */
+  int32_t variant;    /* WDIRAC_OPT_HOP_VARIANT_F64 values (0..5)        */
   int32_t nr;         /* right-hand sides per block (colour-split form)  */
   int32_t xcd_remap;  /* 1 = contiguous tile ranges per XCD               */
   int32_t tblock;     /* t-block of the tile order (0 = lexicographic)    */

@@ -469,7 +469,8 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
     case WDIRAC_OPT_HOP_VARIANT_F64:
     case WDIRAC_OPT_HOP_VARIANT_F32: {
       const int v = (int)value;
-      if (v < wd::HOP_SITE || v > wd::HOP_COMPACT_PAIR || !wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, v))
+      if (v < wd::HOP_SITE || v > wd::HOP_COLOUR_QUAD) return fail(WDIRAC_EINVAL, "hop variant out of range");
+      if (!wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, v))
         return fail(WDIRAC_EUNSUPPORTED, "hop variant not available for this representation");
       ctx->hop_variant[option == WDIRAC_OPT_HOP_VARIANT_F64 ? 0 : 1] = v;
       return WDIRAC_OK;
@@ -524,7 +525,7 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
   for (int tb : tbs) {
     if (tb && (ctx->nlat > 1 || ctx->g[0].T % tb)) continue;
     for (int remap = 0; remap < 2; ++remap) {
-      for (int v = wd::HOP_COLOUR; v <= wd::HOP_COMPACT_PAIR; ++v) {
+      for (int v = wd::HOP_COLOUR; v <= wd::HOP_COLOUR_QUAD; ++v) {
         if (!wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, v)) continue;
         for (int nr : {1, 2, 3, 4, 6})
           if (effective_nr(ctx, nr, nrhs, prec, v) == nr) cands.push_back({v, nr, remap, tb});

@@ -330,11 +330,12 @@ __device__ __forceinline__ void cs_compute(cplx<T> (&acc)[NR][4], const typename
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// One direction mu.  PAIR = false: forward and backward hops are two barrier
-// phases (LDS buffers 0 and 1).  PAIR = true: both are staged before a single
+// One direction mu.  STG = 1: forward and backward hops are two barrier
+// phases (LDS buffers 0 and 1).  STG = 2: both are staged before a single
 // barrier (LDS buffers 2*(MU&1) and 2*(MU&1)+1), which halves the barriers and
 // doubles the loads in flight per phase at the cost of twice the LDS.
-template <int D, bool REAL, typename T, int MU, int SF, int NR, bool PAIR, bool NTL, int NB, int FLY>
+// (STG = 4, two directions per phase, is cs_mu2 below.)
+template <int D, bool REAL, typename T, int MU, int SF, int NR, int STG, bool NTL, int NB, int FLY>
 __device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64], const Geom &g, int parity,
                                       const typename LinkT<T, REAL>::type *links, const cplx<T> *flinks,
                                       const cplx<T> *in0, size_t rstride, int t, int x, int y, int z, int is, int row,
@@ -343,7 +344,7 @@ __device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2
   const int nbf = nb_index(g, t, x, y, z, MU, 1);
   const int nbb = nb_index(g, t, x, y, z, MU, 0);
   L uf[D], ub[D];
-  if constexpr (PAIR) {
+  if constexpr (STG == 2) {
     constexpr int B0 = 2 * (MU & 1);
     cs_stage<D, REAL, T, MU, SF, false, NR, NTL, FLY>(uf, hs[B0], g, parity, links, flinks, in0, rstride, nbf, is,
                                                       row, lane);
@@ -364,11 +365,39 @@ __device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2
   }
 }
 
+// Directions MU0 and MU0 + 1 together (STG = 4): the four hops are staged
+// into LDS buffers 2*MU0 .. 2*MU0 + 3 before one barrier, so a launch has two
+// barrier phases and four hops' loads in flight in each.
+template <int D, bool REAL, typename T, int MU0, int SF, int NR, bool NTL, int FLY>
+__device__ __forceinline__ void cs_mu2(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64], const Geom &g, int parity,
+                                       const typename LinkT<T, REAL>::type *links, const cplx<T> *flinks,
+                                       const cplx<T> *in0, size_t rstride, int t, int x, int y, int z, int is, int row,
+                                       int lane) {
+  using L = typename LinkT<T, REAL>::type;
+  constexpr int MU1 = MU0 + 1, B0 = 2 * MU0;
+  const int f0 = nb_index(g, t, x, y, z, MU0, 1), b0 = nb_index(g, t, x, y, z, MU0, 0);
+  const int f1 = nb_index(g, t, x, y, z, MU1, 1), b1 = nb_index(g, t, x, y, z, MU1, 0);
+  L u0f[D], u0b[D], u1f[D], u1b[D];
+  cs_stage<D, REAL, T, MU0, SF, false, NR, NTL, FLY>(u0f, hs[B0], g, parity, links, flinks, in0, rstride, f0, is, row,
+                                                     lane);
+  cs_stage<D, REAL, T, MU0, -SF, true, NR, NTL, FLY>(u0b, hs[B0 + 1], g, parity, links, flinks, in0, rstride, b0, b0,
+                                                     row, lane);
+  cs_stage<D, REAL, T, MU1, SF, false, NR, NTL, FLY>(u1f, hs[B0 + 2], g, parity, links, flinks, in0, rstride, f1, is,
+                                                     row, lane);
+  cs_stage<D, REAL, T, MU1, -SF, true, NR, NTL, FLY>(u1b, hs[B0 + 3], g, parity, links, flinks, in0, rstride, b1, b1,
+                                                     row, lane);
+  __syncthreads();
+  cs_compute<D, REAL, T, MU0, SF, false, NR>(acc, u0f, hs[B0], lane);
+  cs_compute<D, REAL, T, MU0, -SF, true, NR>(acc, u0b, hs[B0 + 1], lane);
+  cs_compute<D, REAL, T, MU1, SF, false, NR>(acc, u1f, hs[B0 + 2], lane);
+  cs_compute<D, REAL, T, MU1, -SF, true, NR>(acc, u1b, hs[B0 + 3], lane);
+}
+
 // NTL: links read with streaming loads (set when the launch has a single
 // group of right-hand sides, so that no other block re-reads them).
-template <int D, bool REAL, typename T, bool DAG, int NR, bool PAIR, bool NTL, int W, int FLY>
+template <int D, bool REAL, typename T, bool DAG, int NR, int STG, bool NTL, int W, int FLY>
 __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) void k_hop_cs(HopArgs a) {
-  constexpr int NB = PAIR ? 4 : 2;   // LDS buffers
+  constexpr int NB = 2 * STG;   // LDS buffers
   __shared__ cplx<T> hs[NB][NR][2][D][64];
   __shared__ double sh[D];
   // Work item = (tile, group of NR right-hand sides), group fastest, so the
@@ -402,14 +431,21 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[k][s] = mk<T>(0, 0);
   constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
-  cs_mu<D, REAL, T, 0, SF, NR, PAIR, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
-                                                     is, row, lane);
-  cs_mu<D, REAL, T, 1, SF, NR, PAIR, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
-                                                     is, row, lane);
-  cs_mu<D, REAL, T, 2, SF, NR, PAIR, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
-                                                     is, row, lane);
-  cs_mu<D, REAL, T, 3, SF, NR, PAIR, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
-                                                     is, row, lane);
+  if constexpr (STG == 4) {
+    cs_mu2<D, REAL, T, 0, SF, NR, NTL, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z, is, row,
+                                            lane);
+    cs_mu2<D, REAL, T, 2, SF, NR, NTL, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z, is, row,
+                                            lane);
+  } else {
+    cs_mu<D, REAL, T, 0, SF, NR, STG, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+                                                    is, row, lane);
+    cs_mu<D, REAL, T, 1, SF, NR, STG, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+                                                    is, row, lane);
+    cs_mu<D, REAL, T, 2, SF, NR, STG, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+                                                    is, row, lane);
+    cs_mu<D, REAL, T, 3, SF, NR, STG, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+                                                    is, row, lane);
+  }
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
   // Two straight-line epilogues (with and without x_add): every accumulator
   // is used on both paths, so no arithmetic is sunk behind a branch.  The
@@ -471,15 +507,15 @@ constexpr int sp_waves(int D, bool dbl) { return dbl ? 2 : (D <= 2 ? 4 : D <= 4 
 // a gfx950 workgroup may allocate (less the reduction scratch).  Blocks above
 // 80 KB run one per CU; the autotuner weighs that against the link sharing.
 constexpr int LDS_BUDGET = 160 * 1024 - 256;
-template <int D, typename T, int NR, bool PAIR>
+template <int D, typename T, int NR, int STG>
 constexpr bool cs_fits() {
-  return (PAIR ? 4 : 2) * NR * 2 * D * 64 * (int)sizeof(cplx<T>) <= LDS_BUDGET;
+  return 2 * STG * NR * 2 * D * 64 * (int)sizeof(cplx<T>) <= LDS_BUDGET;
 }
 // Six right-hand sides per block: colour form (unpaired) with d_R <= 4 only;
 // beyond that the accumulators no longer fit in registers.
 template <int D, typename T>
 constexpr bool cs6_ok() {
-  return D <= 4 && cs_fits<D, T, 6, false>();
+  return D <= 4 && cs_fits<D, T, 6, 1>();
 }
 
 // Tile bookkeeping of a launch with tiles of ts sites: per-lattice tile
@@ -518,18 +554,32 @@ constexpr int cs_waves_form(int D, bool dbl, int NR, bool pair, int fly) {
   return w > 1 ? w : 1;
 }
 
+// Four hops per phase (stage 4): one right-hand side per block, stored links,
+// d_R <= 4.
+template <int D, typename T, int NR, int FLY>
+constexpr bool cs4_ok() {
+  return NR == 1 && FLY == 0 && D <= 4 && cs_fits<D, T, 1, 4>();
+}
+
+// stage: hops staged per barrier phase, 1, 2 (paired directions) or 4.
 template <int D, bool REAL, typename T, bool DAG, int NR, bool NTL, int FLY>
-static hipError_t launch_cs2(const HopArgs &a, int pair, hipStream_t st) {
+static hipError_t launch_cs2(const HopArgs &a, int stage, hipStream_t st) {
   constexpr int WU = cs_waves_form(D, sizeof(T) == 8, NR, false, FLY);
   constexpr int WP = cs_waves_form(D, sizeof(T) == 8, NR, true, FLY);
   dim3 grid(a.ntiles * a.ngroups);
-  if constexpr (NR <= 4 && cs_fits<D, T, NR, true>()) {
-    if (pair) {
-      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, true, NTL, WP, FLY>), grid, dim3(64 * D), 0, st, a);
+  if constexpr (cs4_ok<D, T, NR, FLY>()) {
+    if (stage == 4) {
+      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, 4, NTL, WP, FLY>), grid, dim3(64 * D), 0, st, a);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, false, NTL, WU, FLY>), grid, dim3(64 * D), 0, st, a);
+  if constexpr (NR <= 4 && cs_fits<D, T, NR, 2>()) {
+    if (stage == 2) {
+      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, 2, NTL, WP, FLY>), grid, dim3(64 * D), 0, st, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, 1, NTL, WU, FLY>), grid, dim3(64 * D), 0, st, a);
   return hipGetLastError();
 }
 
@@ -537,13 +587,13 @@ static hipError_t launch_cs2(const HopArgs &a, int pair, hipStream_t st) {
 // several groups the groups of a tile re-read the links from L2).  Only the
 // one-rhs-per-block kernels carry the streaming form.
 template <int D, bool REAL, typename T, bool DAG, int NR, int FLY = 0>
-static hipError_t launch_cs(HopArgs a, int nrhs, int pair, hipStream_t st, Counts *counts, int *prow) {
+static hipError_t launch_cs(HopArgs a, int nrhs, int stage, hipStream_t st, Counts *counts, int *prow) {
   set_tiles(a, 64, nrhs, counts, prow);
   a.ngroups = nrhs / NR;
   if constexpr (NR == 1) {
-    if (a.ngroups == 1) return launch_cs2<D, REAL, T, DAG, 1, true, FLY>(a, pair, st);
+    if (a.ngroups == 1) return launch_cs2<D, REAL, T, DAG, 1, true, FLY>(a, stage, st);
   }
-  return launch_cs2<D, REAL, T, DAG, NR, false, FLY>(a, pair, st);
+  return launch_cs2<D, REAL, T, DAG, NR, false, FLY>(a, stage, st);
 }
 
 // Compact forms: 1 or 2 right-hand sides per block (more spill registers).
@@ -551,10 +601,10 @@ template <int D, typename T, bool DAG, int FLY>
 static hipError_t launch_compact(const HopArgs &a0, int nrhs, int pair, int nr, hipStream_t st, Counts *counts,
                                  int *prow) {
   if (nr >= 2 && nrhs % 2 == 0) {
-    if constexpr (cs_fits<D, T, 2, false>())
-      return launch_cs<D, false, T, DAG, 2, FLY>(a0, nrhs, pair, st, counts, prow);
+    if constexpr (cs_fits<D, T, 2, 1>())
+      return launch_cs<D, false, T, DAG, 2, FLY>(a0, nrhs, pair ? 2 : 1, st, counts, prow);
   }
-  return launch_cs<D, false, T, DAG, 1, FLY>(a0, nrhs, pair, st, counts, prow);
+  return launch_cs<D, false, T, DAG, 1, FLY>(a0, nrhs, pair ? 2 : 1, st, counts, prow);
 }
 
 template <int D, int FLY>
@@ -570,7 +620,7 @@ static hipError_t compact_d(const HopArgs &a, int prec, int dagger, int nrhs, in
 template <int D, bool REAL, typename T, bool DAG>
 static hipError_t launch_typed(const HopArgs &a0, int nrhs, int variant, int nr, hipStream_t st, Counts *counts,
                                int *prow) {
-  const int pair = variant == HOP_COLOUR_PAIR;
+  const int stage = variant == HOP_COLOUR_QUAD ? 4 : variant == HOP_COLOUR_PAIR ? 2 : 1;
   if (variant == HOP_SITE) {
     if constexpr (D <= 6) {
       HopArgs a = a0;
@@ -591,19 +641,19 @@ static hipError_t launch_typed(const HopArgs &a0, int nrhs, int variant, int nr,
       return hipErrorInvalidValue;
     }
   }
-  if (nr == 6 && nrhs % 6 == 0 && !pair) {
-    if constexpr (cs6_ok<D, T>()) return launch_cs<D, REAL, T, DAG, 6>(a0, nrhs, pair, st, counts, prow);
+  if (nr == 6 && nrhs % 6 == 0 && stage == 1) {
+    if constexpr (cs6_ok<D, T>()) return launch_cs<D, REAL, T, DAG, 6>(a0, nrhs, stage, st, counts, prow);
   }
   if (nr == 4 && nrhs % 4 == 0) {
-    if constexpr (cs_fits<D, T, 4, false>()) return launch_cs<D, REAL, T, DAG, 4>(a0, nrhs, pair, st, counts, prow);
+    if constexpr (cs_fits<D, T, 4, 1>()) return launch_cs<D, REAL, T, DAG, 4>(a0, nrhs, stage, st, counts, prow);
   }
   if (nr == 3 && nrhs % 3 == 0) {
-    if constexpr (cs_fits<D, T, 3, false>()) return launch_cs<D, REAL, T, DAG, 3>(a0, nrhs, pair, st, counts, prow);
+    if constexpr (cs_fits<D, T, 3, 1>()) return launch_cs<D, REAL, T, DAG, 3>(a0, nrhs, stage, st, counts, prow);
   }
   if (nr == 2 && nrhs % 2 == 0) {
-    if constexpr (cs_fits<D, T, 2, false>()) return launch_cs<D, REAL, T, DAG, 2>(a0, nrhs, pair, st, counts, prow);
+    if constexpr (cs_fits<D, T, 2, 1>()) return launch_cs<D, REAL, T, DAG, 2>(a0, nrhs, stage, st, counts, prow);
   }
-  return launch_cs<D, REAL, T, DAG, 1>(a0, nrhs, pair, st, counts, prow);
+  return launch_cs<D, REAL, T, DAG, 1>(a0, nrhs, stage, st, counts, prow);
 }
 
 template <int D, bool REAL>
@@ -647,7 +697,8 @@ hipError_t launch_hop(const HopArgs &a, int N, int rep, int d, int real, int pre
 bool hop_nr_supported(int d, int prec, int variant, int nr) {
   // as cs_fits, cs6_ok and launch_compact
   const int cb = prec == 0 ? 16 : 8;
-  const int nbuf = (variant == HOP_COLOUR_PAIR || variant == HOP_COMPACT_PAIR) ? 4 : 2;
+  const int nbuf = variant == HOP_COLOUR_QUAD ? 8 : (variant == HOP_COLOUR_PAIR || variant == HOP_COMPACT_PAIR) ? 4 : 2;
+  if (variant == HOP_COLOUR_QUAD && (nr != 1 || d > 4)) return false;
   if (nr < 1 || nr > 6 || nr == 5) return false;
   if (nr == 6 && (variant != HOP_COLOUR || d > 4)) return false;
   if ((variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR) && nr > 2) return false;
@@ -659,6 +710,7 @@ bool compact_links_ok(int N, int rep) { return (rep == 2 && N >= 2 && N <= 4) ||
 bool hop_variant_ok(int N, int rep, int d, int variant) {
   if (variant == HOP_SITE) return d <= 6;
   if (variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR) return compact_links_ok(N, rep);
+  if (variant == HOP_COLOUR_QUAD) return d <= 4;
   return variant == HOP_COLOUR || variant == HOP_COLOUR_PAIR;
 }
 

@@ -20,7 +20,9 @@ constexpr int MAXLAT = 8;
 // HOP_COMPACT / HOP_COMPACT_PAIR: the colour-split forms reading the
 // fundamental links and rebuilding the two-index represented entries in
 // registers (SYM and 2AS only, where N^2 < d_R^2).
-enum { HOP_SITE = 0, HOP_COLOUR = 1, HOP_COLOUR_PAIR = 2, HOP_COMPACT = 3, HOP_COMPACT_PAIR = 4 };
+// HOP_COLOUR_QUAD: the colour-split form staging two directions (four hops)
+// per barrier phase (one rhs per block, d_R <= 4).
+enum { HOP_SITE = 0, HOP_COLOUR = 1, HOP_COLOUR_PAIR = 2, HOP_COMPACT = 3, HOP_COMPACT_PAIR = 4, HOP_COLOUR_QUAD = 5 };
 
 // One lattice of a launch.
 struct LatDesc {

@@ -30,7 +30,7 @@ FIELD_HALF_SPINOR, FIELD_LINKS, FIELD_CLOVER = 0, 1, 2
 MAX_SHIFTS = 32
 (OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
  OPT_HOP_NR_F32, OPT_TILE_TBLOCK, OPT_CG_GRAPH) = 0, 1, 2, 3, 4, 5, 6, 7, 8
-HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR, HOP_COMPACT, HOP_COMPACT_PAIR = 0, 1, 2, 3, 4
+HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR, HOP_COMPACT, HOP_COMPACT_PAIR, HOP_COLOUR_QUAD = 0, 1, 2, 3, 4, 5
 REP_CODES = {'FUND': FUND, 'ADJ': ADJ, 'SYM': SYM, '2AS': ASYM}
 STATUS_NAMES = {OK: 'OK', EINVAL: 'EINVAL', EUNSUPPORTED: 'EUNSUPPORTED', EHIP: 'EHIP',
                 ENOCONV: 'ENOCONV', EBREAKDOWN: 'EBREAKDOWN'}

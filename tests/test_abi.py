@@ -115,6 +115,8 @@ def test_site_variant_unavailable_for_large_rep(W):
     rc, h = create(W, 4, 1)   # SU(4) ADJ, d = 15
     assert rc == W.OK
     assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_SITE) == W.EUNSUPPORTED
+    assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_COLOUR_QUAD) == W.EUNSUPPORTED
+    assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, 6) == W.EINVAL
     W._lib.wdirac_destroy(h)
 
 
