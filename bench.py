@@ -130,6 +130,65 @@ def tuned_form(best):
             'xcd_remap': best['xcd_remap'], 't_block': best['tblock']}
 
 
+def hop_rate(W, torch, lat, UR, prec, nrhs, n=40, seed=5):
+    """Mean time of one hop launch in the benchmark pattern (D_eo f0 -> f1,
+    D_oe f1 -> f2 alternating; HIP events on the current stream) with the
+    shape the context uses for (prec, nrhs), and its compulsory-byte rate."""
+    eb = 8 if prec == W.F64 else 4
+    g = torch.Generator(device='cuda')
+    g.manual_seed(seed)
+    f = [lat.new_half(nrhs, prec) for _ in range(3)]
+    f[0].view(torch.float64 if prec == W.F64 else torch.float32).normal_(generator=g)
+
+    def launch(k):
+        src, dst = (f[0], f[1]) if k % 2 == 0 else (f[1], f[2])
+        lat.dslash_eo(dst, src, UR, 0 if k % 2 == 0 else 1, nrhs=nrhs, prec=prec)
+
+    for k in range(4):
+        launch(k)
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for k in range(n):
+        launch(k)
+    e1.record(st)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / n * 1e3
+    link = lat.d * lat.d * eb * (1 if lat.real else 2)
+    by = (8 * link + nrhs * 2 * 4 * lat.d * 2 * eb) * lat.Vh
+    return us, by
+
+
+def dslash_roofline(W, torch, lat, UR, prec, nrhs, tuned, n=40):
+    """Hop rate of the tuned shape, against HBM peak.  Bytes are those of the
+    form that ran: the compact forms read N^2 instead of d_R^2 complex entries
+    per link, and their rate is quoted on their own (smaller) byte count; the
+    best stored-link form is then timed as well, in a fresh context of the
+    same geometry, for the rate on the stored-link bytes."""
+    us, by = hop_rate(W, torch, lat, UR, prec, nrhs, n)
+    eb = 8 if prec == W.F64 else 4
+    compact = tuned['variant'] in (W.HOP_COMPACT, W.HOP_COMPACT_PAIR)
+    if compact:
+        by = (8 * lat.N * lat.N * eb * 2 + nrhs * 2 * 4 * lat.d * 2 * eb) * lat.Vh
+    gbs = by / (us * 1e-6) / 1e9
+    out = {'nrhs': nrhs, 'prec': 'f64' if prec == W.F64 else 'f32', 'form': tuned_form(tuned),
+           'us_per_launch': round(us, 2), 'bytes_per_launch': by, 'GBps': round(gbs, 1),
+           'frac': round(gbs / HBM_PEAK_GBS, 4)}
+    if compact:
+        cfg_lat = W.Lattice(lat.N, lat.rep_name, lat.dims, lat.bc)
+        best = None
+        for v in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR):
+            cfg_lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == W.F64 else W.OPT_HOP_VARIANT_F32, v)
+            us_s, by_s = hop_rate(W, torch, cfg_lat, UR, prec, nrhs, n)
+            if best is None or us_s < best[0]:
+                best = (us_s, by_s, v)
+        gs = best[1] / (best[0] * 1e-6) / 1e9
+        out['stored_links'] = {'form': FORM_NAMES[best[2]], 'us_per_launch': round(best[0], 2),
+                               'bytes_per_launch': best[1], 'GBps': round(gs, 1), 'frac': round(gs / HBM_PEAK_GBS, 4)}
+        del cfg_lat
+    return out
+
+
 def multi_rhs_cg(W, torch, synth, name='su3_sym_48x24x24x24'):
     """Time-to-1e-10 of the even-odd CG for 12 point sources on one gauge
     field: all 12 in one batched solve (every hop streams each link once for
@@ -151,15 +210,18 @@ def multi_rhs_cg(W, torch, synth, name='su3_sym_48x24x24x24'):
     lat.eo_source(bp, eta_e, eta_o, UR64, m0, nrhs)
     lat.apply_dhat(b, bp, UR64, m0, dagger=1, nrhs=nrhs)
     del bp, eta_e, eta_o
-    forms = {}
+    forms, rates = {}, []
     for prec, UR, key in ((W.F64, UR64, 'f64'), (W.F32, UR32, 'f32')):
-        forms[f'{key}_{nrhs}rhs'] = tuned_form(lat.autotune(UR, prec, nrhs))
-        forms[f'{key}_1rhs'] = tuned_form(lat.autotune(UR, prec, 1))
+        for k in (nrhs, 1):
+            tuned = lat.autotune(UR, prec, k)
+            forms[f'{key}_{k}rhs'] = tuned_form(tuned)
+            rates.append(dslash_roofline(W, torch, lat, UR, prec, k, tuned))
+            log(f'[bench]   hop {key} {k} rhs: {rates[-1]}')
     ws = lat.new_workspace(W.OP_CG, nrhs, W.CG_MIXED)
     x = lat.new_half(nrhs)
     per = x.numel() // nrhs
     out = {'workload': name, 'sources': f'{nrhs} point sources (spin k%4, colour k//4) at the origin',
-           'hop_forms': forms}
+           'hop_forms': forms, 'dslash_roofline': rates}
     for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
         x.zero_()
         rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, nrhs=nrhs, mode=mode, UR32=UR32, workspace=ws)
@@ -205,10 +267,15 @@ def mixed_cg_large(W, torch, synth, name='su4_2as_96x48x48x48'):
     b = lat.new_half()
     lat.apply_dhat(b, eta_e, UR64, m0, dagger=1)
     del eta_e
-    forms = {'f64': tuned_form(lat.autotune(UR64, W.F64, 1)), 'f32': tuned_form(lat.autotune(UR32, W.F32, 1))}
+    forms, rates = {}, []
+    for prec, UR, key in ((W.F64, UR64, 'f64'), (W.F32, UR32, 'f32')):
+        tuned = lat.autotune(UR, prec, 1)
+        forms[key] = tuned_form(tuned)
+        rates.append(dslash_roofline(W, torch, lat, UR, prec, 1, tuned, n=20))
+        log(f'[bench]   hop {key}: {rates[-1]}')
     ws = lat.new_workspace(W.OP_CG, 1, W.CG_MIXED)
     x = lat.new_half()
-    out = {'workload': name, 'source': 'D-hat^+ eta, eta Gaussian', 'hop_forms': forms}
+    out = {'workload': name, 'source': 'D-hat^+ eta, eta Gaussian', 'hop_forms': forms, 'dslash_roofline': rates}
     for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
         x.zero_()
         rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, mode=mode, UR32=UR32, workspace=ws)
