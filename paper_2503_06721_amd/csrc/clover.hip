@@ -470,81 +470,11 @@ bool clover_supported(int d) { return d == 2 || d == 3 || d == 4 || d == 6; }
 // g per (plane, site) -> gather over the 24 (leaf, corner) pairs holding each
 // link.  Scratch: K [2][6][d][d][V], g [6][4][N][N][V] complex FP64.
 
-// e = exp(a) (discarded) and om <- L(a, om) = d/dt exp(a + t om) at t = 0:
-// scaling by 2^-s, Horner for exp(a') and its derivative along om / 2^s,
-// then s squarings (e, l) <- (e e, l e + e l).  a is destroyed.
-template <int NB>
-__device__ void expm_frechet(cplx<double> (&a)[NB][NB], cplx<double> (&om)[NB][NB]) {
-  double nrm = 0.0;
-  for (int j = 0; j < NB; ++j) {
-    double s = 0.0;
-    for (int i = 0; i < NB; ++i) s += sqrt(a[i][j].re * a[i][j].re + a[i][j].im * a[i][j].im);
-    nrm = s > nrm ? s : nrm;
-  }
-  int sq = 0;
-  while (nrm > 0.25 && sq < 60) {
-    nrm *= 0.5;
-    ++sq;
-  }
-  const double sc = ldexp(1.0, -sq);
-  for (int i = 0; i < NB; ++i)
-    for (int j = 0; j < NB; ++j) {
-      a[i][j] = sc * a[i][j];
-      om[i][j] = sc * om[i][j];
-    }
-  constexpr int K = 12;   // as in expm
-  cplx<double> e[NB][NB], l[NB][NB], te[NB][NB], tl[NB][NB];
-  for (int i = 0; i < NB; ++i)
-    for (int j = 0; j < NB; ++j) {
-      e[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
-      l[i][j] = mk(0.0, 0.0);
-    }
-  // e_k = 1 + a e_{k+1} / k,  l_k = (om e_{k+1} + a l_{k+1}) / k
-  for (int k = K; k >= 1; --k) {
-    const double rk = 1.0 / k;
-    for (int i = 0; i < NB; ++i)
-      for (int j = 0; j < NB; ++j) {
-        cplx<double> se = mk(0.0, 0.0), sl = mk(0.0, 0.0);
-        for (int q = 0; q < NB; ++q) {
-          se = cfma(a[i][q], e[q][j], se);
-          sl = cfma(om[i][q], e[q][j], sl);
-          sl = cfma(a[i][q], l[q][j], sl);
-        }
-        te[i][j] = rk * se + mk(i == j ? 1.0 : 0.0, 0.0);
-        tl[i][j] = rk * sl;
-      }
-    for (int i = 0; i < NB; ++i)
-      for (int j = 0; j < NB; ++j) {
-        e[i][j] = te[i][j];
-        l[i][j] = tl[i][j];
-      }
-  }
-  for (int s = 0; s < sq; ++s) {
-    for (int i = 0; i < NB; ++i)
-      for (int j = 0; j < NB; ++j) {
-        cplx<double> se = mk(0.0, 0.0), sl = mk(0.0, 0.0);
-        for (int q = 0; q < NB; ++q) {
-          se = cfma(e[i][q], e[q][j], se);
-          sl = cfma(l[i][q], e[q][j], sl);
-          sl = cfma(e[i][q], l[q][j], sl);
-        }
-        te[i][j] = se;
-        tl[i][j] = sl;
-      }
-    for (int i = 0; i < NB; ++i)
-      for (int j = 0; j < NB; ++j) {
-        e[i][j] = te[i][j];
-        l[i][j] = tl[i][j];
-      }
-  }
-  for (int i = 0; i < NB; ++i)
-    for (int j = 0; j < NB; ++j) om[i][j] = l[i][j];
-}
-
 // Thread per (site, chirality block c): Omega_c = X_c Y_c^+ (Xe non-null)
-// + cdet D_oo^{-1} (odd sites), exponential form (EXPO) Omega_c <- L(A_c, Omega_c),
-// then this block's share of Lam_p for the six planes into K[c][p][b][a][V].
-template <int D, bool EXPO>
+// + cdet D_oo^{-1} (odd sites), then this block's share of Lam_p for the six
+// planes into K[c][p][b][a][V] (regular clover; the exponential form is
+// k_clover_insert_rows).
+template <int D>
 __global__ __launch_bounds__(64) void k_clover_insert(const cplx<double> *Xe, const cplx<double> *Xo,
                                                       const cplx<double> *Ye, const cplx<double> *Yo,
                                                       const cplx<double> *__restrict__ clov,
@@ -584,21 +514,6 @@ __global__ __launch_bounds__(64) void k_clover_insert(const cplx<double> *Xe, co
     for (int i = 0; i < NB; ++i)
       for (int j = 0; j < NB; ++j) Om[i][j] = Om[i][j] + cdet * herm_entry(Mi, g.stride, NB, i, j);
   }
-  if constexpr (EXPO) {
-    // A = (i/4) c_sw sum_p S[p][c][s][t] F_p[a][b] / (4 + m), as in k_clover_finish
-    cplx<double> A[NB][NB];
-    const double f = 0.25 * csw / (4.0 + m0);
-    for (int s = 0; s < 2; ++s)
-      for (int a = 0; a < D; ++a)
-        for (int tt = 0; tt < 2; ++tt)
-          for (int b = 0; b < D; ++b) {
-            cplx<double> acc = mk(0.0, 0.0);
-            for (int p = 0; p < 6; ++p)
-              acc = cfma(S.v[p][c][s][tt], F[((size_t)p * D * D + a * D + b) * V + lex], acc);
-            A[s * D + a][tt * D + b] = mk(-f * acc.im, f * acc.re);
-          }
-    expm_frechet<NB>(A, Om);
-  }
   // S.v holds 2 sigma
   for (int p = 0; p < 6; ++p)
     for (int b = 0; b < D; ++b)
@@ -608,6 +523,185 @@ __global__ __launch_bounds__(64) void k_clover_insert(const cplx<double> *Xe, co
           for (int tt = 0; tt < 2; ++tt) acc = cfma(S.v[p][c][s][tt], Om[tt * D + b][s * D + a], acc);
         K[(((size_t)(c * 6 + p) * D + b) * D + a) * V + lex] = 0.5 * acc;
       }
+}
+
+// Exponential form: as k_clover_insert with Omega_c <- L(A_c, Omega_c) before
+// the K entries, L the Frechet derivative of exp at A = C / (4 + m) along
+// Omega: scaling by 2^-s (s from the largest column sum of |A|, down to 1/4),
+// Horner for exp(A') and its derivative along Omega / 2^s (Taylor degree 12,
+// as in expm), then s squarings (e, l) <- (e e, l e + e l).
+// NB = 2 d_R lanes per (site, chirality block): lane i holds row i of A,
+// Omega and of the iterates and reads the other rows from LDS at each matrix
+// product (one lane holding whole NB x NB matrices spills them to scratch).  64-lane blocks (one wavefront) hold MPB = 64 / NB matrices;
+// the lanes past MPB * NB and past the last matrix follow the barriers and
+// store nothing (the former write no LDS either).  Every barrier is reached
+// the same number of times by all lanes: the squarings run to the block's
+// largest count, a matrix that needs fewer keeping its iterates.
+template <int D>
+__global__ __launch_bounds__(64) void k_clover_insert_rows(const cplx<double> *Xe, const cplx<double> *Xo,
+                                                           const cplx<double> *Ye, const cplx<double> *Yo,
+                                                           const cplx<double> *__restrict__ clov,
+                                                           const cplx<double> *__restrict__ F,
+                                                           cplx<double> *__restrict__ K, Geom g, SigmaBlocks S,
+                                                           double m0, double csw, double cdet) {
+  constexpr int NB = 2 * D, MPB = 64 / NB;
+  __shared__ cplx<double> se[MPB][NB][NB], sl[MPB][NB][NB];
+  const size_t V = 2 * (size_t)g.Vh;
+  const int mloc0 = (int)threadIdx.x / NB;
+  const bool lane_used = mloc0 < MPB;
+  const int mloc = lane_used ? mloc0 : MPB - 1;
+  const int i = lane_used ? (int)threadIdx.x - mloc * NB : 0;   // row of this lane
+  const size_t m0g = (size_t)blockIdx.x * MPB + mloc;
+  const bool valid = lane_used && m0g < 2 * V;
+  const size_t mg = m0g < 2 * V ? m0g : 2 * V - 1;
+  const int c = (int)(mg / V);
+  const size_t lex = mg - (size_t)c * V;
+  size_t r = lex;
+  const int z = (int)(r % g.Z); r /= g.Z;
+  const int y = (int)(r % g.Y); r /= g.Y;
+  const int x = (int)(r % g.X);
+  const int t = (int)(r / g.X);
+  const int par = (t + x + y + z) & 1;
+  const size_t cb = lex >> 1;
+  const int si = i / D, ai = i - si * D;   // row i = (spin si, colour ai) of the block
+  cplx<double> om[NB], a[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) om[j] = mk(0.0, 0.0);
+  if (Xe) {
+    const cplx<double> *X = par ? Xo : Xe, *Y = par ? Yo : Ye;
+    const cplx<double> xi = X[(size_t)((2 * c + si) * D + ai) * g.stride + cb];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int sj = j / D, aj = j - sj * D;
+      const cplx<double> yj = Y[(size_t)((2 * c + sj) * D + aj) * g.stride + cb];
+      om[j] = mk(xi.re * yj.re + xi.im * yj.im, xi.im * yj.re - xi.re * yj.im);
+    }
+  }
+  if (cdet != 0.0 && par == 1) {
+    const cplx<double> *Mi = clov + (size_t)(2 + c) * (NB * (NB + 1) / 2) * g.stride + cb;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) om[j] = om[j] + cdet * herm_entry(Mi, g.stride, NB, i, j);
+  }
+  // row i of A = (i/4) c_sw sum_p S[p][c][s][t] F_p[a][b] / (4 + m)
+  const double f = 0.25 * csw / (4.0 + m0);
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      cplx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int p = 0; p < 6; ++p)
+        acc = cfma(S.v[p][c][si][tt], F[((size_t)p * D * D + ai * D + b) * V + lex], acc);
+      a[tt * D + b] = mk(-f * acc.im, f * acc.re);
+    }
+  // scaling: the maximum column sum of |A|, from LDS
+  if (lane_used)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) se[mloc][i][j] = mk(sqrt(a[j].re * a[j].re + a[j].im * a[j].im), 0.0);
+  __syncthreads();
+  double nrm = 0.0;
+  for (int j = 0; j < NB; ++j) {
+    double sum = 0.0;
+    for (int q = 0; q < NB; ++q) sum += se[mloc][q][j].re;
+    nrm = sum > nrm ? sum : nrm;
+  }
+  __syncthreads();
+  int sq = 0;
+  while (nrm > 0.25 && sq < 60) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  int sqmax = sq;   // largest over the wavefront (the block)
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const int o = __shfl_xor(sqmax, off, 64);
+    sqmax = o > sqmax ? o : sqmax;
+  }
+  const double sc = ldexp(1.0, -sq);
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    a[j] = sc * a[j];
+    om[j] = sc * om[j];
+  }
+  constexpr int KT = 12;   // as in expm
+  cplx<double> e[NB], l[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    e[j] = mk(i == j ? 1.0 : 0.0, 0.0);
+    l[j] = mk(0.0, 0.0);
+  }
+  // e_k = 1 + a e_{k+1} / k,  l_k = (om e_{k+1} + a l_{k+1}) / k
+  for (int k = KT; k >= 1; --k) {
+    if (lane_used)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        se[mloc][i][j] = e[j];
+        sl[mloc][i][j] = l[j];
+      }
+    __syncthreads();
+    const double rk = 1.0 / k;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      cplx<double> ae = mk(0.0, 0.0), al = mk(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const cplx<double> eq = se[mloc][q][j];
+        ae = cfma(a[q], eq, ae);
+        al = cfma(om[q], eq, al);
+        al = cfma(a[q], sl[mloc][q][j], al);
+      }
+      e[j] = rk * ae + mk(i == j ? 1.0 : 0.0, 0.0);
+      l[j] = rk * al;
+    }
+    __syncthreads();
+  }
+  for (int s2 = 0; s2 < sqmax; ++s2) {
+    if (lane_used)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        se[mloc][i][j] = e[j];
+        sl[mloc][i][j] = l[j];
+      }
+    __syncthreads();
+    cplx<double> te[NB], tl[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      cplx<double> ae = mk(0.0, 0.0), al = mk(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const cplx<double> eq = se[mloc][q][j];
+        ae = cfma(e[q], eq, ae);
+        al = cfma(l[q], eq, al);
+        al = cfma(e[q], sl[mloc][q][j], al);
+      }
+      te[j] = ae;
+      tl[j] = al;
+    }
+    if (s2 < sq)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        e[j] = te[j];
+        l[j] = tl[j];
+      }
+    __syncthreads();
+  }
+  // Omega' = L(A, Omega): rows to LDS, then this matrix's K entries shared
+  // out over its NB lanes (S.v holds 2 sigma)
+  if (lane_used)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) sl[mloc][i][j] = l[j];
+  __syncthreads();
+  if (valid) {
+    for (int idx = i; idx < 6 * D * D; idx += NB) {
+      const int p = idx / (D * D), b = (idx / D) % D, a2 = idx % D;
+      cplx<double> acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) acc = cfma(S.v[p][c][s][tt], sl[mloc][tt * D + b][s * D + a2], acc);
+      K[(((size_t)(c * 6 + p) * D + b) * D + a2) * V + lex] = 0.5 * acc;
+    }
+  }
 }
 
 // Thread per (plane p, site x): for the four leaves l of Q_p(x), the matrix
@@ -831,12 +925,14 @@ static hipError_t clover_force_nr(void *P, const void *Xe, const void *Xo, const
     }
     const SigmaBlocks S = sigma_blocks();
     const dim3 ig((unsigned)((2 * V + 63) / 64));
-    if (expo)
-      hipLaunchKernelGGL((k_clover_insert<D, true>), ig, dim3(64), 0, st, (const cplx<double> *)Xe,
+    if (expo) {
+      constexpr int MPB = 64 / (2 * D);
+      const dim3 rg((unsigned)((2 * V + MPB - 1) / MPB));
+      hipLaunchKernelGGL((k_clover_insert_rows<D>), rg, dim3(64), 0, st, (const cplx<double> *)Xe,
                          (const cplx<double> *)Xo, (const cplx<double> *)Ye, (const cplx<double> *)Yo,
                          (const cplx<double> *)clov, (const cplx<double> *)F, (cplx<double> *)K, g, S, m0, csw, cdet);
-    else
-      hipLaunchKernelGGL((k_clover_insert<D, false>), ig, dim3(64), 0, st, (const cplx<double> *)Xe,
+    } else
+      hipLaunchKernelGGL((k_clover_insert<D>), ig, dim3(64), 0, st, (const cplx<double> *)Xe,
                          (const cplx<double> *)Xo, (const cplx<double> *)Ye, (const cplx<double> *)Yo,
                          (const cplx<double> *)clov, (const cplx<double> *)F, (cplx<double> *)K, g, S, m0, csw, cdet);
     hipLaunchKernelGGL((k_clover_leafgen<N, REP>), dim3((unsigned)((6 * V + 63) / 64)), dim3(64), 0, st,
