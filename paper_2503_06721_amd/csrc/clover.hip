@@ -97,6 +97,18 @@ __constant__ LeafStep kLeaf[4][4] = {
     // U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^+
     {{0, -1, 1, 1}, {0, -1, 0, 0}, {1, -1, 1, 0}, {0, 0, 0, 1}},
 };
+// The same table for the loops unrolled over (leaf, step), whose lookups then
+// fold into constants.
+__device__ constexpr LeafStep kLeafC[4][4] = {
+    // U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
+    {{0, 0, 0, 0}, {1, 0, 1, 0}, {0, 1, 0, 1}, {0, 0, 1, 1}},
+    // U_nu(x) U_mu(x-mu+nu)^+ U_nu(x-mu)^+ U_mu(x-mu)
+    {{0, 0, 1, 0}, {-1, 1, 0, 1}, {-1, 0, 1, 1}, {-1, 0, 0, 0}},
+    // U_mu(x-mu)^+ U_nu(x-mu-nu)^+ U_mu(x-mu-nu) U_nu(x-nu)
+    {{-1, 0, 0, 1}, {-1, -1, 1, 1}, {-1, -1, 0, 0}, {0, -1, 1, 0}},
+    // U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^+
+    {{0, -1, 1, 1}, {0, -1, 0, 0}, {1, -1, 1, 0}, {0, 0, 0, 1}},
+};
 
 // F scratch: F[p][A][B] of every site, [6][D][D][V] complex FP64.  Thread per
 // (plane, site), consecutive threads on consecutive sites.
@@ -734,10 +746,12 @@ __global__ __launch_bounds__(64) void k_clover_leafgen(const cplx<double> *__res
     for (int b = 0; b < D; ++b)
       for (int a = 0; a < D; ++a) Kh[b][a] = mk(lam[b][a].re + lam[a][b].re, lam[b][a].im - lam[a][b].im);
   }
+#pragma unroll
   for (int k = 0; k < 4; ++k) {
     cplx<double> L[N][N];
+#pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const LeafStep s = kLeaf[k][f];
+      const LeafStep s = kLeafC[k][f];
       cplx<double> u[N][N];
       load_link<N>(u, U, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
       if (f == 0) {
@@ -796,17 +810,20 @@ __global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__res
     const int lo = rho < nu ? rho : nu, hi = rho < nu ? nu : rho;
     const int p = lo == 0 ? hi - 1 : lo == 1 ? hi + 1 : 5;
     const int dsel = rho == lo ? 0 : 1;
+#pragma unroll
     for (int k = 0; k < 4; ++k)
+#pragma unroll
       for (int f = 0; f < 4; ++f) {
-        const LeafStep st = kLeaf[k][f];
+        const LeafStep st = kLeafC[k][f];
         if (st.dir != dsel) continue;
         // path from the corner x = y - a lo - b hi, links placed relative to y
         cplx<double> B[N][N];
         for (int i = 0; i < N; ++i)
           for (int j = 0; j < N; ++j) B[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
         const int nsteps = st.dag ? f + 1 : f;
+#pragma unroll
         for (int j = 0; j < nsteps; ++j) {
-          const LeafStep sj = kLeaf[k][j];
+          const LeafStep sj = kLeafC[k][j];
           cplx<double> u[N][N];
           load_link<N>(u, U, lex_at(g, cy, lo, sj.a - st.a, hi, sj.b - st.b), sj.dir ? hi : lo, sj.dag != 0);
           mul_right<N>(B, u);
