@@ -87,18 +87,8 @@ __device__ __forceinline__ void mul_right(cplx<double> (&acc)[N][N], const cplx<
 struct LeafStep {
   signed char a, b, dir, dag;   // dir 0 = mu, 1 = nu
 };
-__constant__ LeafStep kLeaf[4][4] = {
-    // U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
-    {{0, 0, 0, 0}, {1, 0, 1, 0}, {0, 1, 0, 1}, {0, 0, 1, 1}},
-    // U_nu(x) U_mu(x-mu+nu)^+ U_nu(x-mu)^+ U_mu(x-mu)
-    {{0, 0, 1, 0}, {-1, 1, 0, 1}, {-1, 0, 1, 1}, {-1, 0, 0, 0}},
-    // U_mu(x-mu)^+ U_nu(x-mu-nu)^+ U_mu(x-mu-nu) U_nu(x-nu)
-    {{-1, 0, 0, 1}, {-1, -1, 1, 1}, {-1, -1, 0, 0}, {0, -1, 1, 0}},
-    // U_nu(x-nu)^+ U_mu(x-nu) U_nu(x-nu+mu) U_mu(x)^+
-    {{0, -1, 1, 1}, {0, -1, 0, 0}, {1, -1, 1, 0}, {0, 0, 0, 1}},
-};
-// The same table for the loops unrolled over (leaf, step), whose lookups then
-// fold into constants.
+// Used in loops unrolled over (leaf, step), so that every lookup folds into a
+// constant.
 __device__ constexpr LeafStep kLeafC[4][4] = {
     // U_mu(x) U_nu(x+mu) U_mu(x+nu)^+ U_nu(x)^+
     {{0, 0, 0, 0}, {1, 0, 1, 0}, {0, 1, 0, 1}, {0, 0, 1, 1}},
@@ -130,10 +120,12 @@ __global__ __launch_bounds__(256) void k_clover_F(const cplx<double> *__restrict
   c[1] = (int)(r % g.X);
   c[0] = (int)(r / g.X);
   cplx<double> *Fp = F + (size_t)p * D * D * V + lex;
+#pragma unroll
   for (int k = 0; k < 4; ++k) {
     cplx<double> L[N][N];
+#pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const LeafStep s = kLeaf[k][f];
+      const LeafStep s = kLeafC[k][f];
       cplx<double> u[N][N];
       load_link<N>(u, U, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
       if (f == 0) {
