@@ -27,7 +27,7 @@ Generators T^a_R are the exact linearisation -i d/de R(exp(i e T^a)) at 0:
 
 Normalisations T_R and Casimirs C_2(R) follow the paper's table of
 representations.  The table prints T_R = (N-1)/2 for 2AS; the list of T_R
-values in Sec. 7.5.5 prints (N-2)/2, and only (N-2)/2 satisfies
+values in Sec. 7.6.5 prints (N-2)/2, and only (N-2)/2 satisfies
 T_R (N^2 - 1) = C_2(R) d_R with the table's own Casimir, so (N-2)/2 is used.
 """
 import numpy as np
@@ -82,7 +82,7 @@ def is_real(rep):
 
 
 def T_R(N, rep):
-    """Trace normalisation tr(T^a_R T^b_R) = T_R delta^ab (2AS per Sec. 7.5.5)."""
+    """Trace normalisation tr(T^a_R T^b_R) = T_R delta^ab (2AS per Sec. 7.6.5)."""
     return {FUND: 0.5, ADJ: float(N), SYM: (N + 2) / 2.0, ASYM: (N - 2) / 2.0}[rep]
 
 

@@ -482,10 +482,11 @@ __global__ void k_ms_init(MsScalars *S, const double *b2_partial, int nblk, Shif
   s.beta_old = 0.0;
   s.sigma0 = sigma0;
   s.iters = 0;
-  s.status = 0;
   s.nshift = nshift;
   s.base = base;
-  s.active = b2 > 0.0 ? 1 : 0;
+  // a non-finite right-hand side is a breakdown, not a zero source
+  s.status = isfinite(b2) ? 0 : -5;
+  s.active = (b2 > 0.0 && isfinite(b2)) ? 1 : 0;
   for (int k = 0; k < MAXSHIFT; ++k) {
     s.delta[k] = k < nshift ? d.v[k] : 0.0;
     s.zeta[k] = s.zeta_old[k] = s.zeta_new[k] = 1.0;

@@ -11,7 +11,7 @@ haar_links(dims, N, seed)
     Haar-random SU(N) per link: QR of a complex Gaussian matrix (Re, Im ~
     N(0, 1/2)), Q times the phases of diag(R) (Mezzadri's recipe), then the
     determinant is divided out with its principal N-th root, as in the
-    Gram-Schmidt-then-det-fix SU(N) projection of Sec. 7.5.4.
+    Gram-Schmidt-then-det-fix SU(N) projection of Sec. 7.6.4.
 expH_links(dims, N, eps, seed)
     U = exp(i eps H) per link with H Gaussian traceless Hermitian, distributed
     as sum_a h_a T^a with h_a ~ N(0,1) and tr T^a T^b = delta/2: off-diagonal

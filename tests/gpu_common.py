@@ -23,11 +23,29 @@ def wdirac():
     return importlib.import_module('paper_2503_06721_amd.wdirac')
 
 
-def rel(a, b):
+def rel2(a, b):
+    """||a - b||_2 / ||b||_2 over the whole output."""
     a = np.asarray(a)
     b = np.asarray(b)
     nb = np.linalg.norm(b.ravel())
     return np.linalg.norm((a - b).ravel()) / (nb if nb > 0 else 1.0)
+
+
+def relmax(a, b):
+    """||a - b||_inf / ||b||_inf, the max norm taken over real and imaginary
+    parts separately (the norm of the paper's Sec. 4.2.2)."""
+    d = np.asarray(a) - np.asarray(b)
+    b = np.asarray(b)
+    parts = lambda v: np.concatenate([np.real(v).ravel(), np.imag(v).ravel()]) if np.iscomplexobj(v) else v.ravel()
+    nb = np.abs(parts(b)).max() if b.size else 0.0
+    return (np.abs(parts(d)).max() if d.size else 0.0) / (nb if nb > 0 else 1.0)
+
+
+def rel(a, b):
+    """Parity metric: the larger of the relative 2-norm and the relative max
+    norm, so that one tolerance bounds both (a few wrong elements in a large
+    output move the max norm even where the 2-norm hides them)."""
+    return max(rel2(a, b), relmax(a, b))
 
 
 class Setup:

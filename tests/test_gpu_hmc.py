@@ -5,7 +5,7 @@ the same inputs; and, on an 8^4 lattice, reversibility and the O(eps^2)
 energy-error scaling of both integrators (the paper's table of integrators);
 the same with a clover term (regular and exponential), against the oracle's
 clover trajectory and, on 8^4, in its energy-error scaling; and the
-algorithmic tests of Sec. 7 (Creutz equality, acceptance rate) on a
+algorithmic tests of Sec. 8 (Creutz equality, acceptance rate) on a
 thermalised SU(2) adjoint ensemble."""
 import numpy as np
 import pytest
@@ -164,7 +164,7 @@ def test_clover_energy_error_scaling_8x8x8x8(W, expo):
 
 
 def test_creutz_equality_and_acceptance(W):
-    """The algorithmic tests of Sec. 7 on SU(2) with two adjoint flavours
+    """The algorithmic tests of Sec. 8 on SU(2) with two adjoint flavours
     (4^4, beta = 2.2): after thermalisation, the Creutz equality
     <exp(-dH)> = 1, a positive <dH>, and the acceptance rate against
     erfc(sqrt(<dH^2>/8)), each within four standard errors."""

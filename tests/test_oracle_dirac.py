@@ -186,6 +186,22 @@ def test_dhat_dagger_is_adjoint():
     assert np.abs(G5 @ Mh @ G5 - Md).max() < 1e-14
 
 
+def test_qhat_hermitian_and_squares_to_normal_op():
+    """Q-hat = gamma_5 D-hat (Sec. 5.3.3) is Hermitian, and Q-hat^2 is the
+    normal operator D-hat^+ D-hat that CG inverts (dense, 4x2^3)."""
+    dims = (4, 2, 2, 2)
+    _, UR, d = random_setup(dims, 2, 'SYM', 26)
+    m = -0.3
+    Q = dense.dense_matrix(lambda v: D.Qhat(v, UR, m, APBC, dims), (16, 4, d))
+    A = dense.dense_matrix(lambda v: D.normal_op(v, UR, m, APBC, dims), (16, 4, d))
+    scale = np.abs(Q).max()
+    assert np.abs(Q - Q.conj().T).max() < 1e-14 * scale
+    assert np.abs(Q @ Q - A).max() < 1e-13 * np.abs(A).max()
+    # not trivially Hermitian: D-hat itself is not
+    Mh = dense.dense_matrix(lambda v: D.Dhat(v, UR, m, APBC, dims), (16, 4, d))
+    assert np.abs(Mh - Mh.conj().T).max() > 1e-2
+
+
 def test_hop_at_sites_matches_field():
     dims = (4, 2, 4, 2)
     _, UR, d = random_setup(dims, 2, 'SYM', 24)
