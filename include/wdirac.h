@@ -273,6 +273,24 @@ int wdirac_apply_Moo(const wdirac_ctx *ctx, void *out, const void *in, double m0
 int wdirac_apply_dhat(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, double m0,
                       int dagger, int nrhs, int prec, void *workspace, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * out = D-hat in / D-hat^+ in as wdirac_apply_dhat, with no workspace
+ * argument.  The odd half field between the two hops lives in a fixed
+ * device array inside the library, wdirac_noalloc_scratch_bytes() = 64 MiB
+ * per GPU, held from the first call on that GPU until the process ends.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); the caller owns in, out and UR as for wdirac_apply_dhat.
+ * Every call on one GPU shares that GPU's array and overwrites it before
+ * reading it, so calls that overlap on one GPU (other streams, other
+ * threads, other contexts) race and must be serialised by the caller.
+ * Asynchronous on `stream`.  Errors: EINVAL (as wdirac_apply_dhat, and when
+ * the odd half field, wdirac_field_bytes(ctx, WDIRAC_FIELD_HALF_SPINOR,
+ * nrhs, prec) bytes, exceeds the scratch size), EHIP. */
+int wdirac_apply_dhat_noalloc(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, double m0,
+                              int dagger, int nrhs, int prec, void *stream);
+size_t wdirac_noalloc_scratch_bytes(void);
+
 /* Even-odd source preparation (Sec. 5.3.3, from the block form of D_m psi =
  * eta): b_e = (4+m0) eta_e - D_eo eta_o.  Packed FP64 halves.  Errors: EINVAL, EHIP. */
 int wdirac_eo_source(const wdirac_ctx *ctx, void *b_e, const void *eta_e, const void *eta_o,

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -707,6 +708,64 @@ int wdirac_apply_dhat(const wdirac_ctx *ctx, void *out, const void *in, const vo
   if (dagger != 0 && dagger != 1) return fail(WDIRAC_EINVAL, "dagger must be 0 or 1");
   if (in == out) return fail(WDIRAC_EINVAL, "in and out must not alias");
   return dhat(ctx, out, in, UR, m0, dagger, nrhs, prec, workspace, nullptr, S(stream));
+}
+
+}  // extern "C"
+
+// Scratch of wdirac_apply_dhat_noalloc: the odd half field between the two
+// hops, in a device array of fixed size that every call on a GPU shares (each
+// GPU holds its own copy from the first call until the process ends).  In
+// host code `scratch` names a host-side stand-in; kernels receive the device
+// address that hipGetSymbolAddress returns for the current device.
+static constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void **out) {
+  int dev = -1;
+  WD_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(WDIRAC_EHIP, "device index out of range for the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    WD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(WDIRAC_EHIP, "hipGetSymbolAddress returned a null scratch address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return WDIRAC_OK;
+}
+}  // namespace
+
+extern "C" {
+
+size_t wdirac_noalloc_scratch_bytes(void) { return kNoallocScratchBytes; }
+
+int wdirac_apply_dhat_noalloc(const wdirac_ctx *ctx, void *out, const void *in, const void *UR, double m0,
+                              int dagger, int nrhs, int prec, void *stream) {
+  WD_TRY(check_ctx(ctx));
+  WD_TRY(check_ptr(out, "out"));
+  WD_TRY(check_ptr(in, "in"));
+  WD_TRY(check_ptr(UR, "UR"));
+  WD_TRY(check_nrhs(ctx, nrhs));
+  WD_TRY(check_prec(prec));
+  if (dagger != 0 && dagger != 1) return fail(WDIRAC_EINVAL, "dagger must be 0 or 1");
+  if (in == out) return fail(WDIRAC_EINVAL, "in and out must not alias");
+  const size_t need = half_bytes(ctx, nrhs, prec);
+  if (need > kNoallocScratchBytes)
+    return fail(WDIRAC_EINVAL, "apply_dhat_noalloc: the odd half field needs " + std::to_string(need) +
+                                   " bytes, more than the " + std::to_string(kNoallocScratchBytes) +
+                                   "-byte scratch; use wdirac_apply_dhat with a workspace");
+  void *tmp = nullptr;
+  WD_TRY(scratch_address(&tmp));
+  // the first hop writes every element of tmp that the second reads: nothing
+  // left by an earlier call needs clearing
+  return dhat(ctx, out, in, UR, m0, dagger, nrhs, prec, tmp, nullptr, S(stream));
 }
 
 int wdirac_eo_source(const wdirac_ctx *ctx, void *b_e, const void *eta_e, const void *eta_o, const void *UR,

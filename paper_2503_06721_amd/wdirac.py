@@ -101,6 +101,8 @@ _SIGS = {
     'wdirac_force_clover_logdet': (_I, [_P, _P, _P, _P, _D, _D, _I, _D, _I, _I, _P, _P]),
     'wdirac_clover_logdet': (_I, [_P, ctypes.POINTER(_D), _P, _P, _P]),
     'wdirac_stream_probe': (_I, [_P, ctypes.c_size_t, _I, _I, ctypes.POINTER(_D), _P]),
+    'wdirac_apply_dhat_noalloc': (_I, [_P, _P, _P, _P, _D, _I, _I, _I, _P]),
+    'wdirac_noalloc_scratch_bytes': (ctypes.c_size_t, []),
     'wdirac_last_error': (ctypes.c_char_p, []),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -151,6 +153,11 @@ def stream_probe(elems=1 << 24, nread=7, reps=20, stream=None):
     _check(_lib.wdirac_stream_probe(_ptr(bufs), elems, nread, reps, ctypes.byref(out), _stream(stream)),
            'stream_probe')
     return out.value
+
+
+def noalloc_scratch_bytes():
+    """Size of the fixed device scratch of apply_dhat_noalloc."""
+    return _lib.wdirac_noalloc_scratch_bytes()
 
 
 class Lattice:
@@ -258,6 +265,11 @@ class Lattice:
         ws = workspace if workspace is not None else self.new_workspace(OP_DHAT, nrhs, prec)
         _check(_lib.wdirac_apply_dhat(self._h, _ptr(out), _ptr(inp), _ptr(UR), float(m0), dagger, nrhs, prec,
                                       _ptr(ws), _stream(stream)), 'apply_dhat')
+
+    def apply_dhat_noalloc(self, out, inp, UR, m0, dagger=0, nrhs=1, prec=F64, stream=None):
+        """apply_dhat without a workspace: the library's fixed scratch array holds the odd field."""
+        _check(_lib.wdirac_apply_dhat_noalloc(self._h, _ptr(out), _ptr(inp), _ptr(UR), float(m0), int(dagger),
+                                              nrhs, prec, _stream(stream)), 'apply_dhat_noalloc')
 
     def eo_source(self, b_e, eta_e, eta_o, UR, m0, nrhs=1, stream=None):
         _check(_lib.wdirac_eo_source(self._h, _ptr(b_e), _ptr(eta_e), _ptr(eta_o), _ptr(UR), float(m0), nrhs,
