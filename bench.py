@@ -35,7 +35,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = 'su3_fund_32x32x32x32'
 TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'dslash_eo_su3_fund_32x32x32x32_traffic.json')
-HOP_SOURCE = os.path.join(ROOT, 'paper_2503_06721_amd', 'csrc', 'hop.hip')
+HOP_SOURCES = [os.path.join(ROOT, 'paper_2503_06721_amd', 'csrc', f) for f in ('hop.hip', 'wd_hop.h')]
 
 
 def log(msg):
@@ -75,6 +75,16 @@ def device_copy_gbps(torch, n=1 << 28, reps=3):
     return ms, 2 * n * 8 / ms / 1e6
 
 
+def hop_sources_sha256():
+    """SHA-256 over the sources of the single-rhs hop kernels (hop.hip, then
+    wd_hop.h): a traffic record taken on other sources no longer applies."""
+    h = hashlib.sha256()
+    for p in HOP_SOURCES:
+        with open(p, 'rb') as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def measured_traffic(launch_bytes, shape):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None if the hop kernel source changed since the counters were taken or
@@ -82,9 +92,8 @@ def measured_traffic(launch_bytes, shape):
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
-        with open(HOP_SOURCE, 'rb') as f:
-            h = hashlib.sha256(f.read()).hexdigest()
-        if rec.get('hop_source_sha256') != h:
+        h = hop_sources_sha256()
+        if rec.get('hop_sources_sha256') != h:
             return None
         for row in rec.get('per_launch_shape', []):
             if all(shape.get(k) == v for k, v in row['launch_shape'].items()):
@@ -94,34 +103,148 @@ def measured_traffic(launch_bytes, shape):
         return None
 
 
-def cpu_baseline(cfg, U, psi, seconds_target=15.0):
-    """The CPU oracle (NumPy, FP64) timed on a bounded sample: repeated D_eo
-    applications on the full lattice until ~seconds_target have elapsed."""
+def host_info():
+    """The host the CPU baseline ran on: CPU model, logical CPUs, the CPUs this
+    process may use, and the thread settings NumPy sees."""
+    model = None
+    try:
+        with open('/proc/cpuinfo') as f:
+            for line in f:
+                if line.startswith('model name'):
+                    model = line.split(':', 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = None
+    return {'cpu_model': model, 'nproc': os.cpu_count(), 'usable_cpus': usable,
+            'OMP_NUM_THREADS': os.environ.get('OMP_NUM_THREADS'),
+            'threads_used': 1,
+            'threads_note': 'the oracle is NumPy einsum/roll/elementwise code, which runs on one thread'}
+
+
+BATCH_SHAPES = [(8, 8, 8, 8), (12, 12, 12, 12), (32, 16, 16, 16)]
+BATCH_M0, BATCH_SEED = -0.4, 1003
+
+
+def batch_inputs(synth):
+    """Links and Gaussian sources of the three-lattice SU(3) SYM batch."""
+    Us = [synth.expH_links(dd, 3, 0.3, BATCH_SEED + 10 + k) for k, dd in enumerate(BATCH_SHAPES)]
+    etas = [synth.gaussian_spinor((1,) + dd + (4, 6), BATCH_SEED + 20 + k) for k, dd in enumerate(BATCH_SHAPES)]
+    return Us, etas
+
+
+def small_systems(synth):
+    """The CG systems timed on both sides besides the benchmark lattice:
+    SU(2) FUND 4^4, SU(2) ADJ 32x16^3 and each lattice of the SU(3) SYM batch,
+    b = the even half of a Gaussian spinor.  Returns name -> (N, rep, dims,
+    bc, m0, U, eta)."""
+    out = {}
+    for name in ('su2_fund_4x4x4x4', 'su2_adj_32x16x16x16'):
+        cfg = synth.CONFIGS[name]
+        d = {'FUND': cfg['N'], 'ADJ': cfg['N'] ** 2 - 1}[cfg['rep']]
+        out[name] = (cfg['N'], cfg['rep'], cfg['dims'], cfg['bc'], cfg['m0'], synth.links_for(cfg),
+                     synth.gaussian_spinor((1,) + tuple(cfg['dims']) + (4, d), cfg['seed'] + 1000))
+    Us, etas = batch_inputs(synth)
+    for k, dd in enumerate(BATCH_SHAPES):
+        out['su3_sym_' + 'x'.join(map(str, dd))] = (3, 'SYM', dd, (-1, 1, 1, 1), BATCH_M0, Us[k], etas[k])
+    return out
+
+
+def gpu_small_solves(W, torch, systems):
+    """FP64 CG to 1e-10 on the GPU for each small system (autotuned hop, one
+    warm-up solve, then the median of three)."""
+    out = {}
+    for name, (N, rep, dims, bc, m0, U, eta) in systems.items():
+        lat = W.Lattice(N, rep, dims, bc)
+        UR = lat.new_links(W.F64)
+        lat.rep_links(UR, torch.from_numpy(U).cuda())
+        b = lat.pack_half(torch.from_numpy(eta).cuda(), 0)
+        lat.autotune(UR, W.F64, 1)
+        x = lat.new_half()
+        secs = []
+        for k in range(4):
+            x.zero_()
+            rc, st = lat.cg_eo(x, b, UR, m0, tol=1e-10, maxit=20000)
+            if k:
+                secs.append(st[0]['seconds'])
+        out[name] = {'seconds': round(float(sorted(secs)[1]), 5), 'iters': st[0]['iters'],
+                     'status': W.STATUS_NAMES.get(rc)}
+    return out
+
+
+def cpu_baseline(cfg, U, psi, gpu_c1, systems, gpu_small):
+    """The CPU oracle (NumPy, FP64, one thread) on a bounded sample, beside
+    the GPU:
+      * hop rate: two oracle D_eo applications on the benchmark lattice
+        (compulsory bytes per second, as the GPU's value);
+      * CG time-to-1e-10: the whole oracle CG on SU(2) FUND 4^4; on the
+        larger lattices one oracle application of A = D-hat^+ D-hat (the
+        cost of one CG iteration, less its few vector operations) times the
+        GPU's iteration count for the same system, a lower bound of the
+        oracle's time to solution."""
+    from oracle import cg as OCG
     from oracle import dirac as OD
     from oracle import lattice as OL
     from oracle import reps as OR
-    t0 = time.perf_counter()
+    t_start = time.perf_counter()
+    dims, bc, m0 = cfg['dims'], cfg['bc'], cfg['m0']
     UR = OR.represent(U, cfg['rep'])
-    t_rep = time.perf_counter() - t0
-    psi_o = OL.to_half(psi, cfg['dims'], 1)
-    n, t_hop = 0, 0.0
-    while t_hop < seconds_target and n < 20:
+    psi_o = OL.to_half(psi, dims, 1)
+    n, t_hop = 2, 0.0
+    for _ in range(n):
         t0 = time.perf_counter()
-        OD.D_eo(psi_o, UR, cfg['bc'], cfg['dims'])
+        OD.D_eo(psi_o, UR, bc, dims)
         t_hop += time.perf_counter() - t0
-        n += 1
     Vh = psi_o.shape[0]
     d = UR.shape[-1]
     gbs = hop_bytes_per_site(d, False, 8) * Vh * n / t_hop / 1e9
+    cg = {}
+
+    def per_iteration(URx, m, bcx, dd, x):
+        t0 = time.perf_counter()
+        OD.normal_op(x, URx, m, bcx, dd)
+        return time.perf_counter() - t0
+
+    t_it = per_iteration(UR, m0, bc, dims, OL.to_half(psi, dims, 0))
+    cg[WORKLOAD] = {'oracle_seconds_per_iteration': round(t_it, 3), 'iters': gpu_c1['iters'],
+                    'oracle_seconds_estimate': round(t_it * gpu_c1['iters'], 1),
+                    'gpu_seconds': gpu_c1['seconds'],
+                    'gpu_speedup': round(t_it * gpu_c1['iters'] / gpu_c1['seconds'], 1),
+                    'how': 'one oracle A application x GPU FP64 iterations'}
+    for name, (N, rep, dd, bcx, m, Ux, eta) in systems.items():
+        URx = OR.represent(Ux, rep)
+        b = OL.to_half(eta[0], dd, 0)
+        g = gpu_small.get(name)
+        if name == 'su2_fund_4x4x4x4':
+            t0 = time.perf_counter()
+            _, it, res = OCG.cg_eo(b, URx, m, bcx, dd, tol=1e-10, maxit=20000)
+            t = time.perf_counter() - t0
+            rec = {'oracle_seconds': round(t, 4), 'oracle_iters': it, 'oracle_true_rel_resid': res,
+                   'how': 'whole oracle CG'}
+            if g:
+                rec.update({'gpu_seconds': g['seconds'], 'gpu_iters': g['iters'],
+                            'gpu_speedup': round(t / g['seconds'], 2)})
+        else:
+            t_it = per_iteration(URx, m, bcx, dd, b)
+            rec = {'oracle_seconds_per_iteration': round(t_it, 4), 'how': 'one oracle A application x GPU FP64 iterations'}
+            if g:
+                rec.update({'iters': g['iters'], 'oracle_seconds_estimate': round(t_it * g['iters'], 2),
+                            'gpu_seconds': g['seconds'], 'gpu_speedup': round(t_it * g['iters'] / g['seconds'], 1)})
+        cg[name] = rec
+    total = time.perf_counter() - t_start
     return {'value': round(gbs, 4), 'unit': 'GB/s', 'cores': 1, 'kind': 'oracle',
-            'sample': f'{n} oracle D_eo applications on the full {cfg["dims"]} lattice '
-                      f'({t_hop:.1f} s; NumPy einsum/roll, single thread), plus one U->U_R in {t_rep:.1f} s',
-            'seconds_per_hop': t_hop / n}
+            'sample': f'{n} oracle D_eo applications on the full {dims} lattice ({t_hop:.1f} s) for the hop rate; '
+                      f'CG time-to-1e-10 on {len(cg)} systems (whole CG on 4^4, one A application elsewhere); '
+                      f'{total:.1f} s of CPU work in all, NumPy on one thread',
+            'host': host_info(), 'cg_time_to_1e-10': cg}
 
 
 FORM_NAMES = {0: 'site-parallel', 1: 'colour-split', 2: 'colour-split, paired directions',
               3: 'colour-split, compact links', 4: 'colour-split, compact links, paired directions',
-              5: 'colour-split, two directions per phase'}
+              5: 'colour-split, two directions per phase', 6: 'multi-rhs, links staged in LDS per block'}
 
 
 def tuned_form(best):
@@ -174,17 +297,19 @@ def dslash_roofline(W, torch, lat, UR, prec, nrhs, tuned, n=40):
     out = {'nrhs': nrhs, 'prec': 'f64' if prec == W.F64 else 'f32', 'form': tuned_form(tuned),
            'us_per_launch': round(us, 2), 'bytes_per_launch': by, 'GBps': round(gbs, 1),
            'frac': round(gbs / HBM_PEAK_GBS, 4)}
+    out['tuner_spread'] = round(tuned.get('spread', 0.0), 4)
+    out['tuner_runner_up_us'] = round(tuned.get('runner_up_us', 0.0), 2)
     if compact:
-        stored = W.Lattice(lat.N, lat.rep_name, lat.dims, lat.bc)   # untuned: options apply
-        best = None
-        for v in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR):
-            stored.set_option(W.OPT_HOP_VARIANT_F64 if prec == W.F64 else W.OPT_HOP_VARIANT_F32, v)
-            us_s, by_s = hop_rate(W, torch, stored, UR, prec, nrhs, n)
-            if best is None or us_s < best[0]:
-                best = (us_s, by_s, v)
-        gs = best[1] / (best[0] * 1e-6) / 1e9
-        out['stored_links'] = {'form': FORM_NAMES[best[2]], 'us_per_launch': round(best[0], 2),
-                               'bytes_per_launch': best[1], 'GBps': round(gs, 1), 'frac': round(gs / HBM_PEAK_GBS, 4)}
+        # the best stored-link shape, autotuned in a context whose tuner skips
+        # the compact forms
+        stored = W.Lattice(lat.N, lat.rep_name, lat.dims, lat.bc)
+        stored.set_option(W.OPT_TUNE_COMPACT, 0)
+        ts = stored.autotune(UR, prec, nrhs)
+        us_s, by_s = hop_rate(W, torch, stored, UR, prec, nrhs, n)
+        gs = by_s / (us_s * 1e-6) / 1e9
+        out['stored_links'] = {'form': tuned_form(ts), 'us_per_launch': round(us_s, 2), 'bytes_per_launch': by_s,
+                               'GBps': round(gs, 1), 'frac': round(gs / HBM_PEAK_GBS, 4),
+                               'tuner_spread': round(ts['spread'], 4)}
         del stored
     return out
 
@@ -223,23 +348,36 @@ def multi_rhs_cg(W, torch, synth, name='su3_sym_48x24x24x24'):
     out = {'workload': name, 'sources': f'{nrhs} point sources (spin k%4, colour k//4) at the origin',
            'hop_forms': forms, 'dslash_roofline': rates}
     for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
-        x.zero_()
-        rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, nrhs=nrhs, mode=mode, UR32=UR32, workspace=ws)
-        batched = st[0]['seconds']
+        def batched():
+            x.zero_()
+            rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, nrhs=nrhs, mode=mode, UR32=UR32,
+                               workspace=ws)
+            return st[0]['seconds'], (rc, st)
+
+        batched, (rc, st), batched_runs = median3(batched)
         worst = max(s['true_rel_resid'] for s in st)
-        log(f'[bench]   batched {key}: {batched:.3f} s, iters {[s["iters"] for s in st]}, worst residual {worst:.2e}')
-        seq, its = 0.0, []
-        for r in range(nrhs):
-            xr, br = x[r * per:(r + 1) * per], b[r * per:(r + 1) * per]
-            xr.zero_()
-            rc1, st1 = lat.cg_eo(xr, br, UR64, m0, tol=1e-10, maxit=20000, nrhs=1, mode=mode, UR32=UR32,
-                                 workspace=ws)
-            seq += st1[0]['seconds']
-            its.append(st1[0]['iters'])
-            worst = max(worst, st1[0]['true_rel_resid'])
-        log(f'[bench]   {nrhs} single solves {key}: {seq:.3f} s, iters {its}')
-        out[key] = {'batched_seconds': round(batched, 4), 'sequential_seconds': round(seq, 4),
+        log(f'[bench]   batched {key}: {batched:.3f} s {batched_runs}, iters {[s["iters"] for s in st]}, '
+            f'worst residual {worst:.2e}')
+
+        def sequential():
+            seq, its, res = 0.0, [], []
+            for r in range(nrhs):
+                xr, br = x[r * per:(r + 1) * per], b[r * per:(r + 1) * per]
+                xr.zero_()
+                rc1, st1 = lat.cg_eo(xr, br, UR64, m0, tol=1e-10, maxit=20000, nrhs=1, mode=mode, UR32=UR32,
+                                     workspace=ws)
+                seq += st1[0]['seconds']
+                its.append(st1[0]['iters'])
+                res.append(st1[0]['true_rel_resid'])
+            return seq, (its, res)
+
+        seq, (its, res), seq_runs = median3(sequential)
+        worst = max([worst] + res)
+        log(f'[bench]   {nrhs} single solves {key}: {seq:.3f} s {seq_runs}, iters {its}')
+        out[key] = {'batched_seconds': round(batched, 4), 'batched_runs': batched_runs,
+                    'sequential_seconds': round(seq, 4), 'sequential_runs': seq_runs,
                     'batched_speedup': round(seq / batched, 3), 'max_iters': max(s['iters'] for s in st),
+                    'per_rhs_iters': [s['iters'] for s in st], 'reliable_updates': [s['reliable_updates'] for s in st],
                     'worst_true_rel_resid': worst, 'status': W.STATUS_NAMES.get(rc)}
     out['mixed_batched_vs_f64_sequential'] = round(out['f64']['sequential_seconds'] / out['mixed']['batched_seconds'],
                                                    3)
@@ -277,54 +415,86 @@ def mixed_cg_large(W, torch, synth, name='su4_2as_96x48x48x48'):
     x = lat.new_half()
     out = {'workload': name, 'source': 'D-hat^+ eta, eta Gaussian', 'hop_forms': forms, 'dslash_roofline': rates}
     for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
-        x.zero_()
-        rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, mode=mode, UR32=UR32, workspace=ws)
-        st = st[0]
-        log(f'[bench]   {key}: {st["seconds"]:.3f} s, {st["iters"]} iterations, residual {st["true_rel_resid"]:.2e}')
-        out[key] = {'seconds': round(st['seconds'], 4), 'iters': st['iters'], 'hops': st['hops'],
+        def solve():
+            x.zero_()
+            rc, st = lat.cg_eo(x, b, UR64, m0, tol=1e-10, maxit=20000, mode=mode, UR32=UR32, workspace=ws)
+            return st[0]['seconds'], (rc, st[0])
+
+        secs, (rc, st), runs = median3(solve)
+        log(f'[bench]   {key}: {secs:.3f} s {runs}, {st["iters"]} iterations, residual {st["true_rel_resid"]:.2e}')
+        out[key] = {'seconds': round(secs, 4), 'runs': runs, 'iters': st['iters'], 'hops': st['hops'],
                     'reliable_updates': st['reliable_updates'], 'true_rel_resid': st['true_rel_resid'],
                     'status': W.STATUS_NAMES.get(rc)}
     out['mixed_speedup'] = round(out['f64']['seconds'] / out['mixed']['seconds'], 3)
     return out
 
 
+def median3(run):
+    """Median over three calls of run() -> (seconds, payload); returns
+    (median seconds, payload of the last call, all three times)."""
+    ts, last = [], None
+    for _ in range(3):
+        t, last = run()
+        ts.append(t)
+    return float(sorted(ts)[1]), last, [round(t, 4) for t in ts]
+
+
 def lattice_batch_cg(W, torch, synth):
     """SU(3) SYM on 8^4, 12^4 and 16^3x32 (m0 = -0.4, Gaussian sources on the
     even sites): one batched CG call over the three lattices against three
-    separate single-lattice calls, FP64."""
-    shapes = [(8, 8, 8, 8), (12, 12, 12, 12), (32, 16, 16, 16)]
-    m0, bc, seed = -0.4, (-1, 1, 1, 1), 1003
+    separate single-lattice calls, FP64 and mixed; medians of three solves
+    after one warm-up."""
     log('[bench] batch of three lattices: generating inputs')
-    Us = [torch.from_numpy(synth.expH_links(dd, 3, 0.3, seed + 10 + k)).cuda() for k, dd in enumerate(shapes)]
-    etas = [torch.from_numpy(synth.gaussian_spinor((1,) + dd + (4, 6), seed + 20 + k)).cuda()
-            for k, dd in enumerate(shapes)]
-    lat = W.Lattice(3, 'SYM', shapes, bc)
-    UR = lat.new_links(W.F64)
-    lat.rep_links(UR, torch.cat([u.reshape(-1, 4, 3, 3) for u in Us]))
-    b = lat.pack_half(torch.cat([e.reshape(-1, 4, 6) for e in etas]), 0)
-    lat.autotune(UR, W.F64, 1)
-    x = lat.new_half()
-    lat.cg_eo(x, b, UR, m0, tol=1e-10, maxit=20000)       # warm-up
-    x.zero_()
-    rc, st = lat.cg_eo(x, b, UR, m0, tol=1e-10, maxit=20000)
-    out = {'lattices': ['x'.join(map(str, dd)) for dd in shapes], 'batched_seconds': round(st[0]['seconds'], 4),
-           'batched_iters': [s['iters'] for s in st], 'status': W.STATUS_NAMES.get(rc)}
-    sep, its = 0.0, []
-    for k, dd in enumerate(shapes):
-        l1 = W.Lattice(3, 'SYM', dd, bc)
-        U1 = l1.new_links(W.F64)
-        l1.rep_links(U1, Us[k])
-        b1 = l1.pack_half(etas[k], 0)
-        l1.autotune(U1, W.F64, 1)
-        x1 = l1.new_half()
-        l1.cg_eo(x1, b1, U1, m0, tol=1e-10, maxit=20000)   # warm-up
-        x1.zero_()
-        rc1, st1 = l1.cg_eo(x1, b1, U1, m0, tol=1e-10, maxit=20000)
-        sep += st1[0]['seconds']
-        its.append(st1[0]['iters'])
-    out.update({'separate_seconds': round(sep, 4), 'separate_iters': its,
-                'batched_speedup': round(sep / out['batched_seconds'], 3)})
-    log(f'[bench]   batched {out["batched_seconds"]} s vs separate {out["separate_seconds"]} s')
+    Us, etas = batch_inputs(synth)
+    Ug = [torch.from_numpy(u).cuda() for u in Us]
+    eg = [torch.from_numpy(e).cuda() for e in etas]
+    lat = W.Lattice(3, 'SYM', BATCH_SHAPES, (-1, 1, 1, 1))
+    UR64, UR32 = lat.new_links(W.F64), lat.new_links(W.F32)
+    Ucat = torch.cat([u.reshape(-1, 4, 3, 3) for u in Ug])
+    lat.rep_links(UR64, Ucat, W.F64)
+    lat.rep_links(UR32, Ucat, W.F32)
+    b = lat.pack_half(torch.cat([e.reshape(-1, 4, 6) for e in eg]), 0)
+    lat.autotune(UR64, W.F64, 1)
+    lat.autotune(UR32, W.F32, 1)
+    singles = []
+    for k, dd in enumerate(BATCH_SHAPES):
+        l1 = W.Lattice(3, 'SYM', dd, (-1, 1, 1, 1))
+        u64, u32 = l1.new_links(W.F64), l1.new_links(W.F32)
+        l1.rep_links(u64, Ug[k], W.F64)
+        l1.rep_links(u32, Ug[k], W.F32)
+        l1.autotune(u64, W.F64, 1)
+        l1.autotune(u32, W.F32, 1)
+        singles.append((l1, u64, u32, l1.pack_half(eg[k], 0)))
+    out = {'lattices': ['x'.join(map(str, dd)) for dd in BATCH_SHAPES], 'repeats': 'median of 3 after a warm-up'}
+    for mode, key in ((W.CG_F64, 'f64'), (W.CG_MIXED, 'mixed')):
+        x = lat.new_half()
+
+        def batched():
+            x.zero_()
+            rc, st = lat.cg_eo(x, b, UR64, BATCH_M0, tol=1e-10, maxit=20000, mode=mode, UR32=UR32)
+            return st[0]['seconds'], (rc, st)
+
+        batched()   # warm-up
+        tb, (rc, st), tbs = median3(batched)
+
+        def separate():
+            tot, its, res = 0.0, [], []
+            for l1, u64, u32, b1 in singles:
+                x1 = l1.new_half()
+                rc1, st1 = l1.cg_eo(x1, b1, u64, BATCH_M0, tol=1e-10, maxit=20000, mode=mode, UR32=u32)
+                tot += st1[0]['seconds']
+                its.append(st1[0]['iters'])
+                res.append(st1[0]['true_rel_resid'])
+            return tot, (its, res)
+
+        separate()  # warm-up
+        ts, (its, res), tss = median3(separate)
+        out[key] = {'batched_seconds': round(tb, 4), 'batched_runs': tbs, 'batched_iters': [s_['iters'] for s_ in st],
+                    'batched_worst_true_rel_resid': max(s_['true_rel_resid'] for s_ in st),
+                    'status': W.STATUS_NAMES.get(rc), 'separate_seconds': round(ts, 4), 'separate_runs': tss,
+                    'separate_iters': its, 'batched_speedup': round(ts / tb, 3)}
+        log(f'[bench]   batch {key}: batched {tb:.4f} s vs separate {ts:.4f} s')
+    out['mixed_batched_vs_f64_separate'] = round(out['f64']['separate_seconds'] / out['mixed']['batched_seconds'], 3)
     return out
 
 
@@ -454,33 +624,54 @@ def rhmc_and_clover(W, torch, synth, name='su3_fund_32x32x32x32'):
     return {'workload': name, 'multi_shift_time_to_1e-10': ms, 'clover_cg_time_to_1e-10': cl}
 
 
-def hmc_trajectory(W, torch, synth, name='su2_adj_32x16x16x16'):
-    """One HMC trajectory (second-order Omelyan, tau = 0.5 in 5 steps, Wilson
-    plaquette beta = 2.2 plus the two-flavour adjoint pseudofermion) on SU(2)
-    ADJ 32x16^3: wall time, CG iterations, dH."""
+def hmc_trajectory(W, torch, synth, name='su2_adj_32x16x16x16', n_therm=20, n_meas=4):
+    """HMC on SU(2) ADJ 32x16^3 (second-order Omelyan, tau = 0.5 in 5
+    steps, Wilson plaquette beta = 2.2 plus the two-flavour adjoint
+    pseudofermion): n_therm thermalisation trajectories from the synthetic
+    start (each accepted, fresh momenta and pseudofermions every time), then
+    n_meas timed HMC updates with the Metropolis test: seconds per
+    trajectory, CG iterations, dH and acceptance."""
+    import numpy as np
     from paper_2503_06721_amd.hmc import HMC
     cfg = synth.CONFIGS[name]
-    dims, m0 = cfg['dims'], cfg['m0']
-    lat = W.Lattice(cfg['N'], cfg['rep'], dims, cfg['bc'])
+    dims, m0, N = cfg['dims'], cfg['m0'], cfg['N']
+    lat = W.Lattice(N, cfg['rep'], dims, cfg['bc'])
     U = torch.from_numpy(synth.links_for(cfg)).cuda()
     hmc = HMC(lat, 2.2, m0, tol=1e-10)
     lat.rep_links(hmc.UR, U)
     lat.autotune(hmc.UR, W.F64, 1)
     g = torch.Generator(device='cuda')
     g.manual_seed(cfg['seed'] + 31)
-    w = torch.randn(tuple(dims) + (4, cfg['N'] ** 2 - 1), dtype=torch.float64, device='cuda', generator=g)
-    eta = torch.randn((1,) + tuple(dims) + (4, lat.d), dtype=torch.complex128, device='cuda', generator=g)
-    pi, phi = hmc.refresh(U, w, lat.pack_half(eta, 0))
-    torch.cuda.synchronize()
+    eps, nsteps = 0.1, 5
+    dH_therm = []
     t0 = time.perf_counter()
-    H0, H1 = hmc.trajectory(U, pi, phi, 0.1, 5, 'omelyan2')
+    for _ in range(n_therm):
+        w = torch.randn(tuple(dims) + (4, N * N - 1), dtype=torch.float64, device='cuda', generator=g)
+        re = torch.randn((1,) + tuple(dims) + (4, lat.d), dtype=torch.float64, device='cuda', generator=g)
+        im = torch.randn((1,) + tuple(dims) + (4, lat.d), dtype=torch.float64, device='cuda', generator=g)
+        pi, phi = hmc.refresh(U, w, lat.pack_half(torch.complex(re, im) * (0.5 ** 0.5), 0))
+        H0, H1 = hmc.trajectory(U, pi, phi, eps, nsteps, 'omelyan2')
+        dH_therm.append(H1 - H0)
     torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
-    log(f'[bench] HMC trajectory: {secs:.3f} s, dH {H1 - H0:.3e}, CG iterations {hmc.cg_iters}')
-    return {'workload': name, 'integrator': 'omelyan2', 'tau': 0.5, 'steps': 5, 'beta': 2.2,
-            'seconds': round(secs, 4), 'dH': H1 - H0, 'cg_iterations': hmc.cg_iters,
-            'start': 'synthetic exp(i 0.3 H) links, far from equilibrium at this beta, so |dH| is large; '
-                     'energy conservation is checked in the tests (dH ~ eps^2)'}
+    t_therm = time.perf_counter() - t0
+    it0 = hmc.cg_iters
+    dH, acc, secs = [], [], []
+    for _ in range(n_meas):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, a = hmc.update(U, eps, nsteps, g, 'omelyan2')
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+        dH.append(d)
+        acc.append(bool(a))
+    log(f'[bench] HMC: thermalisation dH {[round(v, 3) for v in dH_therm]}; measured dH {dH}, '
+        f'{np.median(secs):.3f} s per trajectory')
+    return {'workload': name, 'integrator': 'omelyan2', 'tau': eps * nsteps, 'steps': nsteps, 'beta': 2.2,
+            'thermalisation': {'trajectories': n_therm, 'seconds': round(t_therm, 3),
+                               'first_dH': dH_therm[0], 'last_dH': dH_therm[-1]},
+            'seconds_per_trajectory': round(float(np.median(secs)), 4), 'dH': dH, 'accepted': acc,
+            'cg_iterations_per_trajectory': (hmc.cg_iters - it0) / n_meas,
+            'start': f'{n_therm} always-accepted trajectories from the synthetic exp(i 0.3 H) links'}
 
 
 SECTIONS = {'multi_rhs': multi_rhs_cg, 'mixed_large': mixed_cg_large, 'lattice_batch': lattice_batch_cg,
@@ -573,7 +764,8 @@ def main():
     log(f'[bench] autotuned hop shapes: {tuned}')
     variant_name = {W.HOP_SITE: 'k_hop_sp (lane per site)', W.HOP_COLOUR: 'k_hop_cs (colour-split)',
                     W.HOP_COLOUR_PAIR: 'k_hop_cs (colour-split, paired directions)',
-                    W.HOP_COLOUR_QUAD: 'k_hop_cs (colour-split, two directions per phase)'}
+                    W.HOP_COLOUR_QUAD: 'k_hop_cs (colour-split, two directions per phase)',
+                    W.HOP_MULTI: 'k_hop_mr (links staged per block)'}
 
     def step(record):
         lat.rep_links(UR64, Ug, W.F64)
@@ -650,7 +842,9 @@ def main():
                      'us_per_launch_median_of_steps': round(hop_ms_median * 1e3, 3),
                      'frac_of_device_copy': round(gbs / copy_gbs, 4),
                      'stream_7r1w_GBps': stream_gbs,
-                     'frac_of_stream_7r1w': round(gbs / stream_gbs, 4)},
+                     'frac_of_stream_7r1w': round(gbs / stream_gbs, 4),
+                     'tuner_spread': round(tuned['f64']['spread'], 4),
+                     'tuner_runner_up_us': round(tuned['f64']['runner_up_us'], 2)},
     }
     if not args.no_cg:
         def agg(key):
@@ -675,10 +869,11 @@ def main():
         torch.cuda.empty_cache()
         out['hmc_trajectory'] = hmc_trajectory(W, torch, synth)
     if not args.no_cpu:
-        log('[bench] timing the CPU oracle on a bounded sample')
-        cb = cpu_baseline(cfg, U, psi[0])
-        cb.pop('seconds_per_hop')
-        out['cpu_baseline'] = cb
+        log('[bench] small CG systems on the GPU, then the CPU oracle on a bounded sample')
+        systems = small_systems(synth)
+        gpu_small = gpu_small_solves(W, torch, systems)
+        gpu_c1 = out.get('cg_time_to_1e-10', {}).get('f64') or {'seconds': float('nan'), 'iters': 0}
+        out['cpu_baseline'] = cpu_baseline(cfg, U, psi[0], gpu_c1, systems, gpu_small)
     print(json.dumps(out), flush=True)
 
 

@@ -130,6 +130,12 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                      5 = as 1 with two directions (four
  *                                          hops) staged per barrier phase
  *                                          (d_R <= 4; 1 rhs per block)
+ *                                      6 = several right-hand sides per
+ *                                          block, one wavefront each, the
+ *                                          tile's link entries staged once
+ *                                          per block in LDS (complex d_R = 3
+ *                                          and 6, real d_R = 3; 1, 2, 3, 4,
+ *                                          6 or 12 rhs per block)
  *   WDIRAC_OPT_XCD_REMAP               1 (default) = give each XCD a
  *                                      contiguous range of site tiles
  *   WDIRAC_OPT_CG_CHECK_EVERY          CG iterations between host checks of
@@ -142,7 +148,9 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                      b divides T and tiles do not straddle
  *                                      (t, x) rows)
  *   WDIRAC_OPT_HOP_NR_F64 / _F32       right-hand sides sharing each link load
- *                                      (1..6).  Colour-split form: the
+ *                                      (1..12).  Form 6: the largest of 1,
+ *                                      2, 3, 4, 6, 12 not above it that
+ *                                      divides nrhs.  Colour-split form: the
  *                                      largest divisor of nrhs not above it
  *                                      that the form supports is used (1..4
  *                                      within the LDS budget; 6 in the
@@ -157,6 +165,9 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                      (after the caller's stream has
  *                                      drained); 0: direct launches on the
  *                                      caller's stream
+ *   WDIRAC_OPT_TUNE_COMPACT            1 (default): wdirac_autotune() also
+ *                                      times the compact-link forms 3, 4;
+ *                                      0: stored-link forms only
  * Options set here apply to every nrhs except those that wdirac_autotune()
  * has tuned.  Errors: EINVAL (unknown option or value), EUNSUPPORTED. */
 typedef enum {
@@ -168,26 +179,31 @@ typedef enum {
   WDIRAC_OPT_HOP_NR_F64 = 5,
   WDIRAC_OPT_HOP_NR_F32 = 6,
   WDIRAC_OPT_TILE_TBLOCK = 7,
-  WDIRAC_OPT_CG_GRAPH = 8
+  WDIRAC_OPT_CG_GRAPH = 8,
+  WDIRAC_OPT_TUNE_COMPACT = 9
 } wdirac_option;
 int wdirac_set_option(wdirac_ctx *ctx, int option, double value);
 
 /* Launch shape of the hopping kernel chosen by wdirac_autotune(). */
 typedef struct {
-  int32_t variant;    /* WDIRAC_OPT_HOP_VARIANT_F64 values (0..5)        */
+  int32_t variant;    /* WDIRAC_OPT_HOP_VARIANT_F64 values (0..6)        */
   int32_t nr;         /* right-hand sides per block (colour-split form)  */
   int32_t xcd_remap;  /* 1 = contiguous tile ranges per XCD               */
   int32_t tblock;     /* t-block of the tile order (0 = lexicographic)    */
   int32_t candidates; /* number of shapes timed                           */
   double us;          /* mean time of one hop launch with that shape (best
                          round of the second pass)                        */
+  double spread;      /* (slowest - fastest) / fastest over the chosen
+                         shape's five second-pass rounds                  */
+  double runner_up_us;/* best round of the second-fastest finalist        */
 } wdirac_tuning;
 
 /* Autotuner: times every available launch shape of the hopping kernel
  * (variant x right-hand sides per block x XCD tile mapping x tile order) for
  * nrhs right-hand sides in precision prec on the links UR (HIP events: 4
- * warm-up and 10 timed launches each, then the four fastest again in three
- * interleaved rounds of 20, each keeping its fastest round; launches
+ * warm-up and 10 timed launches each, then the four fastest again in five
+ * interleaved rounds of max(20, ~25 ms) launches, each keeping its fastest
+ * round; launches
  * alternate D_eo and D_oe over three fields so that every other launch reads
  * the output just written, as between the hops of a solver), and makes the
  * fastest the one used for this (prec, nrhs) by every later call on ctx (CG

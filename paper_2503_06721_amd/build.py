@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, 'csrc')
 BUILD = os.path.join(HERE, '_build')
 LIB = os.path.join(HERE, 'libwdirac.so')
-SOURCES = ['api.hip', 'hop.hip', 'rep.hip', 'blas.hip', 'force.hip', 'stream.hip', 'clover.hip', 'hmc.hip']
+SOURCES = ['api.hip', 'hop.hip', 'hop_mr.hip', 'rep.hip', 'blas.hip', 'force.hip', 'stream.hip', 'clover.hip', 'hmc.hip']
 HIPCC = os.environ.get('HIPCC', '/opt/rocm/bin/hipcc')
 ARCH = 'gfx950'
 FLAGS = [

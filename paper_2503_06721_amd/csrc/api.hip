@@ -32,6 +32,7 @@ struct wdirac_ctx {
   int cg_check_every;   // CG iterations between host convergence checks
   double mixed_delta;   // reliable-update trigger ||r|| < delta max||r||
   int cg_graph;         // replay the CG iterations between checks as a HIP graph
+  int tune_compact;     // the autotuner also times the compact-link forms
   mutable hipStream_t own = nullptr;   // the library's stream for graph capture (created on first use)
 };
 
@@ -133,9 +134,9 @@ struct Carver {
 size_t partial_doubles(const wdirac_ctx *c, int nrhs) {
   // rows (one per system, twice for the real and imaginary rows of a dot) of
   // the longest per-tile row any producer writes: the smallest tiles are the
-  // 64-site tiles of the colour-split hop
+  // 32-site tiles of the multi-rhs hop with two lanes per site
   int mx = 0;
-  for (int l = 0; l < c->nlat; ++l) mx = std::max(mx, (c->g[l].Vh + 63) / 64);
+  for (int l = 0; l < c->nlat; ++l) mx = std::max(mx, (c->g[l].Vh + 31) / 32);
   return (size_t)2 * nsys_of(c, nrhs) * mx;
 }
 
@@ -201,7 +202,7 @@ size_t compact_links_bytes(const wdirac_ctx *c, int prec) {
 int effective_nr(const wdirac_ctx *c, int pref, int nrhs, int prec, int variant) {
   // site-parallel form: 4 right-hand sides across the lanes of a wavefront, or 1
   if (variant == wd::HOP_SITE) return (pref >= 4 && nrhs % 4 == 0) ? 4 : 1;
-  for (int nr = std::min(pref, 6); nr > 1; --nr)
+  for (int nr = std::min(pref, variant == wd::HOP_MULTI ? 12 : 6); nr > 1; --nr)
     if (nrhs % nr == 0 && wd::hop_nr_supported(c->d, prec, variant, nr)) return nr;
   return 1;
 }
@@ -389,6 +390,7 @@ int wdirac_create_batch(wdirac_ctx **ctx, int Ng, int rep, const wdirac_geom *ge
   c->cg_check_every = 4;
   c->mixed_delta = 0.01;
   c->cg_graph = 1;
+  c->tune_compact = 1;
   *ctx = c;
   return WDIRAC_OK;
 }
@@ -470,7 +472,7 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
     case WDIRAC_OPT_HOP_VARIANT_F64:
     case WDIRAC_OPT_HOP_VARIANT_F32: {
       const int v = (int)value;
-      if (v < wd::HOP_SITE || v > wd::HOP_COLOUR_QUAD) return fail(WDIRAC_EINVAL, "hop variant out of range");
+      if (v < wd::HOP_SITE || v > wd::HOP_MULTI) return fail(WDIRAC_EINVAL, "hop variant out of range");
       if (!wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, v))
         return fail(WDIRAC_EUNSUPPORTED, "hop variant not available for this representation");
       ctx->hop_variant[option == WDIRAC_OPT_HOP_VARIANT_F64 ? 0 : 1] = v;
@@ -495,9 +497,13 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
       if (!(value >= 0 && value <= 64)) return fail(WDIRAC_EINVAL, "t-block must be in [0, 64]");
       ctx->tblock = (int)value;
       return WDIRAC_OK;
+    case WDIRAC_OPT_TUNE_COMPACT:
+      if (value != 0.0 && value != 1.0) return fail(WDIRAC_EINVAL, "compact tuning option must be 0 or 1");
+      ctx->tune_compact = (int)value;
+      return WDIRAC_OK;
     case WDIRAC_OPT_HOP_NR_F64:
     case WDIRAC_OPT_HOP_NR_F32:
-      if (!(value >= 1 && value <= 6)) return fail(WDIRAC_EINVAL, "right-hand sides per block must be in [1, 6]");
+      if (!(value >= 1 && value <= 12)) return fail(WDIRAC_EINVAL, "right-hand sides per block must be in [1, 12]");
       ctx->hop_nr[option == WDIRAC_OPT_HOP_NR_F64 ? 0 : 1] = (int)value;
       return WDIRAC_OK;
   }
@@ -526,10 +532,13 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
   for (int tb : tbs) {
     if (tb && (ctx->nlat > 1 || ctx->g[0].T % tb)) continue;
     for (int remap = 0; remap < 2; ++remap) {
-      for (int v = wd::HOP_COLOUR; v <= wd::HOP_COLOUR_QUAD; ++v) {
+      for (int v = wd::HOP_COLOUR; v <= wd::HOP_MULTI; ++v) {
         if (!wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, v)) continue;
-        for (int nr : {1, 2, 3, 4, 6})
-          if (effective_nr(ctx, nr, nrhs, prec, v) == nr) cands.push_back({v, nr, remap, tb});
+        if (!ctx->tune_compact && (v == wd::HOP_COMPACT || v == wd::HOP_COMPACT_PAIR)) continue;
+        // the multi-rhs form only where it shares links (nr > 1)
+        for (int nr : {1, 2, 3, 4, 6, 12})
+          if ((v != wd::HOP_MULTI || nr > 1) && effective_nr(ctx, nr, nrhs, prec, v) == nr)
+            cands.push_back({v, nr, remap, tb});
       }
       if (wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, wd::HOP_SITE)) {
         cands.push_back({wd::HOP_SITE, 1, remap, tb});
@@ -560,31 +569,44 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
     if (rc == WDIRAC_OK && hipEventElapsedTime(ms, e0, e1) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventElapsedTime");
     *ms /= (float)reps;
   };
-  // Pass 1: every candidate, 10 launches.  Pass 2: the best four again, three
-  // interleaved rounds of 20 launches, keeping each one's fastest round.
+  // Pass 1: every candidate, 10 launches.  Pass 2: the best four again, five
+  // interleaved rounds of at least 20 launches and about 25 ms each (so that
+  // millisecond-scale kernels are timed over many launches), keeping each
+  // one's fastest round; the spread of the pick's rounds is reported.
   std::vector<std::pair<float, int>> t1;
   for (size_t i = 0; i < cands.size() && rc == WDIRAC_OK; ++i) {
     float ms;
     time_cand(cands[i], 10, &ms);
     t1.push_back({ms, (int)i});
   }
-  float best_ms = 1e30f;
+  float best_ms = 1e30f, best_worst = 0.0f, second_ms = 0.0f;
   Cand pick = cands.front();
   if (rc == WDIRAC_OK) {
     std::sort(t1.begin(), t1.end());
     const size_t nfin = std::min<size_t>(4, t1.size());
-    std::vector<float> t2(nfin, 1e30f);
-    for (int round = 0; round < 3 && rc == WDIRAC_OK; ++round)
+    std::vector<float> t2(nfin, 1e30f), t2w(nfin, 0.0f);
+    std::vector<int> reps(nfin);
+    for (size_t j = 0; j < nfin; ++j)
+      reps[j] = std::min(1000, std::max(20, (int)(25.0f / std::max(t1[j].first, 1e-3f))));
+    for (int round = 0; round < 5 && rc == WDIRAC_OK; ++round)
       for (size_t j = 0; j < nfin && rc == WDIRAC_OK; ++j) {
         float ms;
-        time_cand(cands[t1[j].second], 20, &ms);
+        time_cand(cands[t1[j].second], reps[j], &ms);
         t2[j] = std::min(t2[j], ms);
+        t2w[j] = std::max(t2w[j], ms);
       }
+    size_t jb = 0;
     for (size_t j = 0; j < nfin; ++j)
       if (t2[j] < best_ms) {
         best_ms = t2[j];
-        pick = cands[t1[j].second];
+        jb = j;
       }
+    pick = cands[t1[jb].second];
+    best_worst = t2w[jb];
+    second_ms = 1e30f;
+    for (size_t j = 0; j < nfin; ++j)
+      if (j != jb) second_ms = std::min(second_ms, t2[j]);
+    if (nfin < 2) second_ms = best_ms;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -600,6 +622,8 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
     best->tblock = pick.tblock;
     best->candidates = (int)cands.size();
     best->us = best_ms * 1e3;
+    best->spread = best_ms > 0.0f ? (best_worst - best_ms) / best_ms : 0.0;
+    best->runner_up_us = second_ms * 1e3;
   }
   return WDIRAC_OK;
 }
@@ -922,14 +946,18 @@ static int cg_impl(const wdirac_ctx *ctx, void *x, const void *b, const void *UR
   for (;;) {
     WD_HIP(hipMemcpyAsync(hs.data(), w.sc, ns * sizeof(wd::CgScalars), hipMemcpyDeviceToHost, st));
     WD_HIP(hipStreamSynchronize(st));
-    bool any_active = false, any_update = false;
+    // a residual replacement runs once every system that is still iterating
+    // has asked for one (mixed mode) or has stopped (converged recursion,
+    // breakdown)
+    bool any_active = false, any_update = false, all_ready = true;
     for (int k = 0; k < ns; ++k) {
       any_active |= hs[k].active != 0;
       any_update |= hs[k].need_update != 0;
+      all_ready &= hs[k].active == 0 || hs[k].need_update != 0;
     }
     int max_iters = 0;
     for (int k = 0; k < ns; ++k) max_iters = std::max(max_iters, hs[k].iters);
-    if (!any_active && any_update) {
+    if (any_update && all_ready) {
       // residual replacement in FP64 (verifies convergence of the recursion)
       if (mixed) WD_HIP(wd::launch_accum_x(x, w.x32, f, st));
       WD_TRY(true_residual());

@@ -302,7 +302,9 @@ __global__ __launch_bounds__(BT) void k_cg_beta(CgScalars *S, const double *part
       s.active = 0;          // recursive residual converged: verify in FP64
       s.need_update = 1;
     } else if (delta > 0.0 && rn < delta * s.rmax) {
-      s.active = 0;          // mixed mode: pause for a reliable update
+      // mixed mode: ask for a reliable update and keep iterating until every
+      // other active system asks too, so that no system idles while the
+      // batched hops still stream its field
       s.need_update = 1;
     }
   }

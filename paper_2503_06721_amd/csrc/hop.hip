@@ -18,65 +18,11 @@
 //    no longer grows with d_R^2, which is what limits the site-parallel form
 //    for large representations.
 #include "wd_common.h"
+#include "wd_hop.h"
 #include "wd_kernels.h"
 #include "wd_rep.h"
 
 namespace wd {
-
-// ------------------------------------------------------------ tile mapping
-// Blocks are dispatched round-robin over the 8 XCDs of the chip.  With
-// remapping, XCD k receives a contiguous range of tiles, so the neighbours a
-// tile reads (mostly in nearby tiles) stay in that XCD's L2.
-__device__ __forceinline__ int tile_of_block(int b, int ntiles, int remap) {
-  if (!remap) return b;
-  const int q = ntiles >> 3, rmd = ntiles & 7;
-  const int x = b & 7, j = b >> 3;
-  return x * q + (x < rmd ? x : rmd) + j;
-}
-
-// Processing order of tiles.  With tb > 0 the tiles (each tiles_per_tx
-// tiles cover one (t, x) row of Y*Z lexicographic sites) are visited in the
-// order (t-block of tb slices, x, t within the block, tile within the row):
-// t-neighbours are then tiles_per_tx tiles apart instead of a whole t-slice,
-// so they are still in L2 when read.  tb = 0: lexicographic order.
-__device__ __forceinline__ int tile_order(int q, const HopArgs &a) {
-  if (a.tblock == 0) return q;
-  const int nb = a.tiles_per_tx, tb = a.tblock, X = a.lat[0].g.X;
-  const int per_tb = X * tb * nb;
-  const int tbi = q / per_tb;
-  int r = q - tbi * per_tb;
-  const int x = r / (tb * nb);
-  r -= x * tb * nb;
-  const int tin = r / nb;
-  const int yb = r - tin * nb;
-  return ((tbi * tb + tin) * X + x) * nb + yb;
-}
-
-// Lattice of a global tile index (the launch covers the tiles of every
-// lattice of a batch back to back).
-__device__ __forceinline__ int lattice_of_tile(const HopArgs &a, int tile) {
-  int l = 0;
-  while (l + 1 < a.nlat && tile >= a.lat[l + 1].tile0) ++l;
-  return l;
-}
-
-template <typename T, bool REAL>
-struct LinkT {
-  using type = cplx<T>;
-};
-template <typename T>
-struct LinkT<T, true> {
-  using type = T;
-};
-
-template <typename T>
-__device__ __forceinline__ cplx<T> link_mac(cplx<T> u, cplx<T> h, cplx<T> acc, bool conjugate) {
-  return conjugate ? cfma_conj(u, h, acc) : cfma(u, h, acc);
-}
-template <typename T>
-__device__ __forceinline__ cplx<T> link_mac(T u, cplx<T> h, cplx<T> acc, bool) {
-  return rfma(u, h, acc);
-}
 
 // ------------------------------------------------------- site-parallel form
 template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, bool NTL>
@@ -518,34 +464,6 @@ constexpr bool cs6_ok() {
   return D <= 4 && cs_fits<D, T, 6, 1>();
 }
 
-// Tile bookkeeping of a launch with tiles of ts sites: per-lattice tile
-// ranges, the partial-sum row length and counts, and the t-blocked order
-// (single lattices only: tiles_per_tx is the number of tiles covering one
-// (t, x) row of Y*Z sites; the order falls back to lexicographic if tiles
-// straddle rows or tb does not divide T).
-static void set_tiles(HopArgs &a, int ts, int nrhs, Counts *counts, int *prow) {
-  int tot = 0, mx = 0;
-  for (int l = 0; l < a.nlat; ++l) {
-    const int n = (a.lat[l].g.Vh + ts - 1) / ts;
-    a.lat[l].tile0 = tot;
-    a.lat[l].ntiles = n;
-    tot += n;
-    mx = n > mx ? n : mx;
-    for (int r = 0; r < nrhs && l * nrhs + r < MAXSYS; ++r) counts->n[l * nrhs + r] = n;
-  }
-  a.ntiles = tot;
-  a.prow = mx;
-  *prow = mx;
-  const Geom &g = a.lat[0].g;
-  const int lex_per_tile = 2 * ts, rowl = g.Y * g.Z;
-  if (a.nlat == 1 && a.tblock > 0 && rowl % lex_per_tile == 0 && g.T % a.tblock == 0) {
-    a.tiles_per_tx = rowl / lex_per_tile;
-  } else {
-    a.tblock = 0;
-    a.tiles_per_tx = 0;
-  }
-}
-
 // The compact forms hold the fundamental rows besides the rebuilt entries:
 // one wave per SIMD fewer for the paired form and for several rhs, so that
 // they compile without spills.
@@ -668,6 +586,7 @@ static hipError_t launch_d(const HopArgs &a, int prec, int dagger, int nrhs, int
 
 hipError_t launch_hop(const HopArgs &a, int N, int rep, int d, int real, int prec, int dagger, int nrhs, int variant,
                       int nr, hipStream_t st, Counts *counts, int *prow) {
+  if (variant == HOP_MULTI) return launch_hop_mr(a, d, real, prec, dagger, nrhs, nr, st, counts, prow);
   if (variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR) {
     const int pair = variant == HOP_COMPACT_PAIR;
     if (rep == 2 && N == 2) return compact_d<3, 2>(a, prec, dagger, nrhs, pair, nr, st, counts, prow);
@@ -695,6 +614,7 @@ hipError_t launch_hop(const HopArgs &a, int N, int rep, int d, int real, int pre
 }
 
 bool hop_nr_supported(int d, int prec, int variant, int nr) {
+  if (variant == HOP_MULTI) return nr == 1 || nr == 2 || nr == 3 || nr == 4 || nr == 6 || nr == 12;
   // as cs_fits, cs6_ok and launch_compact
   const int cb = prec == 0 ? 16 : 8;
   const int nbuf = variant == HOP_COLOUR_QUAD ? 8 : (variant == HOP_COLOUR_PAIR || variant == HOP_COMPACT_PAIR) ? 4 : 2;
@@ -708,6 +628,7 @@ bool hop_nr_supported(int d, int prec, int variant, int nr) {
 bool compact_links_ok(int N, int rep) { return (rep == 2 && N >= 2 && N <= 4) || (rep == 3 && N == 4); }
 
 bool hop_variant_ok(int N, int rep, int d, int variant) {
+  if (variant == HOP_MULTI) return hop_mr_ok(d, rep == 1);
   if (variant == HOP_SITE) return d <= 6;
   if (variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR) return compact_links_ok(N, rep);
   if (variant == HOP_COLOUR_QUAD) return d <= 4;

@@ -22,7 +22,17 @@ constexpr int MAXLAT = 8;
 // registers (SYM and 2AS only, where N^2 < d_R^2).
 // HOP_COLOUR_QUAD: the colour-split form staging two directions (four hops)
 // per barrier phase (one rhs per block, d_R <= 4).
-enum { HOP_SITE = 0, HOP_COLOUR = 1, HOP_COLOUR_PAIR = 2, HOP_COMPACT = 3, HOP_COMPACT_PAIR = 4, HOP_COLOUR_QUAD = 5 };
+// HOP_MULTI: several right-hand sides per block, one wavefront each, with the
+// tile's link entries staged once per block in LDS (hop_mr.hip).
+enum {
+  HOP_SITE = 0,
+  HOP_COLOUR = 1,
+  HOP_COLOUR_PAIR = 2,
+  HOP_COMPACT = 3,
+  HOP_COMPACT_PAIR = 4,
+  HOP_COLOUR_QUAD = 5,
+  HOP_MULTI = 6
+};
 
 // One lattice of a launch.
 struct LatDesc {
@@ -71,6 +81,12 @@ hipError_t launch_hop(const HopArgs &a, int N, int rep, int d, int real, int pre
 // within the LDS budget.
 bool hop_nr_supported(int d, int prec, int variant, int nr);
 bool hop_variant_ok(int N, int rep, int d, int variant);
+// hop_mr.hip: the HOP_MULTI form (nr = right-hand sides per block, one of
+// 1, 2, 3, 4, 6, 12, dividing nrhs); built for complex d_R = 3, 6 and real
+// d_R = 3.
+bool hop_mr_ok(int d, int real);
+hipError_t launch_hop_mr(const HopArgs &a, int d, int real, int prec, int dagger, int nrhs, int nr, hipStream_t st,
+                         Counts *counts, int *prow);
 // Whether the compact forms exist for (N, rep): SYM for N = 2, 3, 4 and 2AS
 // for N = 4 (where they read fewer bytes than the represented links).
 bool compact_links_ok(int N, int rep);

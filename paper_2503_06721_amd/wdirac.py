@@ -29,8 +29,8 @@ FIELD_HALF_SPINOR, FIELD_LINKS, FIELD_CLOVER = 0, 1, 2
  OP_CLOVER_FORCE) = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9
 MAX_SHIFTS = 32
 (OPT_HOP_VARIANT_F64, OPT_HOP_VARIANT_F32, OPT_XCD_REMAP, OPT_CG_CHECK_EVERY, OPT_MIXED_DELTA, OPT_HOP_NR_F64,
- OPT_HOP_NR_F32, OPT_TILE_TBLOCK, OPT_CG_GRAPH) = 0, 1, 2, 3, 4, 5, 6, 7, 8
-HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR, HOP_COMPACT, HOP_COMPACT_PAIR, HOP_COLOUR_QUAD = 0, 1, 2, 3, 4, 5
+ OPT_HOP_NR_F32, OPT_TILE_TBLOCK, OPT_CG_GRAPH, OPT_TUNE_COMPACT) = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9
+HOP_SITE, HOP_COLOUR, HOP_COLOUR_PAIR, HOP_COMPACT, HOP_COMPACT_PAIR, HOP_COLOUR_QUAD, HOP_MULTI = 0, 1, 2, 3, 4, 5, 6
 REP_CODES = {'FUND': FUND, 'ADJ': ADJ, 'SYM': SYM, '2AS': ASYM}
 STATUS_NAMES = {OK: 'OK', EINVAL: 'EINVAL', EUNSUPPORTED: 'EUNSUPPORTED', EHIP: 'EHIP',
                 ENOCONV: 'ENOCONV', EBREAKDOWN: 'EBREAKDOWN'}
@@ -42,7 +42,8 @@ class Geom(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [('variant', ctypes.c_int32), ('nr', ctypes.c_int32), ('xcd_remap', ctypes.c_int32),
-                ('tblock', ctypes.c_int32), ('candidates', ctypes.c_int32), ('us', ctypes.c_double)]
+                ('tblock', ctypes.c_int32), ('candidates', ctypes.c_int32), ('us', ctypes.c_double),
+                ('spread', ctypes.c_double), ('runner_up_us', ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -116,7 +116,12 @@ def test_site_variant_unavailable_for_large_rep(W):
     assert rc == W.OK
     assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_SITE) == W.EUNSUPPORTED
     assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_COLOUR_QUAD) == W.EUNSUPPORTED
-    assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, 6) == W.EINVAL
+    # the multi-rhs staged-link form is built for d_R = 3 and 6 only
+    assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_MULTI) == W.EUNSUPPORTED
+    assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, 7) == W.EINVAL
+    assert W._lib.wdirac_set_option(h, W.OPT_HOP_NR_F64, 13) == W.EINVAL
+    assert W._lib.wdirac_set_option(h, W.OPT_TUNE_COMPACT, 2) == W.EINVAL
+    assert W._lib.wdirac_set_option(h, W.OPT_TUNE_COMPACT, 0) == W.OK
     W._lib.wdirac_destroy(h)
 
 

@@ -98,6 +98,8 @@ def test_dslash_full_size_sampled(W, name, prec, nrhs):
     # the compact forms explicitly (two-index representations), then the
     # shape the autotuner picks -- the one the benchmark times
     shapes = [W.HOP_COMPACT, W.HOP_COMPACT_PAIR] if lat.compact and nrhs <= 2 else []
+    if nrhs >= 4 and not lat.real and lat.d in (3, 6):
+        shapes.append(W.HOP_MULTI)     # links staged once per block, 4 rhs per block
     for shape in shapes + ['tuned']:
         if shape == 'tuned':
             log(f'  autotuned: {lat.autotune(UR, prec, nrhs)}')

@@ -120,6 +120,63 @@ def test_dslash_rhs_groups(W, N, rep):
                         assert rel(got, exp[(p, dagger)]) < TOL[prec], (nrhs, prec, variant, nr, p)
 
 
+MULTI_PAIRS = [(3, 'FUND'), (3, 'SYM'), (4, '2AS'), (2, 'ADJ')]
+
+
+@pytest.mark.parametrize('dims', [(4, 6, 4, 6), (2, 6, 2, 6), (2, 2, 2, 2)])
+@pytest.mark.parametrize('N,rep', MULTI_PAIRS)
+def test_dslash_multi_rhs_staged_links(W, N, rep, dims):
+    """The multi-rhs form with links staged in LDS (one wavefront per rhs, two
+    lanes per site for d_R = 6): every rhs group size, both parities, the
+    dagger form, the x_add epilogue, both precisions; (2, 6, 2, 6) leaves a
+    ragged tile tail (36 sites per parity) and 2^4 has x+mu = x-mu."""
+    s = Setup(N, rep, dims, seed=280 + N)
+    for nrhs, nrs in ((12, (1, 2, 3, 4, 6, 12)), (4, (2, 4))):
+        psi = s.spinor(281 + nrhs, nrhs)
+        xadd = s.spinor(282 + nrhs, nrhs)
+        exp = {(p, dagger, use_x): hop_expect(s, psi, p, dagger, 0.6 if use_x else 0.0, -1.1 if use_x else 1.0,
+                                              xadd if use_x else None)
+               for p in (0, 1) for dagger in (0, 1) for use_x in (False, True)}
+        for prec in (0, 1):
+            s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, W.HOP_MULTI)
+            for nr in nrs:
+                s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, nr)
+                log(f'multi-rhs N={N} rep={rep} dims={dims} nrhs={nrhs} prec={prec} nr={nr}')
+                for (p, dagger, use_x), e in exp.items():
+                    inp = s.to_gpu_half(psi, 1 - p, prec)
+                    xg = s.to_gpu_half(xadd, p, prec) if use_x else None
+                    out = s.lat.new_half(nrhs, prec)
+                    s.lat.dslash_eo(out, inp, s.URg[prec], p, dagger, nrhs, 0.6 if use_x else 0.0, xg,
+                                    -1.1 if use_x else 1.0, prec)
+                    err = rel(s.from_gpu_half(out, p, nrhs, prec), e)
+                    assert err < TOL[prec], (nrhs, prec, nr, p, dagger, use_x, err)
+
+
+@pytest.mark.parametrize('mode', [0, 1])
+def test_cg_multi_rhs_staged_links(W, mode):
+    """Batched CG with the multi-rhs form (its per-tile |D-hat p|^2 partial
+    sums feed <p, A p>): every rhs reaches the oracle's true residual."""
+    m = -0.3
+    s = Setup(3, 'SYM', (4, 6, 4, 6), seed=290, links='expH')
+    for prec in (0, 1):
+        s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, W.HOP_MULTI)
+        s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, 3)
+    nrhs = 6
+    full = s.spinor(291, nrhs)
+    b = s.half(full, 0)
+    x = s.lat.new_half(nrhs)
+    rc, st = s.lat.cg_eo(x, s.to_gpu_half(full, 0), s.URg[0], m, tol=1e-10, maxit=5000, nrhs=nrhs, mode=mode,
+                         UR32=s.URg[1])
+    assert rc == W.OK, st
+    xs = s.from_gpu_half(x, 0, nrhs)
+    for r in range(nrhs):
+        res = np.sqrt(norm2(b[r] - D.normal_op(xs[r], s.UR, m, s.bc, s.dims)) / norm2(b[r]))
+        assert res <= 1.001e-10, (r, res, st[r])
+        _, it_or, _ = OCG.cg_eo(b[r], s.UR, m, s.bc, s.dims, tol=1e-10, maxit=5000)
+        if mode == 0:
+            assert abs(st[r]['iters'] - it_or) <= 2, (r, st[r]['iters'], it_or)
+
+
 @pytest.mark.parametrize('variant', [1, 2, 0])
 def test_dslash_tile_orders(W, variant):
     """t-blocked tile orders permute the work, never the result."""
