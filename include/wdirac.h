@@ -144,9 +144,11 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                      ||r|| < delta max ||r|| (default 0.01)
  *   WDIRAC_OPT_TILE_TBLOCK             0 (default) = site tiles in lexicographic
  *                                      order; b > 0 = in t-blocks of b slices
- *                                      (t-neighbours close in time; used when
- *                                      b divides T and tiles do not straddle
- *                                      (t, x) rows)
+ *                                      (t-neighbours close in time); b < 0 =
+ *                                      in chunks of -b slices with t fastest
+ *                                      (consecutive tiles are t-neighbours);
+ *                                      used when |b| divides T and tiles do
+ *                                      not straddle (t, x) rows
  *   WDIRAC_OPT_HOP_NR_F64 / _F32       right-hand sides sharing each link load
  *                                      (1..12).  Form 6: the largest of 1,
  *                                      2, 3, 4, 6, 12 not above it that

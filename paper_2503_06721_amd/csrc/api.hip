@@ -303,7 +303,7 @@ int pack(const wdirac_ctx *c, void *packed, void *canon, int parity, int nrhs, i
 // FP64, and the log-det partial sums.
 struct CloverForceWs {
   void *z_o, *y_e, *w_o;
-  double *F, *K, *G, *part, *dtmp;
+  double *F, *K, *G, *Us, *part, *dtmp;
   size_t bytes;
 };
 
@@ -324,6 +324,7 @@ CloverForceWs carve_clover_force(const wdirac_ctx *c, void *base) {
   w.F = static_cast<double *>(cv.take(6 * d2 * V * 16));
   w.K = static_cast<double *>(cv.take(12 * d2 * V * 16));
   w.G = static_cast<double *>(cv.take(24 * n2 * V * 16));
+  w.Us = static_cast<double *>(cv.take(4 * n2 * V * 16));
   w.part = static_cast<double *>(cv.take((size_t)nb * sizeof(double)));
   w.dtmp = static_cast<double *>(cv.take(sizeof(double)));
   w.bytes = cv.off;
@@ -436,7 +437,8 @@ size_t wdirac_workspace_bytes(const wdirac_ctx *ctx, int op, int nrhs, int prec)
     if (!wd::clover_supported(ctx->d)) return 0;
     int mx = 0;
     for (int l = 0; l < ctx->nlat; ++l) mx = std::max(mx, ctx->g[l].Vh);
-    return align256((size_t)6 * ctx->d * ctx->d * 2 * mx * 16);
+    // F, then the structure-of-arrays copy of the links
+    return align256((size_t)6 * ctx->d * ctx->d * 2 * mx * 16) + align256((size_t)4 * ctx->N * ctx->N * 2 * mx * 16);
   }
   if (op == WDIRAC_OP_CLOVER_FORCE) {
     if (!wd::clover_supported(ctx->d)) return 0;
@@ -494,7 +496,7 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
       ctx->cg_graph = (int)value;
       return WDIRAC_OK;
     case WDIRAC_OPT_TILE_TBLOCK:
-      if (!(value >= 0 && value <= 64)) return fail(WDIRAC_EINVAL, "t-block must be in [0, 64]");
+      if (!(value >= -64 && value <= 64)) return fail(WDIRAC_EINVAL, "t-block must be in [-64, 64]");
       ctx->tblock = (int)value;
       return WDIRAC_OK;
     case WDIRAC_OPT_TUNE_COMPACT:
@@ -528,9 +530,12 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
     int variant, nr, remap, tblock;
   };
   std::vector<Cand> cands;
-  const int tbs[] = {0, 2, 4, 8};
+  // t-fastest chunks (negative t-blocks) only where a work item holds
+  // several right-hand sides
+  const int tbs[] = {0, 2, 4, 8, -4, -8};
   for (int tb : tbs) {
-    if (tb && (ctx->nlat > 1 || ctx->g[0].T % tb)) continue;
+    if (tb < 0 && nrhs < 4) continue;
+    if (tb && (ctx->nlat > 1 || ctx->g[0].T % (tb < 0 ? -tb : tb))) continue;
     for (int remap = 0; remap < 2; ++remap) {
       for (int v = wd::HOP_COLOUR; v <= wd::HOP_MULTI; ++v) {
         if (!wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, v)) continue;
@@ -1068,8 +1073,13 @@ int wdirac_clover_field(const wdirac_ctx *ctx, void *clov, const void *U, double
   for (int l = 0; l < ctx->nlat; ++l) {
     const char *Ul = static_cast<const char *>(U) + (size_t)ctx->vpre[l] * 4 * ctx->N * ctx->N * 16;
     char *cl = static_cast<char *>(clov) + (size_t)4 * ctx->d * (2 * ctx->d + 1) * ctx->spre[l] * 2 * el;
-    WD_HIP(wd::launch_clover_field(cl, Ul, static_cast<double *>(workspace), ctx->g[l], ctx->N, ctx->rep, ctx->d, m0,
-                                   csw, exponential, prec, S(stream)));
+    int mx = 0;
+    for (int k = 0; k < ctx->nlat; ++k) mx = std::max(mx, ctx->g[k].Vh);
+    double *Fw = static_cast<double *>(workspace);
+    double *Us = reinterpret_cast<double *>(static_cast<char *>(workspace) +
+                                            align256((size_t)6 * ctx->d * ctx->d * 2 * mx * 16));
+    WD_HIP(wd::launch_clover_field(cl, Ul, Fw, Us, ctx->g[l], ctx->N, ctx->rep, ctx->d, m0, csw, exponential, prec,
+                                   S(stream)));
   }
   return WDIRAC_OK;
 }
@@ -1446,7 +1456,7 @@ int wdirac_force_eo_clover(const wdirac_ctx *ctx, void *P, const void *x_e, cons
                                   static_cast<const char *>(UR64) + (size_t)8 * ctx->d * ctx->d * ctx->spre[l] * el,
                                   gradient ? Ul : nullptr, ctx->g[l], ctx->N, ctx->rep, scale, accumulate, st));
     WD_HIP(wd::launch_clover_force(static_cast<char *>(P) + po, at(x_e), at(w.z_o), at(w.y_e), at(w.w_o), Ul,
-                                   static_cast<const char *>(clov64) + clover_offset(ctx, l), w.F, w.K, w.G,
+                                   static_cast<const char *>(clov64) + clover_offset(ctx, l), w.F, w.K, w.G, w.Us,
                                    ctx->g[l], ctx->N, ctx->rep, m0, csw, exponential, 0.0, csw / 8.0 * scale,
                                    gradient, 1, st));
   }
@@ -1464,7 +1474,7 @@ int wdirac_force_clover_logdet(const wdirac_ctx *ctx, void *P, const void *U, co
     const size_t po = links_offset(ctx, l);
     WD_HIP(wd::launch_clover_force(static_cast<char *>(P) + po, nullptr, nullptr, nullptr, nullptr,
                                    static_cast<const char *>(U) + po,
-                                   static_cast<const char *>(clov64) + clover_offset(ctx, l), w.F, w.K, w.G,
+                                   static_cast<const char *>(clov64) + clover_offset(ctx, l), w.F, w.K, w.G, w.Us,
                                    ctx->g[l], ctx->N, ctx->rep, m0, csw, exponential, 1.0, csw / 8.0 * scale,
                                    gradient, accumulate, st));
   }

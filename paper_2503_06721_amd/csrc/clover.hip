@@ -50,17 +50,43 @@ __device__ __forceinline__ size_t lex_at(const Geom &g, const int (&c)[4], int m
   return (((size_t)q[0] * g.X + q[1]) * g.Y + q[2]) * g.Z + q[3];
 }
 
+// The clover kernels read the fundamental links from a structure-of-arrays
+// copy Us[mu][N*N][V] (lexicographic site minor; k_links_soa), so that the
+// lanes of a wavefront, on consecutive sites, read consecutive addresses.
 template <int N>
-__device__ __forceinline__ void load_link(cplx<double> (&u)[N][N], const cplx<double> *U, size_t lex, int mu,
-                                          bool dag) {
-  const cplx<double> *p = U + (lex * 4 + mu) * N * N;
+__device__ __forceinline__ void load_link(cplx<double> (&u)[N][N], const cplx<double> *Us, size_t V, size_t lex,
+                                          int mu, bool dag) {
+  const cplx<double> *p = Us + (size_t)mu * N * N * V + lex;
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const cplx<double> v = p[dag ? j * N + i : i * N + j];
+      const cplx<double> v = p[(size_t)(dag ? j * N + i : i * N + j) * V];
       u[i][j] = dag ? mk(v.re, -v.im) : v;
     }
+}
+
+// Us[mu][e][lex] = U[lex][mu][e] (canonical [T][X][Y][Z][4][N][N] complex).
+// Thread per (site, direction), site fastest, so the writes are coalesced.
+template <int N>
+__global__ __launch_bounds__(256) void k_links_soa(const cplx<double> *__restrict__ U, cplx<double> *__restrict__ Us,
+                                                   size_t V) {
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 4 * V) return;
+  const int mu = (int)(gid / V);
+  const size_t lex = gid - (size_t)mu * V;
+  const cplx<double> *src = U + (lex * 4 + mu) * N * N;
+  cplx<double> *dst = Us + (size_t)mu * N * N * V + lex;
+#pragma unroll
+  for (int e = 0; e < N * N; ++e) dst[(size_t)e * V] = src[e];
+}
+
+template <int N>
+static hipError_t links_soa_launch(const void *U, double *Us, const Geom &g, hipStream_t st) {
+  const size_t V = 2 * (size_t)g.Vh;
+  hipLaunchKernelGGL((k_links_soa<N>), dim3((unsigned)((4 * V + 255) / 256)), dim3(256), 0, st,
+                     (const cplx<double> *)U, (cplx<double> *)Us, V);
+  return hipGetLastError();
 }
 
 // acc = acc * u
@@ -120,6 +146,60 @@ __global__ __launch_bounds__(256) void k_clover_F(const cplx<double> *__restrict
   c[1] = (int)(r % g.X);
   c[0] = (int)(r / g.X);
   cplx<double> *Fp = F + (size_t)p * D * D * V + lex;
+  if constexpr (REP == 0) {
+    // fundamental representation (R = 1): the four leaves summed in
+    // registers, F = (Q - Q^+)/8 written once (the other representations
+    // accumulate (R(L) - R(L)^+)/8 leaf by leaf in F below: their d_R^2
+    // accumulators do not fit in registers beside the leaf products)
+    constexpr bool FUND = true;
+    constexpr int DA = FUND ? N : D;
+    cplx<double> acc[DA][DA];
+#pragma unroll
+    for (int A = 0; A < DA; ++A)
+#pragma unroll
+      for (int B = 0; B < DA; ++B) acc[A][B] = mk(0.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cplx<double> L[N][N];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        const LeafStep st = kLeafC[k][f];
+        cplx<double> u[N][N];
+        load_link<N>(u, U, V, lex_at(g, c, mu, st.a, nu, st.b), st.dir ? nu : mu, st.dag != 0);
+        if (f == 0) {
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < N; ++j) L[i][j] = u[i][j];
+        } else {
+          mul_right<N>(L, u);
+        }
+      }
+#pragma unroll
+      for (int A = 0; A < DA; ++A)
+#pragma unroll
+        for (int B = 0; B < DA; ++B) {
+          if constexpr (FUND) {
+            acc[A][B] = acc[A][B] + L[A][B];
+          } else {
+            const cplx<double> rab = rep_entry<N, REP>(L, A, B), rba = rep_entry<N, REP>(L, B, A);
+            acc[A][B] = acc[A][B] + mk(rab.re - rba.re, rab.im + rba.im);
+          }
+        }
+      // one leaf's links live at a time
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // F = (Q - Q^+)/8 (fundamental), or the sum of (R(L) - R(L)^+)/8
+#pragma unroll
+    for (int A = 0; A < DA; ++A)
+#pragma unroll
+      for (int B = 0; B < DA; ++B) {
+        const cplx<double> v = FUND ? mk(0.125 * (acc[A][B].re - acc[B][A].re), 0.125 * (acc[A][B].im + acc[B][A].im))
+                                    : 0.125 * acc[A][B];
+        Fp[(size_t)(A * D + B) * V] = v;
+      }
+    return;
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     cplx<double> L[N][N];
@@ -127,7 +207,7 @@ __global__ __launch_bounds__(256) void k_clover_F(const cplx<double> *__restrict
     for (int f = 0; f < 4; ++f) {
       const LeafStep s = kLeafC[k][f];
       cplx<double> u[N][N];
-      load_link<N>(u, U, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
+      load_link<N>(u, U, V, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
       if (f == 0) {
 #pragma unroll
         for (int i = 0; i < N; ++i)
@@ -300,6 +380,132 @@ __global__ __launch_bounds__(64) void k_clover_finish(const cplx<double> *__rest
     }
 }
 
+// In-place Gauss-Jordan inverse with partial pivoting of the NB x NB matrix
+// a, every index a compile-time constant so that the matrix stays in
+// registers: the row interchange of a step is a set of selects over the rows
+// below the diagonal, and the interchanges are undone at the end as column
+// interchanges in reverse order (A^-1 = (P A)^-1 P).
+template <int NB>
+__device__ __forceinline__ void invert_in_place(cplx<double> (&a)[NB][NB]) {
+  int piv[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    int p = k;
+    double best = a[k][k].re * a[k][k].re + a[k][k].im * a[k][k].im;
+#pragma unroll
+    for (int r = k + 1; r < NB; ++r) {
+      const double m2 = a[r][k].re * a[r][k].re + a[r][k].im * a[r][k].im;
+      p = m2 > best ? r : p;
+      best = m2 > best ? m2 : best;
+    }
+    piv[k] = p;
+#pragma unroll
+    for (int r = k + 1; r < NB; ++r) {
+      const bool sw = p == r;
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const cplx<double> tk = a[k][j], tr = a[r][j];
+        a[k][j] = sw ? tr : tk;
+        a[r][j] = sw ? tk : tr;
+      }
+    }
+    const cplx<double> d = a[k][k];
+    const double dn = 1.0 / (d.re * d.re + d.im * d.im);
+    const cplx<double> di = mk(d.re * dn, -d.im * dn);
+    a[k][k] = mk(1.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) a[k][j] = cmul(a[k][j], di);
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      if (r == k) continue;
+      const cplx<double> f = a[r][k];
+      a[r][k] = mk(0.0, 0.0);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) a[r][j] = a[r][j] - cmul(f, a[k][j]);
+    }
+  }
+#pragma unroll
+  for (int k = NB - 1; k >= 0; --k) {
+#pragma unroll
+    for (int r = k + 1; r < NB; ++r) {
+      const bool sw = piv[k] == r;
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const cplx<double> tk = a[i][k], tr = a[i][r];
+        a[i][k] = sw ? tr : tk;
+        a[i][r] = sw ? tk : tr;
+      }
+    }
+  }
+}
+
+// Regular clover (no exponential), d_R <= 4: as k_clover_finish with the
+// block in registers throughout.  Thread per (site, chirality block), the
+// block index fastest, so that the two threads of a site read the same F
+// entries together (F comes from HBM once).
+template <int D, typename T>
+__global__ __launch_bounds__(64) void k_clover_finish_reg(const cplx<double> *__restrict__ F, void *__restrict__ clov,
+                                                          Geom g, SigmaBlocks S, double m0, double csw) {
+  constexpr int NB = 2 * D;
+  const size_t V = 2 * (size_t)g.Vh;
+  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= 2 * V) return;
+  const int c = (int)(gid & 1);
+  const size_t lex = gid >> 1;
+  size_t r = lex;
+  const int z = (int)(r % g.Z); r /= g.Z;
+  const int y = (int)(r % g.Y); r /= g.Y;
+  const int x = (int)(r % g.X);
+  const int t = (int)(r / g.X);
+  const int par = (t + x + y + z) & 1;
+  const size_t cb = lex >> 1;
+  cplx<double> M[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) M[i][j] = mk(0.0, 0.0);
+  // (i/4) c_sw sum_p S[p][c][s][t] F_p[a][b], plane by plane
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    cplx<double> fp[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = 0; b < D; ++b) fp[a][b] = F[((size_t)p * D * D + a * D + b) * V + lex];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) {
+        const cplx<double> sv = S.v[p][c][s2][tt];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int b = 0; b < D; ++b) M[s2 * D + a][tt * D + b] = cfma(sv, fp[a][b], M[s2 * D + a][tt * D + b]);
+      }
+    // one plane's F entries live at a time
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  const double m4 = 4.0 + m0;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const cplx<double> v = M[i][j];
+      M[i][j] = mk(-0.25 * csw * v.im + (i == j ? m4 : 0.0), 0.25 * csw * v.re);   // (i/4) c_sw acc (+ 4 + m)
+    }
+  if (par == 1) invert_in_place<NB>(M);
+  constexpr int NT = NB * (NB + 1) / 2;
+  cplx<T> *dst = static_cast<cplx<T> *>(clov) + ((size_t)(par * 2 + c) * NT) * g.stride + cb;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = i; j < NB; ++j) {
+      // Hermitian up to rounding: store the mean of (i,j) and conj(j,i)
+      const double re = 0.5 * (M[i][j].re + M[j][i].re), im = 0.5 * (M[i][j].im - M[j][i].im);
+      dst[(size_t)tri_index(NB, i, j) * g.stride] = mk<T>((T)re, (T)(i == j ? 0.0 : im));
+    }
+}
+
 // out = M_c in on the sites of `parity` (thread per (site, rhs, block); the
 // thread reads its block's spin components before writing them, so out may
 // alias in).
@@ -350,6 +556,17 @@ static hipError_t finish_launch(const double *F, void *clov, const Geom &g, cons
                                 double csw, int expo, int prec, hipStream_t st) {
   const size_t n = 2 * 2 * (size_t)g.Vh;
   const dim3 grid((unsigned)((n + 63) / 64));
+  if constexpr (D <= 4) {
+    if (!expo) {
+      if (prec == 0)
+        hipLaunchKernelGGL((k_clover_finish_reg<D, double>), grid, dim3(64), 0, st, (const cplx<double> *)F, clov, g,
+                           S, m0, csw);
+      else
+        hipLaunchKernelGGL((k_clover_finish_reg<D, float>), grid, dim3(64), 0, st, (const cplx<double> *)F, clov, g,
+                           S, m0, csw);
+      return hipGetLastError();
+    }
+  }
   if (prec == 0)
     hipLaunchKernelGGL((k_clover_finish<D, double>), grid, dim3(64), 0, st, (const cplx<double> *)F, clov, g, S, m0,
                        csw, expo);
@@ -404,13 +621,13 @@ static hipError_t F_launch_n(const void *U, double *F, const Geom &g, int rep, h
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_clover_field(void *clov, const void *U, double *F, const Geom &g, int N, int rep, int d, double m0,
-                               double csw, int expo, int prec, hipStream_t st) {
+hipError_t launch_clover_field(void *clov, const void *U, double *F, double *Us, const Geom &g, int N, int rep, int d,
+                               double m0, double csw, int expo, int prec, hipStream_t st) {
   hipError_t e = hipErrorInvalidValue;
   switch (N) {
-    case 2: e = F_launch_n<2>(U, F, g, rep, st); break;
-    case 3: e = F_launch_n<3>(U, F, g, rep, st); break;
-    case 4: e = F_launch_n<4>(U, F, g, rep, st); break;
+    case 2: e = links_soa_launch<2>(U, Us, g, st); if (e == hipSuccess) e = F_launch_n<2>(Us, F, g, rep, st); break;
+    case 3: e = links_soa_launch<3>(U, Us, g, st); if (e == hipSuccess) e = F_launch_n<3>(Us, F, g, rep, st); break;
+    case 4: e = links_soa_launch<4>(U, Us, g, st); if (e == hipSuccess) e = F_launch_n<4>(Us, F, g, rep, st); break;
   }
   if (e != hipSuccess) return e;
   const SigmaBlocks S = sigma_blocks();
@@ -745,7 +962,7 @@ __global__ __launch_bounds__(64) void k_clover_leafgen(const cplx<double> *__res
     for (int f = 0; f < 4; ++f) {
       const LeafStep s = kLeafC[k][f];
       cplx<double> u[N][N];
-      load_link<N>(u, U, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
+      load_link<N>(u, U, V, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
       if (f == 0) {
         for (int i = 0; i < N; ++i)
           for (int j = 0; j < N; ++j) L[i][j] = u[i][j];
@@ -766,14 +983,40 @@ __global__ __launch_bounds__(64) void k_clover_leafgen(const cplx<double> *__res
     rep_pullback<N, REP>([&](int B, int A) { return M[B][A]; }, Z);
     double tr = 0.0;
     for (int i = 0; i < N; ++i) tr += Z[i][i].re;
+    // g = (H - tr(H)/N) / 2, H = (Z + Z^+)/2, Hermitian: stored as N^2 reals
+    // (g_ii, then Re g_ij and Im g_ij for i < j), see g_load
+    double *gr = reinterpret_cast<double *>(G) + (size_t)(p * 4 + k) * N * N * V + lex;
+#pragma unroll
+    for (int i = 0; i < N; ++i) gr[(size_t)i * V] = 0.5 * (Z[i][i].re - tr / N);
+    int t = N;
+#pragma unroll
     for (int i = 0; i < N; ++i)
-      for (int j = 0; j < N; ++j) {
-        // (H - tr(H)/N) / 2, H = (Z + Z^+)/2
-        cplx<double> h = mk(0.25 * (Z[i][j].re + Z[j][i].re), 0.25 * (Z[i][j].im - Z[j][i].im));
-        if (i == j) h.re -= 0.5 * tr / N;
-        G[((size_t)(p * 4 + k) * N * N + i * N + j) * V + lex] = h;
+#pragma unroll
+      for (int j = i + 1; j < N; ++j) {
+        gr[(size_t)t * V] = 0.25 * (Z[i][j].re + Z[j][i].re);
+        gr[(size_t)(t + 1) * V] = 0.25 * (Z[i][j].im - Z[j][i].im);
+        t += 2;
       }
   }
+}
+
+// The Hermitian leaf matrix g of (plane, leaf) p4k at site xl from its N^2
+// stored reals (k_clover_leafgen).
+template <int N>
+__device__ __forceinline__ void g_load(cplx<double> (&gm)[N][N], const cplx<double> *G, int p4k, size_t xl, size_t V) {
+  const double *gr = reinterpret_cast<const double *>(G) + (size_t)p4k * N * N * V + xl;
+#pragma unroll
+  for (int i = 0; i < N; ++i) gm[i][i] = mk(gr[(size_t)i * V], 0.0);
+  int t = N;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i + 1; j < N; ++j) {
+      const double re = gr[(size_t)t * V], im = gr[(size_t)(t + 1) * V];
+      gm[i][j] = mk(re, im);
+      gm[j][i] = mk(re, -im);
+      t += 2;
+    }
 }
 
 // Thread per link (y, rho): P = coef sum over the planes (rho, nu) and the
@@ -786,8 +1029,11 @@ __global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__res
   const size_t V = 2 * (size_t)g.Vh;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= 4 * V) return;
-  const size_t lex = gid >> 2;
-  const int rho = (int)(gid & 3);
+  // direction slowest: the lanes of a wavefront hold one direction on
+  // consecutive sites (coalesced structure-of-arrays link reads, the same
+  // planes in every lane)
+  const int rho = (int)(gid / V);
+  const size_t lex = gid - (size_t)rho * V;
   size_t r = lex;
   int cy[4];
   cy[3] = (int)(r % g.Z); r /= g.Z;
@@ -817,16 +1063,17 @@ __global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__res
         for (int j = 0; j < nsteps; ++j) {
           const LeafStep sj = kLeafC[k][j];
           cplx<double> u[N][N];
-          load_link<N>(u, U, lex_at(g, cy, lo, sj.a - st.a, hi, sj.b - st.b), sj.dir ? hi : lo, sj.dag != 0);
+          load_link<N>(u, U, V, lex_at(g, cy, lo, sj.a - st.a, hi, sj.b - st.b), sj.dir ? hi : lo, sj.dag != 0);
           mul_right<N>(B, u);
         }
         const size_t xl = lex_at(g, cy, lo, -st.a, hi, -st.b);
-        const cplx<double> *gp = Gl + (size_t)(p * 4 + k) * N * N * V + xl;
+        cplx<double> gm[N][N];
+        g_load<N>(gm, Gl, p * 4 + k, xl, V);
         cplx<double> T1[N][N];
         for (int i = 0; i < N; ++i)
           for (int j = 0; j < N; ++j) {
             cplx<double> sum = mk(0.0, 0.0);
-            for (int q = 0; q < N; ++q) sum = cfma(gp[(size_t)(i * N + q) * V], B[q][j], sum);
+            for (int q = 0; q < N; ++q) sum = cfma(gm[i][q], B[q][j], sum);
             T1[i][j] = sum;
           }
         const double sg = st.dag ? -1.0 : 1.0;
@@ -842,12 +1089,12 @@ __global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__res
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) Fo[i][j] = coef * acc[i][j];
   if (gradient) {
-    const cplx<double> *u = U + (lex * 4 + rho) * N * N;
+    const cplx<double> *u = U + (size_t)rho * N * N * V + lex;
     cplx<double> Gm[N][N];
     for (int i = 0; i < N; ++i)
       for (int j = 0; j < N; ++j) {
         cplx<double> s = mk(0.0, 0.0);
-        for (int q = 0; q < N; ++q) s = cfma(Fo[i][q], u[q * N + j], s);
+        for (int q = 0; q < N; ++q) s = cfma(Fo[i][q], u[(size_t)(q * N + j) * V], s);
         Gm[i][j] = mk(-2.0 * s.im, 2.0 * s.re);
       }
     for (int i = 0; i < N; ++i)
@@ -922,12 +1169,18 @@ constexpr bool clover_rep_ok(int N, int REP) {
 
 template <int N, int REP>
 static hipError_t clover_force_nr(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo,
-                                  const void *U, const void *clov, double *F, double *K, double *Gl, const Geom &g,
+                                  const void *U0, const void *clov, double *F, double *K, double *Gl, double *Us,
+                                  const Geom &g,
                                   double m0, double csw, int expo, double cdet, double coef, int gradient,
                                   int accumulate, hipStream_t st) {
   if constexpr (clover_rep_ok(N, REP)) {
     constexpr int D = rep_dim(N, REP);
     const size_t V = 2 * (size_t)g.Vh;
+    {
+      hipError_t e = links_soa_launch<N>(U0, Us, g, st);
+      if (e != hipSuccess) return e;
+    }
+    const double *U = Us;
     if (expo) {
       hipError_t e = F_launch<N, REP>(U, F, g, st);
       if (e != hipSuccess) return e;
@@ -956,26 +1209,27 @@ static hipError_t clover_force_nr(void *P, const void *Xe, const void *Xo, const
 
 template <int N>
 static hipError_t clover_force_n(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo,
-                                 const void *U, const void *clov, double *F, double *K, double *Gl, const Geom &g,
+                                 const void *U, const void *clov, double *F, double *K, double *Gl, double *Us,
+                                 const Geom &g,
                                  int rep, double m0, double csw, int expo, double cdet, double coef, int gradient,
                                  int accumulate, hipStream_t st) {
   switch (rep) {
-    case 0: return clover_force_nr<N, 0>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
-    case 1: return clover_force_nr<N, 1>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
-    case 2: return clover_force_nr<N, 2>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
-    case 3: return clover_force_nr<N, 3>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 0: return clover_force_nr<N, 0>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, Us, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 1: return clover_force_nr<N, 1>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, Us, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 2: return clover_force_nr<N, 2>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, Us, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 3: return clover_force_nr<N, 3>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, Us, g, m0, csw, expo, cdet, coef, gradient, accumulate, st);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_clover_force(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo, const void *U,
-                               const void *clov, double *F, double *K, double *Gl, const Geom &g, int N, int rep,
+                               const void *clov, double *F, double *K, double *Gl, double *Us, const Geom &g, int N, int rep,
                                double m0, double csw, int expo, double cdet, double coef, int gradient, int accumulate,
                                hipStream_t st) {
   switch (N) {
-    case 2: return clover_force_n<2>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, rep, m0, csw, expo, cdet, coef, gradient, accumulate, st);
-    case 3: return clover_force_n<3>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, rep, m0, csw, expo, cdet, coef, gradient, accumulate, st);
-    case 4: return clover_force_n<4>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, g, rep, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 2: return clover_force_n<2>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, Us, g, rep, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 3: return clover_force_n<3>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, Us, g, rep, m0, csw, expo, cdet, coef, gradient, accumulate, st);
+    case 4: return clover_force_n<4>(P, Xe, Xo, Ye, Yo, U, clov, F, K, Gl, Us, g, rep, m0, csw, expo, cdet, coef, gradient, accumulate, st);
   }
   return hipErrorInvalidValue;
 }

@@ -68,10 +68,10 @@ __device__ void force_link(double *__restrict__ P, const cplx<double> *Xe, const
   for (int j = 0; j < 4; ++j)
 #pragma unroll
     for (int a = 0; a < D; ++a) v[j][a] = mk(0.0, 0.0);
-  const size_t lbase = (size_t)(par * 4 + MU) * D * D * g.stride + cb;
+  const size_t lbase = (size_t)(par * 4 + MU) * D * D * g.stride + link_site(D * D, g.stride, cb);
   for (int a = 0; a < D; ++a)
     for (int b = 0; b < D; ++b) {
-      const size_t o = lbase + (size_t)(a * D + b) * g.stride;
+      const size_t o = lbase + link_row(a * D + b, g.stride);
       if constexpr (REAL) {
         const double u = static_cast<const double *>(UR)[o];
 #pragma unroll

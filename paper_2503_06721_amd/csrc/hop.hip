@@ -46,7 +46,7 @@ __device__ __forceinline__ void sp_dir(cplx<T> (&acc)[4][D], const cplx<T> *__re
 #pragma unroll
     for (int b = 0; b < D; ++b) {
       // forward: U_ab;  backward: (U^+)_ab = conj(U_ba)
-      const auto u = ld_stream<NTL>(lk + (size_t)(BWD ? b * D + a : a * D + b) * stride + lsite);
+      const auto u = ld_stream<NTL>(lk + link_row(BWD ? b * D + a : a * D + b, stride) + link_site(D * D, stride, lsite));
       chi[0] = link_mac(u, h[0][b], chi[0], BWD);
       chi[1] = link_mac(u, h[1][b], chi[1], BWD);
     }
@@ -227,21 +227,21 @@ __device__ __forceinline__ void cs_stage(typename LinkT<T, REAL>::type (&u)[D], 
   if constexpr (FLY != 0) {
     constexpr bool SYM = FLY == 2;
     constexpr int N = two_index_n<D, SYM>();
-    const cplx<T> *fk = flinks + (size_t)(lpar * 4 + MU) * N * N * stride + lsite;
+    const cplx<T> *fk = flinks + (size_t)(lpar * 4 + MU) * N * N * stride + link_site(N * N, stride, lsite);
     int a1, a2;
     pair_of<N, SYM>(row, a1, a2);
     cplx<T> xr[N], yr[N];
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-      xr[c] = ld_stream<NTL>(fk + (size_t)(BWD ? c * N + a1 : a1 * N + c) * stride);
-      yr[c] = ld_stream<NTL>(fk + (size_t)(BWD ? c * N + a2 : a2 * N + c) * stride);
+      xr[c] = ld_stream<NTL>(fk + link_row(BWD ? c * N + a1 : a1 * N + c, stride));
+      yr[c] = ld_stream<NTL>(fk + link_row(BWD ? c * N + a2 : a2 * N + c, stride));
     }
     rebuild_row<D, N, SYM, T>(u, xr, yr, (SYM && a1 == a2) ? (T)0.70710678118654752440 : (T)1);
   } else {
     const L *lk = links + (size_t)(lpar * 4 + MU) * D * D * stride;
 #pragma unroll
     for (int b = 0; b < D; ++b)
-      u[b] = ld_stream<NTL>(lk + (size_t)(BWD ? b * D + row : row * D + b) * stride + lsite);
+      u[b] = ld_stream<NTL>(lk + link_row(BWD ? b * D + row : row * D + b, stride) + link_site(D * D, stride, lsite));
   }
 #pragma unroll
   for (int k = 0; k < NR; ++k) {

@@ -37,24 +37,28 @@ struct MrShape {
   static constexpr int TS = 64 / LPS;                           // sites per tile
 };
 
-// Value of the partner lane (lane ^ 32) for the two-lane split.
-__device__ __forceinline__ float swap_half(float v) {
+// Two-lane split: lanes 0..31 hold a quantity for colour k, lanes 32..63 the
+// same quantity for colour k + RPL of the same 32 sites.  One
+// v_permlane32_swap of v with itself swaps the upper half of its first
+// operand with the lower half of its second, so that its first result holds
+// colour k in every lane and its second colour k + RPL: no select by lane.
+__device__ __forceinline__ void split_halves(float v, float &lo, float &hi) {
   const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
-  return __int_as_float((threadIdx.x & 32) ? r[0] : r[1]);
+  lo = __int_as_float(r[0]);
+  hi = __int_as_float(r[1]);
 }
-__device__ __forceinline__ double swap_half(double v) {
+__device__ __forceinline__ void split_halves(double v, double &lo, double &hi) {
   const long long b = __double_as_longlong(v);
-  const int lo = (int)(b & 0xffffffffLL), hi = (int)(b >> 32);
-  const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-  const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  const bool upper = threadIdx.x & 32;
-  const unsigned nlo = (unsigned)(upper ? rl[0] : rl[1]);
-  const unsigned nhi = (unsigned)(upper ? rh[0] : rh[1]);
-  return __longlong_as_double((long long)(((unsigned long long)nhi << 32) | nlo));
+  const int b0 = (int)(b & 0xffffffffLL), b1 = (int)(b >> 32);
+  const auto r0 = __builtin_amdgcn_permlane32_swap(b0, b0, false, false);
+  const auto r1 = __builtin_amdgcn_permlane32_swap(b1, b1, false, false);
+  lo = __longlong_as_double((long long)(((unsigned long long)(unsigned)r1[0] << 32) | (unsigned)r0[0]));
+  hi = __longlong_as_double((long long)(((unsigned long long)(unsigned)r1[1] << 32) | (unsigned)r0[1]));
 }
 template <typename T>
-__device__ __forceinline__ cplx<T> swap_half(cplx<T> v) {
-  return mk<T>(swap_half(v.re), swap_half(v.im));
+__device__ __forceinline__ void split_halves(cplx<T> v, cplx<T> &lo, cplx<T> &hi) {
+  split_halves(v.re, lo.re, hi.re);
+  split_halves(v.im, lo.im, hi.im);
 }
 
 // Element off of the array at base: base is the same for every lane of the
@@ -92,13 +96,13 @@ __device__ __forceinline__ void mr_load_links(typename LinkT<T, REAL>::type (&lr
   using M = MrTile<D, K>;
   const int lpar = BWD ? 1 - parity : parity;
   // backward hop: U(x - mu, mu) sits at the neighbour's index
-  const uint32_t off = (uint32_t)(rg * g.stride + (BWD ? nbb[MU] : is));
+  const uint32_t off = (uint32_t)(link_row(rg, g.stride) + link_site(D * D, g.stride, BWD ? nbb[MU] : is));
   const auto *lk = links + (size_t)(lpar * 4 + MU) * D * D * g.stride;
 #pragma unroll
   for (int p = 0; p < M::PER; ++p) {
     const int eu = M::LPS * (w + p * K);
     const int ec = eu < M::NE - M::LPS ? eu : M::NE - M::LPS;
-    lr[p] = ld_stream<NTL>(at(lk + (size_t)ec * g.stride, off));
+    lr[p] = ld_stream<NTL>(at(lk + link_row(ec, g.stride), off));
   }
 }
 
@@ -108,6 +112,54 @@ __device__ __forceinline__ void mr_store_links(L (*buf)[(MrShape<D>::TS)], const
   using M = MrTile<D, K>;
 #pragma unroll
   for (int p = 0; p < M::PER; ++p) buf[M::LPS * (w + p * K) + rg][sl] = lr[p];
+}
+
+// Direct global -> LDS loads of the same entries (16-byte link entries: FP64
+// complex).  A wavefront's lanes fill LPS consecutive rows of TS entries,
+// i.e. 64 consecutive LDS elements starting at row LPS (w + p K), so each
+// load is one global_load_lds_dwordx4 with a wave-uniform LDS base; nothing
+// passes through registers.  Completion is awaited with vmcnt(0) before the
+// barrier that publishes the tile.
+template <int D, typename L, int K, int MU, bool BWD>
+__device__ __forceinline__ void mr_dma_links(L (*buf)[(MrShape<D>::TS)], const L *links, const Geom &g, int parity,
+                                             int w, int rg, int is, const int (&nbb)[4]) {
+  static_assert(sizeof(L) == 16, "direct LDS loads of 16-byte entries");
+  using M = MrTile<D, K>;
+  const int lpar = BWD ? 1 - parity : parity;
+  const uint32_t off = (uint32_t)(link_row(rg, g.stride) + link_site(D * D, g.stride, BWD ? nbb[MU] : is));
+  const L *lk = links + (size_t)(lpar * 4 + MU) * D * D * g.stride;
+#pragma unroll
+  for (int p = 0; p < M::PER; ++p) {
+    const int eu = M::LPS * (w + p * K);
+    const int ec = eu < M::NE - M::LPS ? eu : M::NE - M::LPS;
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(at(lk + link_row(ec, g.stride), off)),
+                                     (__attribute__((address_space(3))) void *)(&buf[eu][0]), 16, 0, 0);
+  }
+}
+
+// Raw neighbour components of this lane's colour rows: p[s][k] = in(nb) of
+// spin s, colour c0 + k (loaded one hop ahead of their use).
+template <int D, typename T>
+__device__ __forceinline__ void mr_load_spinor(cplx<T> (&p)[4][MrShape<D>::RPL], const cplx<T> *in, int stride,
+                                               uint32_t roff, int nb) {
+  constexpr int RPL = MrShape<D>::RPL;
+  const uint32_t off = roff + (uint32_t)nb;
+#pragma unroll
+  for (int k = 0; k < RPL; ++k)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) p[s][k] = *at(in + (size_t)(s * D + k) * stride, off);
+}
+
+// Spin projection of loaded components into slots 0 .. RPL - 1 of h0/h1.
+template <int D, typename T, int MU, int SIG>
+__device__ __forceinline__ void mr_project_loaded(cplx<T> (&h0)[D], cplx<T> (&h1)[D],
+                                                  const cplx<T> (&p)[4][MrShape<D>::RPL]) {
+  constexpr int RPL = MrShape<D>::RPL;
+#pragma unroll
+  for (int k = 0; k < RPL; ++k) {
+    h0[k] = p[0][k] + ipow<PROJ_PH(MU, SIG, 0)>(p[2 + ECOL(MU, 0)][k]);
+    h1[k] = p[1][k] + ipow<PROJ_PH(MU, SIG, 1)>(p[2 + ECOL(MU, 1)][k]);
+  }
 }
 
 // Spin-project this lane's colour rows (row group rg) of the neighbour spinor
@@ -129,24 +181,16 @@ __device__ __forceinline__ void mr_project(cplx<T> (&h0)[D], cplx<T> (&h1)[D], c
 }
 
 // Complete h0/h1 (own colours in slots 0 .. RPL - 1) to the full projected
-// two-spinor in colour order: with two lanes per site the lower lane holds
-// colours 0 .. RPL - 1 and receives the rest from its partner; the upper
-// lane the opposite.
+// two-spinor in colour order (with two lanes per site; see split_halves).
 template <int D, typename T>
-__device__ __forceinline__ void mr_gather(cplx<T> (&h0)[D], cplx<T> (&h1)[D], int rg) {
+__device__ __forceinline__ void mr_gather(cplx<T> (&h0)[D], cplx<T> (&h1)[D]) {
   constexpr int RPL = MrShape<D>::RPL;
   if constexpr (MrShape<D>::LPS == 2) {
 #pragma unroll
-    for (int k = 0; k < RPL; ++k) {
-      const cplx<T> m0 = h0[k], m1 = h1[k];
-      const cplx<T> o0 = swap_half(m0), o1 = swap_half(m1);
-      h0[k] = rg ? o0 : m0;
-      h1[k] = rg ? o1 : m1;
-      h0[RPL + k] = rg ? m0 : o0;
-      h1[RPL + k] = rg ? m1 : o1;
+    for (int k = RPL - 1; k >= 0; --k) {
+      split_halves(h0[k], h0[k], h0[RPL + k]);
+      split_halves(h1[k], h1[k], h1[RPL + k]);
     }
-  } else {
-    (void)rg;
   }
 }
 
@@ -177,44 +221,59 @@ __device__ __forceinline__ void mr_compute(cplx<T> (&acc)[4][MrShape<D>::RPL], c
   }
 }
 
-// Hop H = 2 mu + (backward) of the pipeline: project the neighbour spinor,
-// load the next hop's link entries, barrier, gather the full projected
-// two-spinor, compute from LDS buffer H & 1, store the next entries in the
-// other buffer (free: every wave has passed this barrier, so every wave has
-// finished hop H - 1, the last reader of that buffer).
+// Hop H = 2 mu + (backward) of the pipeline.  On entry the raw neighbour
+// components of hop H are in registers (p) and its link tile is on its way
+// to LDS buffer H & 1 (direct loads, or registers lr for other entry sizes).
+//   wait for the tile, barrier (every wave has finished hop H - 1, the last
+//   reader of buffer (H + 1) & 1);
+//   start hop H + 1: its link tile towards buffer (H + 1) & 1, its raw
+//   neighbour components into registers;
+//   project and gather hop H, compute it from buffer H & 1;
+//   (register staging) store hop H + 1's entries.
 template <int D, bool REAL, typename T, int K, bool DAG, bool NTL, int H>
 __device__ __forceinline__ void mr_step(cplx<T> (&acc)[4][(MrShape<D>::RPL)],
                                         typename LinkT<T, REAL>::type (*lbuf)[(MrTile<D, K>::NEP)][(MrShape<D>::TS)],
                                         typename LinkT<T, REAL>::type (&lr)[(MrTile<D, K>::PER)],
+                                        cplx<T> (&p)[4][(MrShape<D>::RPL)],
                                         const typename LinkT<T, REAL>::type *links, const cplx<T> *in, const Geom &g,
                                         int parity, const int (&nbf)[4], const int (&nbb)[4], int w, int rg, int is,
                                         int sl, uint32_t roff) {
   using L = typename LinkT<T, REAL>::type;
+  constexpr bool DMA = sizeof(L) == 16;
   constexpr int RPL = MrShape<D>::RPL;
   constexpr int MU = H / 2;
   constexpr bool BWD = (H & 1) != 0;
   constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
   constexpr int SIG = BWD ? -SF : SF;
-  cplx<T> h0[D], h1[D];
-  mr_project<D, T, MU, SIG>(h0, h1, in, g.stride, roff, BWD ? nbb[MU] : nbf[MU]);
-  if constexpr (H < 7)
-    mr_load_links<D, REAL, T, K, (H + 1) / 2, ((H + 1) & 1) != 0, NTL>(lr, links, g, parity, w, rg, is, nbb);
+  constexpr int MU1 = (H + 1) / 2;
+  constexpr bool BWD1 = ((H + 1) & 1) != 0;
+  if constexpr (DMA) __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this hop's tile has landed
   __syncthreads();
-  mr_gather<D, T>(h0, h1, rg);
+  cplx<T> h0[D], h1[D];
+  mr_project_loaded<D, T, MU, SIG>(h0, h1, p);
+  if constexpr (H < 7) {
+    if constexpr (DMA)
+      mr_dma_links<D, L, K, MU1, BWD1>(lbuf[(H + 1) & 1], links, g, parity, w, rg, is, nbb);
+    else
+      mr_load_links<D, REAL, T, K, MU1, BWD1, NTL>(lr, links, g, parity, w, rg, is, nbb);
+    mr_load_spinor<D, T>(p, in, g.stride, roff, BWD1 ? nbb[MU1] : nbf[MU1]);
+  }
+  mr_gather<D, T>(h0, h1);
   mr_compute<D, REAL, T, MU, SIG, BWD>(acc, h0, h1, lbuf[H & 1], rg * RPL, sl);
-  if constexpr (H < 7) mr_store_links<D, L, K>(lbuf[(H + 1) & 1], lr, w, rg, sl);
+  if constexpr (H < 7 && !DMA) mr_store_links<D, L, K>(lbuf[(H + 1) & 1], lr, w, rg, sl);
 }
 
 template <int D, bool REAL, typename T, int K, bool DAG, bool NTL, int H = 0>
 __device__ __forceinline__ void mr_steps(cplx<T> (&acc)[4][(MrShape<D>::RPL)],
                                          typename LinkT<T, REAL>::type (*lbuf)[(MrTile<D, K>::NEP)][(MrShape<D>::TS)],
                                          typename LinkT<T, REAL>::type (&lr)[(MrTile<D, K>::PER)],
+                                         cplx<T> (&p)[4][(MrShape<D>::RPL)],
                                          const typename LinkT<T, REAL>::type *links, const cplx<T> *in,
                                          const Geom &g, int parity, const int (&nbf)[4], const int (&nbb)[4], int w,
                                          int rg, int is, int sl, uint32_t roff) {
   if constexpr (H < 8) {
-    mr_step<D, REAL, T, K, DAG, NTL, H>(acc, lbuf, lr, links, in, g, parity, nbf, nbb, w, rg, is, sl, roff);
-    mr_steps<D, REAL, T, K, DAG, NTL, H + 1>(acc, lbuf, lr, links, in, g, parity, nbf, nbb, w, rg, is, sl, roff);
+    mr_step<D, REAL, T, K, DAG, NTL, H>(acc, lbuf, lr, p, links, in, g, parity, nbf, nbb, w, rg, is, sl, roff);
+    mr_steps<D, REAL, T, K, DAG, NTL, H + 1>(acc, lbuf, lr, p, links, in, g, parity, nbf, nbb, w, rg, is, sl, roff);
   }
 }
 
@@ -259,9 +318,15 @@ __global__ __launch_bounds__(64 * K) __attribute__((amdgpu_waves_per_eu(W))) voi
 #pragma unroll
     for (int k = 0; k < RPL; ++k) acc[s][k] = mk<T>(0, 0);
   L lr[(MrTile<D, K>::PER)];
-  mr_load_links<D, REAL, T, K, 0, false, NTL>(lr, links, g, a.parity, w, rg, is, nbb);
-  mr_store_links<D, L, K>(lbuf[0], lr, w, rg, sl);
-  mr_steps<D, REAL, T, K, DAG, NTL>(acc, lbuf, lr, links, in, g, a.parity, nbf, nbb, w, rg, is, sl, roff);
+  cplx<T> p[4][RPL];
+  if constexpr (sizeof(L) == 16) {
+    mr_dma_links<D, L, K, 0, false>(lbuf[0], links, g, a.parity, w, rg, is, nbb);
+  } else {
+    mr_load_links<D, REAL, T, K, 0, false, NTL>(lr, links, g, a.parity, w, rg, is, nbb);
+    mr_store_links<D, L, K>(lbuf[0], lr, w, rg, sl);
+  }
+  mr_load_spinor<D, T>(p, in, g.stride, roff, nbf[0]);
+  mr_steps<D, REAL, T, K, DAG, NTL>(acc, lbuf, lr, p, links, in, g, a.parity, nbf, nbb, w, rg, is, sl, roff);
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
   cplx<T> *out = static_cast<cplx<T> *>(a.out) + fbase;
   const uint32_t ooff = roff + (uint32_t)i;   // i < stride: lanes past the end write the padding
@@ -300,7 +365,7 @@ __global__ __launch_bounds__(64 * K) __attribute__((amdgpu_waves_per_eu(W))) voi
 }
 
 // Waves per SIMD asked of the register allocator, per (d_R, precision).
-constexpr int mr_waves(int D, bool dbl) { return dbl ? (D <= 4 ? 4 : 3) : (D <= 4 ? 6 : 4); }
+constexpr int mr_waves(int D, bool dbl) { return dbl ? (D <= 4 ? 3 : 2) : (D <= 4 ? 6 : 4); }
 
 template <int D, bool REAL, typename T, bool DAG, int K>
 static hipError_t launch_mr_k(HopArgs a, int nrhs, hipStream_t st, Counts *counts, int *prow) {

@@ -38,19 +38,18 @@ __global__ __launch_bounds__(256) void k_rep_links(const cplx<double> *__restric
   for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int j = 0; j < N; ++j) u[i][j] = U[(size_t)gid * N * N + i * N + j];
-  const size_t base = (size_t)(par * 4 + mu) * D * D * g.stride + cb;
-  const size_t es = g.stride;
   for (int A = 0; A < D; ++A)
     for (int B = 0; B < D; ++B)
-      store_entry<T>(UR, base + (size_t)(A * D + B) * es, rep_entry<N, REP>(u, A, B), sign, REP == 1);
+      store_entry<T>(UR, link_at(par * 4 + mu, D * D, g.stride, A * D + B, cb), rep_entry<N, REP>(u, A, B), sign,
+                     REP == 1);
   if (F) {
     // compact fundamental copy: i U where the phase is -1
-    const size_t fb = (size_t)(par * 4 + mu) * N * N * g.stride + cb;
     cplx<T> *f = static_cast<cplx<T> *>(F);
     for (int i = 0; i < N; ++i)
       for (int j = 0; j < N; ++j) {
         const cplx<double> v = u[i][j];
-        f[fb + (size_t)(i * N + j) * es] = sign < 0.0 ? mk<T>((T)(-v.im), (T)v.re) : mk<T>((T)v.re, (T)v.im);
+        f[link_at(par * 4 + mu, N * N, g.stride, i * N + j, cb)] =
+            sign < 0.0 ? mk<T>((T)(-v.im), (T)v.re) : mk<T>((T)v.re, (T)v.im);
       }
   }
 }
@@ -106,7 +105,7 @@ __global__ __launch_bounds__(256) void k_unpack_links(double *__restrict__ out, 
   const int x = r % g.X;
   const int t = r / g.X;
   const int par = (t + x + y + z) & 1;
-  const size_t src = ((size_t)(par * 4 + mu) * d * d + e) * g.stride + (lex >> 1);
+  const size_t src = link_at(par * 4 + mu, d * d, g.stride, e, lex >> 1);
   if (real) {
     out[gid] = (double)static_cast<const T *>(UR)[src];
   } else {

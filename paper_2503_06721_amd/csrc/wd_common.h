@@ -146,6 +146,38 @@ __device__ __forceinline__ int nb_index(const Geom &g, int t, int x, int y, int 
   return cb_index(g, t, x, y, z);
 }
 
+// ------------------------------------------------------------ link layout
+// Packed links of one lattice: (parity, direction) blocks of E x stride
+// elements (E = d_R^2 represented entries, or N^2 for the compact copy).
+// Inside a block the sites go in tiles of kLinkTile: the E entry rows of a
+// tile (kLinkTile consecutive sites each) follow one another, so that the
+// link entries a wavefront reads for its 64 sites form one contiguous run
+// instead of E runs a whole stride apart.  (kLinkTile = 0: plain
+// structure of arrays, element (e, i) at e * stride + i.)
+constexpr int kLinkTile = 64;
+// Offset of site i's element of entry row 0 inside a block; entry e adds
+// link_row(e).
+__host__ __device__ __forceinline__ size_t link_site(int E, int stride, int i) {
+  if constexpr (kLinkTile == 0) {
+    (void)E;
+    (void)stride;
+    return (size_t)i;
+  } else {
+    return (size_t)(i / kLinkTile) * ((size_t)E * kLinkTile) + (size_t)(i % kLinkTile);
+  }
+}
+__host__ __device__ __forceinline__ size_t link_row(int e, int stride) {
+  if constexpr (kLinkTile == 0) return (size_t)e * stride;
+  else {
+    (void)stride;
+    return (size_t)e * kLinkTile;
+  }
+}
+// Element (e, i) of (parity, direction) block pmu.
+__host__ __device__ __forceinline__ size_t link_at(int pmu, int E, int stride, int e, int i) {
+  return (size_t)pmu * E * stride + link_site(E, stride, i) + link_row(e, stride);
+}
+
 // ------------------------------------------------------------- reductions
 // Sum over a 64-lane wavefront (result valid in every lane).
 __device__ __forceinline__ double wave_sum(double v) {

@@ -24,8 +24,24 @@ __device__ __forceinline__ int tile_of_block(int b, int ntiles, int remap) {
 // order (t-block of tb slices, x, t within the block, tile within the row):
 // t-neighbours are then tiles_per_tx tiles apart instead of a whole t-slice,
 // so they are still in L2 when read.  tb = 0: lexicographic order.
+// With tb < 0 the slices are taken in chunks of -tb with t fastest:
+// (chunk, x, tile within the row, t within the chunk), so consecutive work
+// items are t-neighbours and the tiles of a (t, x) row follow each other
+// -tb items apart (for work items holding many right-hand sides, whose
+// neighbourhoods would not stay in L2 across a whole row of tiles).
 __device__ __forceinline__ int tile_order(int q, const HopArgs &a) {
   if (a.tblock == 0) return q;
+  if (a.tblock < 0) {
+    const int nb = a.tiles_per_tx, tc = -a.tblock, X = a.lat[0].g.X;
+    const int per_c = X * nb * tc;
+    const int ci = q / per_c;
+    int r = q - ci * per_c;
+    const int x = r / (nb * tc);
+    r -= x * nb * tc;
+    const int yb = r / tc;
+    const int tin = r - yb * tc;
+    return ((ci * tc + tin) * X + x) * nb + yb;
+  }
   const int nb = a.tiles_per_tx, tb = a.tblock, X = a.lat[0].g.X;
   const int per_tb = X * tb * nb;
   const int tbi = q / per_tb;
@@ -83,7 +99,8 @@ inline void set_tiles(HopArgs &a, int ts, int nrhs, Counts *counts, int *prow) {
   *prow = mx;
   const Geom &g = a.lat[0].g;
   const int lex_per_tile = 2 * ts, rowl = g.Y * g.Z;
-  if (a.nlat == 1 && a.tblock > 0 && rowl % lex_per_tile == 0 && g.T % a.tblock == 0) {
+  const int tbabs = a.tblock < 0 ? -a.tblock : a.tblock;
+  if (a.nlat == 1 && tbabs > 0 && rowl % lex_per_tile == 0 && g.T % tbabs == 0) {
     a.tiles_per_tx = rowl / lex_per_tile;
   } else {
     a.tblock = 0;

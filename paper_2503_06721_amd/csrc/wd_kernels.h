@@ -200,19 +200,21 @@ hipError_t launch_ms_update_xp(void *x, void *p, const void *r, const MsScalars 
 // Clover field: [parity][chirality block][d(2d+1)][stride] complex, the upper
 // triangle (row-major, diagonal included) of the Hermitian 2d x 2d block; even
 // sites holding D_ee, odd sites D_oo^{-1}.  F: scratch of 6 d^2 complex FP64
-// per site.
+// per site; Us: scratch of 4 N^2 complex FP64 per site (a structure-of-arrays
+// copy of the links).
 bool clover_supported(int d);
-hipError_t launch_clover_field(void *clov, const void *U, double *F, const Geom &g, int N, int rep, int d, double m0,
-                               double csw, int expo, int prec, hipStream_t st);
+hipError_t launch_clover_field(void *clov, const void *U, double *F, double *Us, const Geom &g, int N, int rep, int d,
+                               double m0, double csw, int expo, int prec, hipStream_t st);
 // out = D_ee in (parity 0) or D_oo^{-1} in (parity 1); out may alias in
 hipError_t launch_clover_apply(void *out, const void *in, const void *clov, const Geom &g, int d, int parity,
                                int nrhs, int prec, hipStream_t st);
 // Clover contribution to the link force of a functional with variation
 // -2 Re sum_x tr[dM Omega], Omega = X Y^+ (Xe non-null) + cdet D_oo^{-1} on odd
 // sites; P (+)= coef * force (or its gradient form).  F: 6 d^2 V, K: 12 d^2 V,
-// Gl: 24 N^2 V complex FP64 scratch (F only for the exponential form).
+// Gl: 24 N^2 V complex FP64 scratch (F only for the exponential form), Us:
+// 4 N^2 V complex FP64 (structure-of-arrays copy of the links).
 hipError_t launch_clover_force(void *P, const void *Xe, const void *Xo, const void *Ye, const void *Yo, const void *U,
-                               const void *clov, double *F, double *K, double *Gl, const Geom &g, int N, int rep,
+                               const void *clov, double *F, double *K, double *Gl, double *Us, const Geom &g, int N, int rep,
                                double m0, double csw, int expo, double cdet, double coef, int gradient, int accumulate,
                                hipStream_t st);
 // Partial sums of log|det D_oo(x)| over the odd sites (clover_logdet_blocks of them).
