@@ -22,6 +22,7 @@ SU(2) ADJ 32x16^3.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--hops H] [--no-cpu] [--no-multi]
 """
 import argparse
+import csv
 import hashlib
 import json
 import os
@@ -35,7 +36,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = 'su3_fund_32x32x32x32'
 TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'dslash_eo_su3_fund_32x32x32x32_traffic.json')
-HOP_SOURCES = [os.path.join(ROOT, 'paper_2503_06721_amd', 'csrc', f) for f in ('hop.hip', 'wd_hop.h')]
+HOP_SOURCES = [os.path.join(ROOT, 'paper_2503_06721_amd', 'csrc', f)
+               for f in ('hop.hip', 'hop_mr.hip', 'wd_hop.h', 'wd_common.h')]
 
 
 def log(msg):
@@ -76,8 +78,9 @@ def device_copy_gbps(torch, n=1 << 28, reps=3):
 
 
 def hop_sources_sha256():
-    """SHA-256 over the sources of the single-rhs hop kernels (hop.hip, then
-    wd_hop.h): a traffic record taken on other sources no longer applies."""
+    """SHA-256 over the sources of the hop kernels and the link layout they
+    read (hop.hip, hop_mr.hip, wd_hop.h, wd_common.h, in that order): a
+    traffic record taken on other sources no longer applies."""
     h = hashlib.sha256()
     for p in HOP_SOURCES:
         with open(p, 'rb') as f:
@@ -101,6 +104,82 @@ def measured_traffic(launch_bytes, shape):
         return None
     except (OSError, KeyError, ValueError):
         return None
+
+
+def _counter_per_dispatch(path, counter):
+    """(dispatch id, kernel name, value) of one rocprofv3 counter, summed over
+    the rows of a dispatch, in dispatch order."""
+    acc = {}
+    with open(path, newline='') as f:
+        for r in csv.DictReader(f):
+            if r['Counter_Name'] == counter:
+                k = int(r['Dispatch_Id'])
+                name, v = acc.get(k, (r['Kernel_Name'], 0.0))
+                acc[k] = (name, v + float(r['Counter_Value']))
+    return [(k, n, v) for k, (n, v) in sorted(acc.items())]
+
+
+def _calibration(cal, fetch_csv, write_csv):
+    """Bytes per counted KiB of FETCH_SIZE and WRITE_SIZE for each kernel of
+    known traffic in the calibration run."""
+    fetch = _counter_per_dispatch(fetch_csv, 'FETCH_SIZE')
+    write = _counter_per_dispatch(write_csv, 'WRITE_SIZE')
+    out = {}
+    for k in cal['kernels']:
+        fv = [v for _, n, v in fetch if k['pattern'] in n]
+        wv = [v for _, n, v in write if k['pattern'] in n]
+        if not fv or not wv:
+            raise SystemExit(f'calibration kernel {k["pattern"]} not found in the counter files')
+        f_kib, w_kib = sum(fv) / len(fv), sum(wv) / len(wv)
+        out[k['name']] = {'kernel_pattern': k['pattern'], 'dispatches': len(fv),
+                          'bytes_read': k['bytes_read'], 'bytes_written': k['bytes_written'],
+                          'fetch_size_kib': round(f_kib, 1), 'write_size_kib': round(w_kib, 1),
+                          'fetch_factor': round(k['bytes_read'] / (f_kib * 1024), 4),
+                          'write_factor': round(k['bytes_written'] / (w_kib * 1024), 4)}
+    return out
+
+
+def write_traffic_record(out_path, run_json, fetch_csv, write_csv, cal_json, cal_fetch_csv, cal_write_csv):
+    """Per-launch HBM traffic of the hop for every launch shape of a
+    --traffic-shapes / --traffic-multi run, from its FETCH_SIZE and WRITE_SIZE
+    counter passes, calibrated on the kernels of known traffic of a
+    --copy-calibration run (a device copy and the non-temporal streaming
+    probe, whose loads are of the hop's kind; the probe's factors are the ones
+    applied, the copy's are shown beside them).  The record carries the
+    SHA-256 of the hop sources it was taken on."""
+    with open(run_json) as f:
+        run = json.load(f)
+    with open(cal_json) as f:
+        cal = _calibration(json.load(f), cal_fetch_csv, cal_write_csv)
+    ff, wf = cal['stream_probe']['fetch_factor'], cal['stream_probe']['write_factor']
+    pat, per = run['kernel_pattern'], run['launches_per_shape']
+    fetch = [r for r in _counter_per_dispatch(fetch_csv, 'FETCH_SIZE') if pat in r[1]]
+    write = [r for r in _counter_per_dispatch(write_csv, 'WRITE_SIZE') if pat in r[1]]
+    need = per * len(run['shapes'])
+    if len(fetch) < need or len(write) < need:
+        raise SystemExit(f'{len(fetch)} / {len(write)} hop dispatches in the counter files, {need} expected')
+    fetch, write = fetch[-need:], write[-need:]
+    algo = run['algorithmic_bytes_per_launch']
+    rows = []
+    for i, shape in enumerate(run['shapes']):
+        fr, wr = fetch[i * per:(i + 1) * per], write[i * per:(i + 1) * per]
+        f_kib = sum(v for _, _, v in fr) / per
+        w_kib = sum(v for _, _, v in wr) / per
+        hbm = f_kib * 1024 * ff + w_kib * 1024 * wf
+        rows.append({'launch_shape': shape, 'kernel': fr[0][1],
+                     'fetch_size_kib_per_launch': round(f_kib, 1), 'write_size_kib_per_launch': round(w_kib, 1),
+                     'raw_bytes_per_launch': int(round((f_kib + w_kib) * 1024)),
+                     'hbm_bytes_per_launch': int(round(hbm)),
+                     'traffic_over_algorithmic': round(hbm / algo, 4),
+                     'reads_over_compulsory_reads': round(f_kib * 1024 * ff / run['compulsory_read_bytes'], 4)})
+    rec = {'workload': run['workload'], 'hop_sources_sha256': run['hop_sources_sha256'],
+           'calibration': cal, 'factors_applied': {'fetch': ff, 'write': wf, 'from': 'stream_probe'},
+           'algorithmic_bytes_per_launch': algo, 'compulsory_read_bytes': run['compulsory_read_bytes'],
+           'per_launch_shape': rows}
+    with open(out_path, 'w') as f:
+        json.dump(rec, f, indent=1)
+        f.write('\n')
+    print(json.dumps({'written': out_path, 'shapes': len(rows)}))
 
 
 def host_info():
@@ -312,6 +391,33 @@ def dslash_roofline(W, torch, lat, UR, prec, nrhs, tuned, n=40):
                                'tuner_spread': round(ts['spread'], 4)}
         del stored
     return out
+
+
+def traffic_multi(W, torch, synth, name='su3_sym_48x24x24x24', nrhs=12, launches=6):
+    """The batched FP64 hop of the 12-source solve (autotuned shape), launched
+    `launches` times in the benchmark pattern so that its HBM counters can be
+    taken; returns the run description the traffic record is written from."""
+    cfg = synth.CONFIGS[name]
+    lat = W.Lattice(cfg['N'], cfg['rep'], cfg['dims'], cfg['bc'])
+    UR = lat.new_links(W.F64)
+    lat.rep_links(UR, torch.from_numpy(synth.links_for(cfg)).cuda(), W.F64)
+    best = lat.autotune(UR, W.F64, nrhs)
+    f = [lat.new_half(nrhs) for _ in range(3)]
+    g = torch.Generator(device='cuda')
+    g.manual_seed(7)
+    f[0].view(torch.float64).normal_(generator=g)
+    for k in range(launches):
+        src, dst = (f[0], f[1]) if k % 2 == 0 else (f[1], f[2])
+        lat.dslash_eo(dst, src, UR, 0 if k % 2 == 0 else 1, nrhs=nrhs)
+    torch.cuda.synchronize()
+    link = lat.d * lat.d * 8 * (1 if lat.real else 2)
+    spinor = 4 * lat.d * 2 * 8
+    return {'workload': f'{name} FP64, {nrhs} right-hand sides in one launch, launches alternating D_eo / D_oe',
+            'hop_sources_sha256': hop_sources_sha256(), 'kernel_pattern': 'k_hop', 'launches_per_shape': launches,
+            'algorithmic_bytes_per_launch': (8 * link + 2 * nrhs * spinor) * lat.Vh,
+            'compulsory_read_bytes': (8 * link + nrhs * spinor) * lat.Vh,
+            'shapes': [{k: best[k] for k in ('variant', 'xcd_remap', 'tblock', 'nr')}],
+            'tuned_us': best['us']}
 
 
 def multi_rhs_cg(W, torch, synth, name='su3_sym_48x24x24x24'):
@@ -694,10 +800,23 @@ def main():
     ap.add_argument('--traffic-shapes', action='store_true',
                     help='profiling aid: 6 hop launches (the benchmark pattern) for every FP64 launch shape the '
                          'autotuner may pick, in the order printed, to take HBM counters per shape')
+    ap.add_argument('--traffic-multi', action='store_true',
+                    help='profiling aid: 6 launches of the 12-source FP64 hop on SU(3) SYM 48x24^3 with the '
+                         'autotuned shape, to take HBM counters on the batched hop')
     ap.add_argument('--copy-calibration', action='store_true',
-                    help='run only a device copy of 2 GiB (x3), the known-size kernel that calibrates the '
-                         'FETCH_SIZE / WRITE_SIZE counters, and print its bandwidth')
+                    help='run only the kernels of known traffic that calibrate the FETCH_SIZE / WRITE_SIZE '
+                         'counters (a 2 GiB device copy x4, the 7-read/1-write streaming probe x4) and print '
+                         'their byte counts')
+    ap.add_argument('--traffic-record', nargs=7,
+                    metavar=('OUT', 'RUN_JSON', 'FETCH_CSV', 'WRITE_CSV', 'CAL_JSON', 'CAL_FETCH_CSV',
+                             'CAL_WRITE_CSV'),
+                    help='no GPU: write the per-launch traffic record OUT from the JSON line of a '
+                         '--traffic-shapes or --traffic-multi run, its rocprofv3 FETCH_SIZE and WRITE_SIZE '
+                         'counter_collection.csv files, and the same three of a --copy-calibration run')
     args = ap.parse_args()
+    if args.traffic_record:
+        write_traffic_record(*args.traffic_record)
+        return
     if args.gpus != 1:
         print(f'bench.py measures one GPU only; --gpus {args.gpus} is not supported '
               f'(how the path would shard over several GPUs is described in the design notes, not implemented)', file=sys.stderr)
@@ -709,13 +828,22 @@ def main():
     if args.copy_calibration:
         n = 1 << 28
         ms, g = device_copy_gbps(torch, n)
-        print(json.dumps({'copy_bytes_read': n * 8, 'copy_bytes_written': n * 8, 'copies': 4,
-                          'ms_per_copy': round(ms, 4), 'GBps_read_plus_write': round(g, 1)}))
+        from paper_2503_06721_amd import wdirac as W
+        elems = 1 << 24
+        sg = W.stream_probe(elems, 7, 3)
+        print(json.dumps({'kernels': [
+            {'name': 'device_copy', 'pattern': 'copyBuffer', 'bytes_read': n * 8, 'bytes_written': n * 8,
+             'dispatches': 4, 'ms_per_copy': round(ms, 4), 'GBps_read_plus_write': round(g, 1)},
+            {'name': 'stream_probe', 'pattern': 'k_stream<7>', 'bytes_read': 7 * elems * 16,
+             'bytes_written': elems * 16, 'dispatches': 4, 'GBps_read_plus_write': round(sg, 1)}]}))
         return
 
     from paper_2503_06721_amd import synth
     from paper_2503_06721_amd import wdirac as W
 
+    if args.traffic_multi:
+        print(json.dumps(traffic_multi(W, torch, synth)), flush=True)
+        return
     if args.only:
         print(json.dumps(SECTIONS[args.only](W, torch, synth)), flush=True)
         return
@@ -757,7 +885,12 @@ def main():
                         lat.dslash_eo(dst, src, UR64, 0 if k % 2 == 0 else 1)
                     shapes.append({'variant': variant, 'xcd_remap': remap, 'tblock': tb, 'nr': 1})
         torch.cuda.synchronize()
-        print(json.dumps({'launches_per_shape': 6, 'shapes': shapes}))
+        print(json.dumps({'workload': f'{WORKLOAD} FP64, one right-hand side, launches alternating D_eo / D_oe '
+                                      'as in the benchmark',
+                          'hop_sources_sha256': hop_sources_sha256(), 'kernel_pattern': 'k_hop',
+                          'launches_per_shape': 6, 'algorithmic_bytes_per_launch': bytes_per_launch,
+                          'compulsory_read_bytes': bytes_per_launch - 4 * d * 2 * 8 * lat.Vh,
+                          'shapes': shapes}))
         return
     # the library's autotuner picks the hop launch shape for both precisions
     tuned = {'f64': lat.autotune(UR64, W.F64, 1), 'f32': lat.autotune(UR32, W.F32, 1)}

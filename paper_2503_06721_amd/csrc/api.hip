@@ -574,21 +574,24 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
     if (rc == WDIRAC_OK && hipEventElapsedTime(ms, e0, e1) != hipSuccess) rc = fail(WDIRAC_EHIP, "hipEventElapsedTime");
     *ms /= (float)reps;
   };
-  // Pass 1: every candidate, 10 launches.  Pass 2: the best four again, five
-  // interleaved rounds of at least 20 launches and about 25 ms each (so that
-  // millisecond-scale kernels are timed over many launches), keeping each
-  // one's fastest round; the spread of the pick's rounds is reported.
+  // Pass 1: every candidate, 10 launches, then again over about 5 ms (at
+  // most 100 launches), keeping the faster.  Pass 2: the best six again,
+  // five interleaved rounds of at least 20 launches and about 25 ms each (so
+  // that millisecond-scale kernels are timed over many launches), keeping
+  // each one's fastest round; the spread of the pick's rounds is reported.
   std::vector<std::pair<float, int>> t1;
   for (size_t i = 0; i < cands.size() && rc == WDIRAC_OK; ++i) {
-    float ms;
+    float ms, ms2 = 1e30f;
     time_cand(cands[i], 10, &ms);
-    t1.push_back({ms, (int)i});
+    const int n2 = std::min(100, (int)(5.0f / std::max(ms, 1e-3f)));
+    if (rc == WDIRAC_OK && n2 > 10) time_cand(cands[i], n2, &ms2);
+    t1.push_back({std::min(ms, ms2), (int)i});
   }
   float best_ms = 1e30f, best_worst = 0.0f, second_ms = 0.0f;
   Cand pick = cands.front();
   if (rc == WDIRAC_OK) {
     std::sort(t1.begin(), t1.end());
-    const size_t nfin = std::min<size_t>(4, t1.size());
+    const size_t nfin = std::min<size_t>(6, t1.size());
     std::vector<float> t2(nfin, 1e30f), t2w(nfin, 0.0f);
     std::vector<int> reps(nfin);
     for (size_t j = 0; j < nfin; ++j)
