@@ -963,8 +963,8 @@ def main():
         'roofline': {'bound': 'hbm', 'achieved': round(gbs, 2), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
                      'frac': round(gbs / HBM_PEAK_GBS, 4),
                      'traffic': traffic,
-                     'traffic_unit': 'HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, calibrated '
-                                     'on a 2 GiB copy)',
+                     'traffic_unit': 'HBM bytes per launch (rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1, factors '
+                                     'calibrated on the non-temporal streaming probe and a 2 GiB copy)',
                      'traffic_GBps': None if traffic is None else round(traffic / (hop_ms * 1e-3) / 1e9, 2),
                      'effective_GBps': round(effective_bytes_per_site(d, lat.real, 8) * lat.Vh / (hop_ms * 1e-3)
                                              / 1e9, 2),
