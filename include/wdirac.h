@@ -202,8 +202,9 @@ typedef struct {
 
 /* Autotuner: times every available launch shape of the hopping kernel
  * (variant x right-hand sides per block x XCD tile mapping x tile order) for
- * nrhs right-hand sides in precision prec on the links UR (HIP events: 4
- * warm-up and 10 timed launches each, repeated over ~5 ms, then the six
+ * nrhs right-hand sides in precision prec on the links UR (HIP events,
+ * after ~50 ms of untimed launches: 4 warm-up and 10 timed launches each,
+ * repeated over ~5 ms, then the six
  * fastest again in five interleaved rounds of max(20, ~25 ms) launches, each
  * keeping its fastest round; launches
  * alternate D_eo and D_oe over three fields so that every other launch reads

@@ -203,7 +203,7 @@ int effective_nr(const wdirac_ctx *c, int pref, int nrhs, int prec, int variant)
   // site-parallel form: 4 right-hand sides across the lanes of a wavefront, or 1
   if (variant == wd::HOP_SITE) return (pref >= 4 && nrhs % 4 == 0) ? 4 : 1;
   for (int nr = std::min(pref, variant == wd::HOP_MULTI ? 12 : 6); nr > 1; --nr)
-    if (nrhs % nr == 0 && wd::hop_nr_supported(c->d, prec, variant, nr)) return nr;
+    if (nrhs % nr == 0 && wd::hop_nr_supported(c->N, c->d, prec, variant, nr)) return nr;
   return 1;
 }
 
@@ -580,6 +580,13 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
   // that millisecond-scale kernels are timed over many launches), keeping
   // each one's fastest round; the spread of the pick's rounds is reported.
   std::vector<std::pair<float, int>> t1;
+  {
+    // untimed: about 50 ms of launches first, so that no candidate is timed
+    // while the clocks are still ramping up
+    float ms;
+    time_cand(cands.front(), 4, &ms);
+    if (rc == WDIRAC_OK) time_cand(cands.front(), std::min(1000, std::max(4, (int)(50.0f / std::max(ms, 1e-3f)))), &ms);
+  }
   for (size_t i = 0; i < cands.size() && rc == WDIRAC_OK; ++i) {
     float ms, ms2 = 1e30f;
     time_cand(cands[i], 10, &ms);

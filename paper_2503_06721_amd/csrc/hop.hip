@@ -216,27 +216,41 @@ __device__ __forceinline__ void rebuild_row(cplx<T> (&u)[D], const cplx<T> (&xr)
   }
 }
 
+// Fundamental entries per link of the compact form FLY (1 for stored links),
+// and the LDS rows that hold them: a multiple of D, so that every wave loads
+// the same number of entries (the last rows repeat entry NE - 1 unused).
+template <int D, int FLY>
+constexpr int fly_entries() {
+  return FLY ? two_index_n<D, FLY == 2>() * two_index_n<D, FLY == 2>() : 1;
+}
+template <int D, int FLY>
+constexpr int fly_rows() {
+  return FLY ? (fly_entries<D, FLY>() + D - 1) / D * D : 1;
+}
+
+// Stage one hop.  Stored links: this lane's row (forward) or column
+// (backward) of U_R into registers u.  Compact form: the block's waves share
+// the N^2 fundamental entries of each site's link, wave `row` loading entries
+// row, row + D, ... into fl (each entry is read from memory once per site, not
+// once per wave that needs it); u is rebuilt from fl after the barrier
+// (cs_rebuild).  Then the spin projection of colour `row` of the neighbour
+// spinor into hs.
 template <int D, bool REAL, typename T, int MU, int SIG, bool BWD, int NR, bool NTL, int FLY>
 __device__ __forceinline__ void cs_stage(typename LinkT<T, REAL>::type (&u)[D], cplx<T> (*hs)[2][D][64],
-                                         const Geom &g, int parity, const typename LinkT<T, REAL>::type *links,
-                                         const cplx<T> *flinks, const cplx<T> *in0, size_t rstride, int nb,
-                                         int lsite, int row, int lane) {
+                                         cplx<T> (*fl)[64], const Geom &g, int parity,
+                                         const typename LinkT<T, REAL>::type *links, const cplx<T> *flinks,
+                                         const cplx<T> *in0, size_t rstride, int nb, int lsite, int row, int lane) {
   using L = typename LinkT<T, REAL>::type;
   const int stride = g.stride;
   const int lpar = BWD ? 1 - parity : parity;
   if constexpr (FLY != 0) {
-    constexpr bool SYM = FLY == 2;
-    constexpr int N = two_index_n<D, SYM>();
-    const cplx<T> *fk = flinks + (size_t)(lpar * 4 + MU) * N * N * stride + link_site(N * N, stride, lsite);
-    int a1, a2;
-    pair_of<N, SYM>(row, a1, a2);
-    cplx<T> xr[N], yr[N];
+    constexpr int NE = fly_entries<D, FLY>();
+    const cplx<T> *fk = flinks + (size_t)(lpar * 4 + MU) * NE * stride + link_site(NE, stride, lsite);
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-      xr[c] = ld_stream<NTL>(fk + link_row(BWD ? c * N + a1 : a1 * N + c, stride));
-      yr[c] = ld_stream<NTL>(fk + link_row(BWD ? c * N + a2 : a2 * N + c, stride));
+    for (int j = 0; j < fly_rows<D, FLY>() / D; ++j) {
+      const int e = row + j * D;
+      fl[e][lane] = ld_stream<NTL>(fk + link_row(e < NE ? e : NE - 1, stride));
     }
-    rebuild_row<D, N, SYM, T>(u, xr, yr, (SYM && a1 == a2) ? (T)0.70710678118654752440 : (T)1);
   } else {
     const L *lk = links + (size_t)(lpar * 4 + MU) * D * D * stride;
 #pragma unroll
@@ -251,6 +265,27 @@ __device__ __forceinline__ void cs_stage(typename LinkT<T, REAL>::type (&u)[D], 
     for (int s = 0; s < 4; ++s) p[s] = in[(size_t)(s * D + row) * stride + nb];
     hs[k][0][row][lane] = p[0] + ipow<PROJ_PH(MU, SIG, 0)>(p[2 + ECOL(MU, 0)]);
     hs[k][1][row][lane] = p[1] + ipow<PROJ_PH(MU, SIG, 1)>(p[2 + ECOL(MU, 1)]);
+  }
+}
+
+// Compact form, after the barrier: rebuild this lane's row (forward) or
+// column (backward) of U_R from the fundamental rows (columns) a1, a2 staged
+// in fl.
+// (No-op for stored links.)
+template <int D, typename T, bool BWD, int FLY, typename U>
+__device__ __forceinline__ void cs_rebuild(U (&u)[D], cplx<T> (*fl)[64], int row, int lane) {
+  if constexpr (FLY != 0) {
+    constexpr bool SYM = FLY == 2;
+    constexpr int N = two_index_n<D, SYM>();
+    int a1, a2;
+    pair_of<N, SYM>(row, a1, a2);
+    cplx<T> xr[N], yr[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      xr[c] = fl[BWD ? c * N + a1 : a1 * N + c][lane];
+      yr[c] = fl[BWD ? c * N + a2 : a2 * N + c][lane];
+    }
+    rebuild_row<D, N, SYM, T>(u, xr, yr, (SYM && a1 == a2) ? (T)0.70710678118654752440 : (T)1);
   }
 }
 
@@ -282,7 +317,8 @@ __device__ __forceinline__ void cs_compute(cplx<T> (&acc)[NR][4], const typename
 // doubles the loads in flight per phase at the cost of twice the LDS.
 // (STG = 4, two directions per phase, is cs_mu2 below.)
 template <int D, bool REAL, typename T, int MU, int SF, int NR, int STG, bool NTL, int NB, int FLY>
-__device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64], const Geom &g, int parity,
+__device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64],
+                                      cplx<T> (*fls)[(fly_rows<D, FLY>())][64], const Geom &g, int parity,
                                       const typename LinkT<T, REAL>::type *links, const cplx<T> *flinks,
                                       const cplx<T> *in0, size_t rstride, int t, int x, int y, int z, int is, int row,
                                       int lane) {
@@ -292,21 +328,25 @@ __device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2
   L uf[D], ub[D];
   if constexpr (STG == 2) {
     constexpr int B0 = 2 * (MU & 1);
-    cs_stage<D, REAL, T, MU, SF, false, NR, NTL, FLY>(uf, hs[B0], g, parity, links, flinks, in0, rstride, nbf, is,
-                                                      row, lane);
-    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL, FLY>(ub, hs[B0 + 1], g, parity, links, flinks, in0, rstride, nbb,
-                                                      nbb, row, lane);
+    cs_stage<D, REAL, T, MU, SF, false, NR, NTL, FLY>(uf, hs[B0], fls[B0], g, parity, links, flinks, in0, rstride,
+                                                      nbf, is, row, lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL, FLY>(ub, hs[B0 + 1], fls[B0 + 1], g, parity, links, flinks, in0,
+                                                      rstride, nbb, nbb, row, lane);
     __syncthreads();
+    cs_rebuild<D, T, false, FLY>(uf, fls[B0], row, lane);
     cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[B0], lane);
+    cs_rebuild<D, T, true, FLY>(ub, fls[B0 + 1], row, lane);
     cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[B0 + 1], lane);
   } else {
-    cs_stage<D, REAL, T, MU, SF, false, NR, NTL, FLY>(uf, hs[0], g, parity, links, flinks, in0, rstride, nbf, is,
-                                                      row, lane);
+    cs_stage<D, REAL, T, MU, SF, false, NR, NTL, FLY>(uf, hs[0], fls[0], g, parity, links, flinks, in0, rstride, nbf,
+                                                      is, row, lane);
     __syncthreads();
+    cs_rebuild<D, T, false, FLY>(uf, fls[0], row, lane);
     cs_compute<D, REAL, T, MU, SF, false, NR>(acc, uf, hs[0], lane);
-    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL, FLY>(ub, hs[1], g, parity, links, flinks, in0, rstride, nbb, nbb,
-                                                      row, lane);
+    cs_stage<D, REAL, T, MU, -SF, true, NR, NTL, FLY>(ub, hs[1], fls[1], g, parity, links, flinks, in0,
+                                                      rstride, nbb, nbb, row, lane);
     __syncthreads();
+    cs_rebuild<D, T, true, FLY>(ub, fls[1], row, lane);
     cs_compute<D, REAL, T, MU, -SF, true, NR>(acc, ub, hs[1], lane);
   }
 }
@@ -323,15 +363,16 @@ __device__ __forceinline__ void cs_mu2(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][
   constexpr int MU1 = MU0 + 1, B0 = 2 * MU0;
   const int f0 = nb_index(g, t, x, y, z, MU0, 1), b0 = nb_index(g, t, x, y, z, MU0, 0);
   const int f1 = nb_index(g, t, x, y, z, MU1, 1), b1 = nb_index(g, t, x, y, z, MU1, 0);
+  static_assert(FLY == 0, "four hops per phase: stored links only");
   L u0f[D], u0b[D], u1f[D], u1b[D];
-  cs_stage<D, REAL, T, MU0, SF, false, NR, NTL, FLY>(u0f, hs[B0], g, parity, links, flinks, in0, rstride, f0, is, row,
-                                                     lane);
-  cs_stage<D, REAL, T, MU0, -SF, true, NR, NTL, FLY>(u0b, hs[B0 + 1], g, parity, links, flinks, in0, rstride, b0, b0,
-                                                     row, lane);
-  cs_stage<D, REAL, T, MU1, SF, false, NR, NTL, FLY>(u1f, hs[B0 + 2], g, parity, links, flinks, in0, rstride, f1, is,
-                                                     row, lane);
-  cs_stage<D, REAL, T, MU1, -SF, true, NR, NTL, FLY>(u1b, hs[B0 + 3], g, parity, links, flinks, in0, rstride, b1, b1,
-                                                     row, lane);
+  cs_stage<D, REAL, T, MU0, SF, false, NR, NTL, 0>(u0f, hs[B0], nullptr, g, parity, links, flinks, in0, rstride, f0,
+                                                   is, row, lane);
+  cs_stage<D, REAL, T, MU0, -SF, true, NR, NTL, 0>(u0b, hs[B0 + 1], nullptr, g, parity, links, flinks, in0, rstride,
+                                                   b0, b0, row, lane);
+  cs_stage<D, REAL, T, MU1, SF, false, NR, NTL, 0>(u1f, hs[B0 + 2], nullptr, g, parity, links, flinks, in0, rstride,
+                                                   f1, is, row, lane);
+  cs_stage<D, REAL, T, MU1, -SF, true, NR, NTL, 0>(u1b, hs[B0 + 3], nullptr, g, parity, links, flinks, in0, rstride,
+                                                   b1, b1, row, lane);
   __syncthreads();
   cs_compute<D, REAL, T, MU0, SF, false, NR>(acc, u0f, hs[B0], lane);
   cs_compute<D, REAL, T, MU0, -SF, true, NR>(acc, u0b, hs[B0 + 1], lane);
@@ -344,8 +385,14 @@ __device__ __forceinline__ void cs_mu2(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][
 template <int D, bool REAL, typename T, bool DAG, int NR, int STG, bool NTL, int W, int FLY>
 __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) void k_hop_cs(HopArgs a) {
   constexpr int NB = 2 * STG;   // LDS buffers
+  constexpr int NE = fly_rows<D, FLY>();
   __shared__ cplx<T> hs[NB][NR][2][D][64];
   __shared__ double sh[D];
+  cplx<T>(*fls)[NE][64] = nullptr;   // compact form: staged fundamental entries
+  if constexpr (FLY != 0) {
+    __shared__ cplx<T> fbuf[NB][NE][64];
+    fls = fbuf;
+  }
   // Work item = (tile, group of NR right-hand sides), group fastest, so the
   // groups of one tile are consecutive and (after the XCD remap) run on the
   // same XCD at nearly the same time: each link entry comes from HBM once
@@ -358,7 +405,8 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
   const int l = lattice_of_tile(a, tile);
   const Geom g = a.lat[l].g;
   const int tl = tile - a.lat[l].tile0;   // tile within its lattice
-  const int lane = threadIdx.x & 63, row = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int row = FLY ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : (int)(threadIdx.x >> 6);
   const int i = tl * 64 + lane;
   const bool valid = i < g.Vh;
   const int is = valid ? i : g.Vh - 1;   // lanes past the end: see k_hop_sp
@@ -383,13 +431,13 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
     cs_mu2<D, REAL, T, 2, SF, NR, NTL, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z, is, row,
                                             lane);
   } else {
-    cs_mu<D, REAL, T, 0, SF, NR, STG, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+    cs_mu<D, REAL, T, 0, SF, NR, STG, NTL, NB, FLY>(acc, hs, fls, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
                                                     is, row, lane);
-    cs_mu<D, REAL, T, 1, SF, NR, STG, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+    cs_mu<D, REAL, T, 1, SF, NR, STG, NTL, NB, FLY>(acc, hs, fls, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
                                                     is, row, lane);
-    cs_mu<D, REAL, T, 2, SF, NR, STG, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+    cs_mu<D, REAL, T, 2, SF, NR, STG, NTL, NB, FLY>(acc, hs, fls, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
                                                     is, row, lane);
-    cs_mu<D, REAL, T, 3, SF, NR, STG, NTL, NB, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
+    cs_mu<D, REAL, T, 3, SF, NR, STG, NTL, NB, FLY>(acc, hs, fls, g, a.parity, links, flinks, in0, rstride, t, x, y, z,
                                                     is, row, lane);
   }
   const T cb = (T)(-0.5 * a.beta), ca = (T)a.alpha;
@@ -453,9 +501,9 @@ constexpr int sp_waves(int D, bool dbl) { return dbl ? 2 : (D <= 2 ? 4 : D <= 4 
 // a gfx950 workgroup may allocate (less the reduction scratch).  Blocks above
 // 80 KB run one per CU; the autotuner weighs that against the link sharing.
 constexpr int LDS_BUDGET = 160 * 1024 - 256;
-template <int D, typename T, int NR, int STG>
+template <int D, typename T, int NR, int STG, int FLY = 0>
 constexpr bool cs_fits() {
-  return 2 * STG * NR * 2 * D * 64 * (int)sizeof(cplx<T>) <= LDS_BUDGET;
+  return 2 * STG * (NR * 2 * D + (FLY ? fly_rows<D, FLY>() : 0)) * 64 * (int)sizeof(cplx<T>) <= LDS_BUDGET;
 }
 // Six right-hand sides per block: colour form (unpaired) with d_R <= 4 only;
 // beyond that the accumulators no longer fit in registers.
@@ -464,13 +512,9 @@ constexpr bool cs6_ok() {
   return D <= 4 && cs_fits<D, T, 6, 1>();
 }
 
-// The compact forms hold the fundamental rows besides the rebuilt entries:
-// one wave per SIMD fewer for the paired form and for several rhs, so that
-// they compile without spills.
-constexpr int cs_waves_form(int D, bool dbl, int NR, bool pair, int fly) {
-  const int w = cs_waves(D, dbl, NR) - (fly ? (pair ? 1 : 0) + (NR > 1 ? 1 : 0) : 0);
-  return w > 1 ? w : 1;
-}
+// The compact forms rebuild the entries after the barrier from LDS, so they
+// hold no link registers across it: the same occupancy as the stored form.
+constexpr int cs_waves_form(int D, bool dbl, int NR, bool, int) { return cs_waves(D, dbl, NR); }
 
 // Four hops per phase (stage 4): one right-hand side per block, stored links,
 // d_R <= 4.
@@ -491,7 +535,7 @@ static hipError_t launch_cs2(const HopArgs &a, int stage, hipStream_t st) {
       return hipGetLastError();
     }
   }
-  if constexpr (NR <= 4 && cs_fits<D, T, NR, 2>()) {
+  if constexpr (NR <= 4 && cs_fits<D, T, NR, 2, FLY>()) {
     if (stage == 2) {
       hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, 2, NTL, WP, FLY>), grid, dim3(64 * D), 0, st, a);
       return hipGetLastError();
@@ -519,7 +563,7 @@ template <int D, typename T, bool DAG, int FLY>
 static hipError_t launch_compact(const HopArgs &a0, int nrhs, int pair, int nr, hipStream_t st, Counts *counts,
                                  int *prow) {
   if (nr >= 2 && nrhs % 2 == 0) {
-    if constexpr (cs_fits<D, T, 2, 1>())
+    if constexpr (cs_fits<D, T, 2, 1, FLY>())
       return launch_cs<D, false, T, DAG, 2, FLY>(a0, nrhs, pair ? 2 : 1, st, counts, prow);
   }
   return launch_cs<D, false, T, DAG, 1, FLY>(a0, nrhs, pair ? 2 : 1, st, counts, prow);
@@ -613,16 +657,17 @@ hipError_t launch_hop(const HopArgs &a, int N, int rep, int d, int real, int pre
   return hipErrorInvalidValue;
 }
 
-bool hop_nr_supported(int d, int prec, int variant, int nr) {
+bool hop_nr_supported(int N, int d, int prec, int variant, int nr) {
   if (variant == HOP_MULTI) return nr == 1 || nr == 2 || nr == 3 || nr == 4 || nr == 6 || nr == 12;
   // as cs_fits, cs6_ok and launch_compact
   const int cb = prec == 0 ? 16 : 8;
   const int nbuf = variant == HOP_COLOUR_QUAD ? 8 : (variant == HOP_COLOUR_PAIR || variant == HOP_COMPACT_PAIR) ? 4 : 2;
+  const bool compact = variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR;
   if (variant == HOP_COLOUR_QUAD && (nr != 1 || d > 4)) return false;
   if (nr < 1 || nr > 6 || nr == 5) return false;
   if (nr == 6 && (variant != HOP_COLOUR || d > 4)) return false;
-  if ((variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR) && nr > 2) return false;
-  return nbuf * nr * 2 * d * 64 * cb <= LDS_BUDGET;
+  if (compact && nr > 2) return false;
+  return nbuf * (nr * 2 * d + (compact ? (N * N + d - 1) / d * d : 0)) * 64 * cb <= LDS_BUDGET;
 }
 
 bool compact_links_ok(int N, int rep) { return (rep == 2 && N >= 2 && N <= 4) || (rep == 3 && N == 4); }

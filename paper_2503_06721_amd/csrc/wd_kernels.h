@@ -79,7 +79,7 @@ hipError_t launch_hop(const HopArgs &a, int N, int rep, int d, int real, int pre
 // Whether the colour-split form of the given variant takes nr right-hand
 // sides per block (nr in 1..4, or 6 for the unpaired form with d_R <= 4)
 // within the LDS budget.
-bool hop_nr_supported(int d, int prec, int variant, int nr);
+bool hop_nr_supported(int N, int d, int prec, int variant, int nr);
 bool hop_variant_ok(int N, int rep, int d, int variant);
 // hop_mr.hip: the HOP_MULTI form (nr = right-hand sides per block, one of
 // 1, 2, 3, 4, 6, 12, dividing nrhs); built for complex d_R = 3, 6 and real

@@ -128,28 +128,29 @@ MULTI_PAIRS = [(3, 'FUND'), (3, 'SYM'), (4, '2AS'), (2, 'ADJ')]
 def test_dslash_multi_rhs_staged_links(W, N, rep, dims):
     """The multi-rhs form with links staged in LDS (one wavefront per rhs, two
     lanes per site for d_R = 6): every rhs group size, both parities, the
-    dagger form, the x_add epilogue, both precisions; (2, 6, 2, 6) leaves a
-    ragged tile tail (36 sites per parity) and 2^4 has x+mu = x-mu."""
+    dagger form, the x_add epilogue, both precisions, both XCD mappings;
+    (2, 6, 2, 6) leaves a ragged tile tail (36 sites per parity) and 2^4 has
+    x+mu = x-mu."""
     s = Setup(N, rep, dims, seed=280 + N)
-    for nrhs, nrs in ((12, (1, 2, 3, 4, 6, 12)), (4, (2, 4))):
+    for nrhs, nrs in ((12, (1, 2, 3, 4, 6, 12)), (4, (1, 2, 4))):
         psi = s.spinor(281 + nrhs, nrhs)
         xadd = s.spinor(282 + nrhs, nrhs)
         exp = {(p, dagger, use_x): hop_expect(s, psi, p, dagger, 0.6 if use_x else 0.0, -1.1 if use_x else 1.0,
                                               xadd if use_x else None)
                for p in (0, 1) for dagger in (0, 1) for use_x in (False, True)}
-        for prec in (0, 1):
+        for prec, nr, remap in [(pr, n, m) for pr in (0, 1) for n in nrs for m in (0, 1)]:
             s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, W.HOP_MULTI)
-            for nr in nrs:
-                s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, nr)
-                log(f'multi-rhs N={N} rep={rep} dims={dims} nrhs={nrhs} prec={prec} nr={nr}')
-                for (p, dagger, use_x), e in exp.items():
-                    inp = s.to_gpu_half(psi, 1 - p, prec)
-                    xg = s.to_gpu_half(xadd, p, prec) if use_x else None
-                    out = s.lat.new_half(nrhs, prec)
-                    s.lat.dslash_eo(out, inp, s.URg[prec], p, dagger, nrhs, 0.6 if use_x else 0.0, xg,
-                                    -1.1 if use_x else 1.0, prec)
-                    err = rel(s.from_gpu_half(out, p, nrhs, prec), e)
-                    assert err < TOL[prec], (nrhs, prec, nr, p, dagger, use_x, err)
+            s.lat.set_option(W.OPT_XCD_REMAP, remap)
+            s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, nr)
+            log(f'multi-rhs N={N} rep={rep} dims={dims} nrhs={nrhs} prec={prec} nr={nr} remap={remap}')
+            for (p, dagger, use_x), e in exp.items():
+                inp = s.to_gpu_half(psi, 1 - p, prec)
+                xg = s.to_gpu_half(xadd, p, prec) if use_x else None
+                out = s.lat.new_half(nrhs, prec)
+                s.lat.dslash_eo(out, inp, s.URg[prec], p, dagger, nrhs, 0.6 if use_x else 0.0, xg,
+                                -1.1 if use_x else 1.0, prec)
+                err = rel(s.from_gpu_half(out, p, nrhs, prec), e)
+                assert err < TOL[prec], (nrhs, prec, nr, remap, p, dagger, use_x, err)
 
 
 @pytest.mark.parametrize('mode', [0, 1])
