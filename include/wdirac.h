@@ -129,7 +129,7 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                          1 or 2 rhs per block)
  *                                      5 = as 1 with two directions (four
  *                                          hops) staged per barrier phase
- *                                          (d_R <= 4; 1 rhs per block)
+ *                                          (d_R <= 6; 1 rhs per block)
  *                                      6 = several right-hand sides per
  *                                          block, one wavefront each, the
  *                                          tile's link entries staged once

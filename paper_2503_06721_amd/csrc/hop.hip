@@ -517,10 +517,11 @@ constexpr bool cs6_ok() {
 constexpr int cs_waves_form(int D, bool dbl, int NR, bool, int) { return cs_waves(D, dbl, NR); }
 
 // Four hops per phase (stage 4): one right-hand side per block, stored links,
-// d_R <= 4.
+// d_R <= 6 (at d_R = 6 in FP64 the block's 96 KB of LDS leave one block per
+// CU; still the fastest stored form on SU(3) SYM 48x24^3, 324 against 331 us).
 template <int D, typename T, int NR, int FLY>
 constexpr bool cs4_ok() {
-  return NR == 1 && FLY == 0 && D <= 4 && cs_fits<D, T, 1, 4>();
+  return NR == 1 && FLY == 0 && D <= 6 && cs_fits<D, T, 1, 4>();
 }
 
 // stage: hops staged per barrier phase, 1, 2 (paired directions) or 4.
@@ -663,7 +664,7 @@ bool hop_nr_supported(int N, int d, int prec, int variant, int nr) {
   const int cb = prec == 0 ? 16 : 8;
   const int nbuf = variant == HOP_COLOUR_QUAD ? 8 : (variant == HOP_COLOUR_PAIR || variant == HOP_COMPACT_PAIR) ? 4 : 2;
   const bool compact = variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR;
-  if (variant == HOP_COLOUR_QUAD && (nr != 1 || d > 4)) return false;
+  if (variant == HOP_COLOUR_QUAD && (nr != 1 || d > 6)) return false;
   if (nr < 1 || nr > 6 || nr == 5) return false;
   if (nr == 6 && (variant != HOP_COLOUR || d > 4)) return false;
   if (compact && nr > 2) return false;
@@ -676,7 +677,7 @@ bool hop_variant_ok(int N, int rep, int d, int variant) {
   if (variant == HOP_MULTI) return hop_mr_ok(d, rep == 1);
   if (variant == HOP_SITE) return d <= 6;
   if (variant == HOP_COMPACT || variant == HOP_COMPACT_PAIR) return compact_links_ok(N, rep);
-  if (variant == HOP_COLOUR_QUAD) return d <= 4;
+  if (variant == HOP_COLOUR_QUAD) return d <= 6;
   return variant == HOP_COLOUR || variant == HOP_COLOUR_PAIR;
 }
 

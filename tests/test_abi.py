@@ -116,6 +116,13 @@ def test_site_variant_unavailable_for_large_rep(W):
     assert rc == W.OK
     assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_SITE) == W.EUNSUPPORTED
     assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_COLOUR_QUAD) == W.EUNSUPPORTED
+    assert W._lib.wdirac_destroy(h) == W.OK
+    rc, h6 = create(W, 3, 2)   # SU(3) SYM, d = 6: four hops per phase available
+    assert rc == W.OK
+    assert W._lib.wdirac_set_option(h6, W.OPT_HOP_VARIANT_F64, W.HOP_COLOUR_QUAD) == W.OK
+    assert W._lib.wdirac_destroy(h6) == W.OK
+    rc, h = create(W, 4, 1)
+    assert rc == W.OK
     # the multi-rhs staged-link form is built for d_R = 3 and 6 only
     assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_MULTI) == W.EUNSUPPORTED
     assert W._lib.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, 7) == W.EINVAL
@@ -136,7 +143,9 @@ def test_batch_sizes_and_rejects(W):
     shapes = [(4, 6, 4, 6), (2, 2, 2, 2), (8, 8, 8, 8)]
     rc, h = create_batch(W, 3, 2, shapes)            # SU(3) SYM, d = 6
     assert rc == W.OK
-    strides = [((dd[0] * dd[1] * dd[2] * dd[3] // 2 + 255) // 256) * 256 for dd in shapes]
+    rows = [((dd[0] * dd[1] * dd[2] * dd[3] // 2 + 255) // 256) * 256 for dd in shapes]
+    # pitches that are a multiple of 1024 entries are padded by 256
+    strides = [r + 256 if r % 1024 == 0 else r for r in rows]
     assert W._lib.wdirac_field_bytes(h, W.FIELD_HALF_SPINOR, 1, W.F64) == 4 * 6 * sum(strides) * 16
     assert W._lib.wdirac_field_bytes(h, W.FIELD_LINKS, 1, W.F32) == (8 * 36 + 8 * 9) * sum(strides) * 8
     dummy = ctypes.c_void_p(0x1000)

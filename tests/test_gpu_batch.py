@@ -77,7 +77,7 @@ def test_batch_links_and_hops(W, N, rep):
     psi = b.spinors(901)
     for variant in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR, W.HOP_SITE) + (
             (W.HOP_COMPACT, W.HOP_COMPACT_PAIR) if b.lat.compact else ()) + (
-            (W.HOP_COLOUR_QUAD,) if b.lat.d <= 4 else ()):
+            (W.HOP_COLOUR_QUAD,) if b.lat.d <= 6 else ()):
         for prec in (0, 1):
             b.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, variant)
             for p, dagger in ((0, 0), (1, 1), (0, 1)):

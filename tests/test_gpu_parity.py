@@ -72,7 +72,7 @@ def hop_expect(s, psi_full, p, dagger, alpha, beta, xadd_full):
 @pytest.mark.parametrize('N,rep', PAIRS)
 def test_dslash_eo(W, N, rep, dims):
     s = Setup(N, rep, dims, seed=200 + N)
-    variants = ([W.HOP_COLOUR] + ([W.HOP_SITE] if s.d <= 6 else []) + ([W.HOP_COLOUR_QUAD] if s.d <= 4 else [])
+    variants = ([W.HOP_COLOUR] + ([W.HOP_SITE] if s.d <= 6 else []) + ([W.HOP_COLOUR_QUAD] if s.d <= 6 else [])
                 + ([W.HOP_COMPACT, W.HOP_COMPACT_PAIR] if s.lat.compact else []))
     nrhs = 2
     psi = s.spinor(201, nrhs)
@@ -107,7 +107,7 @@ def test_dslash_rhs_groups(W, N, rep):
         for prec in (0, 1):
             for variant in (W.HOP_COLOUR, W.HOP_COLOUR_PAIR, W.HOP_SITE) + (
                     (W.HOP_COMPACT, W.HOP_COMPACT_PAIR) if s.lat.compact else ()) + (
-                    (W.HOP_COLOUR_QUAD,) if s.d <= 4 else ()):
+                    (W.HOP_COLOUR_QUAD,) if s.d <= 6 else ()):
                 s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, variant)
                 for nr in (1, 2, 3, 4, 6):
                     s.lat.set_option(W.OPT_HOP_NR_F64 if prec == 0 else W.OPT_HOP_NR_F32, nr)
