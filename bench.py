@@ -182,6 +182,28 @@ def write_traffic_record(out_path, run_json, fetch_csv, write_csv, cal_json, cal
     print(json.dumps({'written': out_path, 'shapes': len(rows)}))
 
 
+def kernel_durations(trace_csv, pattern, last):
+    """Dispatch count and mean duration of the kernels whose name contains
+    `pattern` in a rocprofv3 kernel_trace.csv, and the mean, median, min and
+    max over the last `last` of them (the benchmark's timed launches)."""
+    import statistics
+    rows = []
+    with open(trace_csv, newline='') as f:
+        for r in csv.DictReader(f):
+            if pattern in r['Kernel_Name']:
+                rows.append((int(r['Dispatch_Id']), int(r['End_Timestamp']) - int(r['Start_Timestamp']),
+                             r['Kernel_Name']))
+    if not rows:
+        raise SystemExit(f'no dispatch of {pattern!r} in {trace_csv}')
+    rows.sort()
+    d = [x[1] for x in rows]
+    t = d[-last:]
+    return (f'kernel: {rows[-1][2]}\n'
+            f'dispatches: {len(d)}, mean over all: {statistics.mean(d):.0f} ns\n'
+            f'last {len(t)} dispatches: mean {statistics.mean(t):.0f} ns, median {statistics.median(t):.0f} ns, '
+            f'min {min(t)} ns, max {max(t)} ns')
+
+
 def host_info():
     """The host the CPU baseline ran on: CPU model, logical CPUs, the CPUs this
     process may use, and the thread settings NumPy sees."""
@@ -813,7 +835,13 @@ def main():
                     help='no GPU: write the per-launch traffic record OUT from the JSON line of a '
                          '--traffic-shapes or --traffic-multi run, its rocprofv3 FETCH_SIZE and WRITE_SIZE '
                          'counter_collection.csv files, and the same three of a --copy-calibration run')
+    ap.add_argument('--kernel-durations', nargs=3, metavar=('TRACE_CSV', 'PATTERN', 'LAST'),
+                    help='no GPU: mean duration of one kernel in a rocprofv3 kernel_trace.csv, over all its '
+                         'dispatches and over the last LAST (the timed launches)')
     args = ap.parse_args()
+    if args.kernel_durations:
+        print(kernel_durations(args.kernel_durations[0], args.kernel_durations[1], int(args.kernel_durations[2])))
+        return
     if args.traffic_record:
         write_traffic_record(*args.traffic_record)
         return

@@ -1,5 +1,6 @@
 """Host logic of bench.py that needs no GPU: the compulsory-byte counts of the
-hop and the traffic record written from rocprofv3 counter files."""
+hop, the traffic record written from rocprofv3 counter files, and kernel
+durations read from a rocprofv3 kernel trace."""
 import csv
 import json
 import os
@@ -78,3 +79,19 @@ def test_traffic_record(tmp_path):
     assert a['traffic_over_algorithmic'] == 1.0
     assert b['fetch_size_kib_per_launch'] == 700.0 and 'k_hop_sp' in b['kernel']
     assert b['reads_over_compulsory_reads'] == round(700.0 * 2 / 800, 4)
+
+
+def test_kernel_durations(tmp_path):
+    """Mean over all dispatches of the kernel and over the last ones, in
+    dispatch order, other kernels ignored."""
+    p = tmp_path / 'trace.csv'
+    with open(p, 'w', newline='') as f:
+        w = csv.writer(f)
+        w.writerow(['Dispatch_Id', 'Kernel_Name', 'Start_Timestamp', 'End_Timestamp'])
+        w.writerow([3, 'k_hop_cs<A>', 100, 400])     # 300
+        w.writerow([1, 'k_hop_cs<A>', 0, 100])       # 100
+        w.writerow([2, 'other', 0, 5000])
+        w.writerow([4, 'k_hop_cs<A>', 500, 1000])    # 500
+    out = bench.kernel_durations(str(p), 'k_hop_cs<A>', 2)
+    assert 'dispatches: 3, mean over all: 300 ns' in out
+    assert 'last 2 dispatches: mean 400 ns, median 400 ns, min 300 ns, max 500 ns' in out
