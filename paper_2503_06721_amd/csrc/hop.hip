@@ -351,6 +351,76 @@ __device__ __forceinline__ void cs_mu(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2
   }
 }
 
+// Compact form, software-pipelined (FP64, one rhs per block, STG = 1): the
+// global loads of hop h + 1 (this wave's fundamental link entries and spinor
+// components) are issued right after hop h's barrier and land while hop h
+// rebuilds its link row and computes; one barrier per hop over the two LDS
+// buffer sets (a buffer is rewritten two hops after it was read, with a
+// barrier between).  Measured per hop: SU(3) SYM 48x24^3 212 -> 191 us,
+// SU(4) 2AS 96x48^3 4769 -> 4014 us; in FP32 it gains nothing (1811 -> 1859
+// us for SU(4) 2AS) and is not used.
+template <int D, typename T, int NR, int FLY>
+struct CsRaw {
+  cplx<T> f[fly_rows<D, FLY>() / D];   // fundamental entries row, row + D, ...
+  cplx<T> p[NR][4];                     // colour `row` of the neighbour spinor, per spin
+};
+
+template <int D, typename T, int MU, bool BWD, int NR, bool NTL, int FLY>
+__device__ __forceinline__ void cs_load(CsRaw<D, T, NR, FLY> &rw, const Geom &g, int parity, const cplx<T> *flinks,
+                                        const cplx<T> *in0, size_t rstride, int nb, int lsite, int row) {
+  constexpr int NE = fly_entries<D, FLY>();
+  const int stride = g.stride;
+  const int lpar = BWD ? 1 - parity : parity;
+  const cplx<T> *fk = flinks + (size_t)(lpar * 4 + MU) * NE * stride + link_site(NE, stride, lsite);
+#pragma unroll
+  for (int j = 0; j < fly_rows<D, FLY>() / D; ++j) {
+    const int e = row + j * D;
+    rw.f[j] = ld_stream<NTL>(fk + link_row(e < NE ? e : NE - 1, stride));
+  }
+#pragma unroll
+  for (int k = 0; k < NR; ++k)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) rw.p[k][s] = in0[k * rstride + (size_t)(s * D + row) * stride + nb];
+}
+
+template <int D, typename T, int MU, int SIG, int NR, int FLY>
+__device__ __forceinline__ void cs_publish(const CsRaw<D, T, NR, FLY> &rw, cplx<T> (*hs)[2][D][64], cplx<T> (*fl)[64],
+                                           int row, int lane) {
+#pragma unroll
+  for (int j = 0; j < fly_rows<D, FLY>() / D; ++j) fl[row + j * D][lane] = rw.f[j];
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    hs[k][0][row][lane] = rw.p[k][0] + ipow<PROJ_PH(MU, SIG, 0)>(rw.p[k][2 + ECOL(MU, 0)]);
+    hs[k][1][row][lane] = rw.p[k][1] + ipow<PROJ_PH(MU, SIG, 1)>(rw.p[k][2 + ECOL(MU, 1)]);
+  }
+}
+
+template <int D, typename T, int SF, int NR, bool NTL, int FLY, int H = 0>
+__device__ __forceinline__ void cs_pipe(cplx<T> (&acc)[NR][4], cplx<T> (*hs)[NR][2][D][64],
+                                        cplx<T> (*fls)[(fly_rows<D, FLY>())][64], CsRaw<D, T, NR, FLY> &rw,
+                                        const Geom &g, int parity, const cplx<T> *flinks, const cplx<T> *in0,
+                                        size_t rstride, const int (&nbf)[4], const int (&nbb)[4], int is, int row,
+                                        int lane) {
+  if constexpr (H < 8) {
+    constexpr int MU = H / 2;
+    constexpr bool BWD = (H & 1) != 0;
+    constexpr int SIG = BWD ? -SF : SF;
+    cs_publish<D, T, MU, SIG, NR, FLY>(rw, hs[H & 1], fls[H & 1], row, lane);
+    __syncthreads();
+    if constexpr (H < 7) {
+      constexpr int MU1 = (H + 1) / 2;
+      constexpr bool BWD1 = ((H + 1) & 1) != 0;
+      cs_load<D, T, MU1, BWD1, NR, NTL, FLY>(rw, g, parity, flinks, in0, rstride, BWD1 ? nbb[MU1] : nbf[MU1],
+                                             BWD1 ? nbb[MU1] : is, row);
+    }
+    cplx<T> u[D];
+    cs_rebuild<D, T, BWD, FLY>(u, fls[H & 1], row, lane);
+    cs_compute<D, false, T, MU, SIG, BWD, NR>(acc, u, hs[H & 1], lane);
+    cs_pipe<D, T, SF, NR, NTL, FLY, H + 1>(acc, hs, fls, rw, g, parity, flinks, in0, rstride, nbf, nbb, is, row,
+                                           lane);
+  }
+}
+
 // Directions MU0 and MU0 + 1 together (STG = 4): the four hops are staged
 // into LDS buffers 2*MU0 .. 2*MU0 + 3 before one barrier, so a launch has two
 // barrier phases and four hops' loads in flight in each.
@@ -425,7 +495,17 @@ __global__ __launch_bounds__(64 * D) __attribute__((amdgpu_waves_per_eu(W))) voi
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc[k][s] = mk<T>(0, 0);
   constexpr int SF = DAG ? -1 : 1;   // forward hop: 1 - g_mu (dagger: 1 + g_mu)
-  if constexpr (STG == 4) {
+  if constexpr (FLY != 0 && STG == 1 && NR == 1 && sizeof(T) == 8) {
+    int nbf[4], nbb[4];
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+      nbf[mu] = nb_index(g, t, x, y, z, mu, 1);
+      nbb[mu] = nb_index(g, t, x, y, z, mu, 0);
+    }
+    CsRaw<D, T, NR, FLY> rw;
+    cs_load<D, T, 0, false, NR, NTL, FLY>(rw, g, a.parity, flinks, in0, rstride, nbf[0], is, row);
+    cs_pipe<D, T, SF, NR, NTL, FLY>(acc, hs, fls, rw, g, a.parity, flinks, in0, rstride, nbf, nbb, is, row, lane);
+  } else if constexpr (STG == 4) {
     cs_mu2<D, REAL, T, 0, SF, NR, NTL, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z, is, row,
                                             lane);
     cs_mu2<D, REAL, T, 2, SF, NR, NTL, FLY>(acc, hs, g, a.parity, links, flinks, in0, rstride, t, x, y, z, is, row,
@@ -531,8 +611,10 @@ static hipError_t launch_cs2(const HopArgs &a, int stage, hipStream_t st) {
   constexpr int WP = cs_waves_form(D, sizeof(T) == 8, NR, true, FLY);
   dim3 grid(a.ntiles * a.ngroups);
   if constexpr (cs4_ok<D, T, NR, FLY>()) {
+    // (d_R = 6 in FP32: one wave per SIMD fewer, so that it compiles without spills)
+    constexpr int WQ = (D == 6 && sizeof(T) == 4) ? WP - 1 : WP;
     if (stage == 4) {
-      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, 4, NTL, WP, FLY>), grid, dim3(64 * D), 0, st, a);
+      hipLaunchKernelGGL((k_hop_cs<D, REAL, T, DAG, NR, 4, NTL, WQ, FLY>), grid, dim3(64 * D), 0, st, a);
       return hipGetLastError();
     }
   }
