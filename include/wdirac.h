@@ -144,10 +144,13 @@ int wdirac_destroy(wdirac_ctx *ctx);
  *                                      ||r|| < delta max ||r|| (default 0.01)
  *   WDIRAC_OPT_TILE_TBLOCK             0 (default) = site tiles in lexicographic
  *                                      order; b > 0 = in t-blocks of b slices
- *                                      (t-neighbours close in time); b < 0 =
- *                                      in chunks of -b slices with t fastest
- *                                      (consecutive tiles are t-neighbours);
- *                                      used when |b| divides T and tiles do
+ *                                      (t-neighbours close in time), used
+ *                                      when b divides T; b = -(10 bx + by) < 0
+ *                                      = sub-lattices of bx x-rows by by
+ *                                      tiles of a (t, x) row, each swept
+ *                                      along t, used when bx, by > 0 divide
+ *                                      X and the tiles of a row (values in
+ *                                      [-99, 64]); both need tiles that do
  *                                      not straddle (t, x) rows
  *   WDIRAC_OPT_HOP_NR_F64 / _F32       right-hand sides sharing each link load
  *                                      (1..12).  Form 6: the largest of 1,
@@ -191,7 +194,7 @@ typedef struct {
   int32_t variant;    /* WDIRAC_OPT_HOP_VARIANT_F64 values (0..6)        */
   int32_t nr;         /* right-hand sides per block (colour-split form)  */
   int32_t xcd_remap;  /* 1 = contiguous tile ranges per XCD               */
-  int32_t tblock;     /* t-block of the tile order (0 = lexicographic)    */
+  int32_t tblock;     /* tile order (WDIRAC_OPT_TILE_TBLOCK values)      */
   int32_t candidates; /* number of shapes timed                           */
   double us;          /* mean time of one hop launch with that shape (best
                          round of the second pass)                        */

@@ -502,7 +502,7 @@ int wdirac_set_option(wdirac_ctx *ctx, int option, double value) {
       ctx->cg_graph = (int)value;
       return WDIRAC_OK;
     case WDIRAC_OPT_TILE_TBLOCK:
-      if (!(value >= -64 && value <= 64)) return fail(WDIRAC_EINVAL, "t-block must be in [-64, 64]");
+      if (!(value >= -99 && value <= 64)) return fail(WDIRAC_EINVAL, "t-block must be in [-99, 64]");
       ctx->tblock = (int)value;
       return WDIRAC_OK;
     case WDIRAC_OPT_TUNE_COMPACT:
@@ -536,12 +536,14 @@ int wdirac_autotune(wdirac_ctx *ctx, const void *UR, int prec, int nrhs, void *w
     int variant, nr, remap, tblock;
   };
   std::vector<Cand> cands;
-  // t-fastest chunks (negative t-blocks) only where a work item holds
-  // several right-hand sides
-  const int tbs[] = {0, 2, 4, 8, -4, -8};
+  // sub-lattice sweeps (negative codes -(10 bx + by)) only where a work item
+  // holds several right-hand sides; shapes whose code does not fit the
+  // lattice fall back to lexicographic order in the launch
+  const int tbs[] = {0, 2, 4, 8, -23, -33, -43, -63, -39};
   for (int tb : tbs) {
     if (tb < 0 && nrhs < 4) continue;
-    if (tb && (ctx->nlat > 1 || ctx->g[0].T % (tb < 0 ? -tb : tb))) continue;
+    if (tb > 0 && (ctx->nlat > 1 || ctx->g[0].T % tb)) continue;
+    if (tb < 0 && (ctx->nlat > 1 || ctx->g[0].X % ((-tb) / 10))) continue;
     for (int remap = 0; remap < 2; ++remap) {
       for (int v = wd::HOP_COLOUR; v <= wd::HOP_MULTI; ++v) {
         if (!wd::hop_variant_ok(ctx->N, ctx->rep, ctx->d, v)) continue;

@@ -24,23 +24,27 @@ __device__ __forceinline__ int tile_of_block(int b, int ntiles, int remap) {
 // order (t-block of tb slices, x, t within the block, tile within the row):
 // t-neighbours are then tiles_per_tx tiles apart instead of a whole t-slice,
 // so they are still in L2 when read.  tb = 0: lexicographic order.
-// With tb < 0 the slices are taken in chunks of -tb with t fastest:
-// (chunk, x, tile within the row, t within the chunk), so consecutive work
-// items are t-neighbours and the tiles of a (t, x) row follow each other
-// -tb items apart (for work items holding many right-hand sides, whose
-// neighbourhoods would not stay in L2 across a whole row of tiles).
+// With tb = -(10 bx + by) < 0 (for work items holding many right-hand
+// sides, whose per-site inputs are too large for a whole row of tiles to
+// stay in L2): the lattice is cut into sub-lattices of bx x-rows by by tiles
+// of a (t, x) row, and each sub-lattice is swept along t, (sub-lattice, t,
+// x within it, tile within it), so that a tile's t-neighbours are bx by
+// items away and its x-neighbours inside the sub-lattice by items away.
+// With the XCD remap each XCD sweeps a contiguous set of sub-lattices.
 __device__ __forceinline__ int tile_order(int q, const HopArgs &a) {
   if (a.tblock == 0) return q;
   if (a.tblock < 0) {
-    const int nb = a.tiles_per_tx, tc = -a.tblock, X = a.lat[0].g.X;
-    const int per_c = X * nb * tc;
-    const int ci = q / per_c;
-    int r = q - ci * per_c;
-    const int x = r / (nb * tc);
-    r -= x * nb * tc;
-    const int yb = r / tc;
-    const int tin = r - yb * tc;
-    return ((ci * tc + tin) * X + x) * nb + yb;
+    const int code = -a.tblock, bx = code / 10, by = code % 10;
+    const int nb = a.tiles_per_tx, X = a.lat[0].g.X, T = a.lat[0].g.T;
+    const int per_sub = T * bx * by;
+    const int sub = q / per_sub;
+    int r = q - sub * per_sub;
+    const int t = r / (bx * by);
+    r -= t * bx * by;
+    const int xi = r / by, yi = r - xi * by;
+    const int nyb = nb / by;
+    const int xs = sub / nyb, ys = sub - xs * nyb;
+    return (t * X + xs * bx + xi) * nb + ys * by + yi;
   }
   const int nb = a.tiles_per_tx, tb = a.tblock, X = a.lat[0].g.X;
   const int per_tb = X * tb * nb;
@@ -80,10 +84,11 @@ __device__ __forceinline__ cplx<T> link_mac(T u, cplx<T> h, cplx<T> acc, bool) {
 }
 
 // Tile bookkeeping of a launch with tiles of ts sites: per-lattice tile
-// ranges, the partial-sum row length and counts, and the t-blocked order
-// (single lattices only: tiles_per_tx is the number of tiles covering one
-// (t, x) row of Y*Z sites; the order falls back to lexicographic if tiles
-// straddle rows or tb does not divide T).
+// ranges, the partial-sum row length and counts, and the t-blocked or
+// sub-lattice order (single lattices only: tiles_per_tx is the number of
+// tiles covering one (t, x) row of Y*Z sites; the order falls back to
+// lexicographic if tiles straddle rows, tb > 0 does not divide T, or bx, by
+// of tb < 0 are zero or do not divide X and the tiles of a row).
 inline void set_tiles(HopArgs &a, int ts, int nrhs, Counts *counts, int *prow) {
   int tot = 0, mx = 0;
   for (int l = 0; l < a.nlat; ++l) {
@@ -99,9 +104,16 @@ inline void set_tiles(HopArgs &a, int ts, int nrhs, Counts *counts, int *prow) {
   *prow = mx;
   const Geom &g = a.lat[0].g;
   const int lex_per_tile = 2 * ts, rowl = g.Y * g.Z;
-  const int tbabs = a.tblock < 0 ? -a.tblock : a.tblock;
-  if (a.nlat == 1 && tbabs > 0 && rowl % lex_per_tile == 0 && g.T % tbabs == 0) {
-    a.tiles_per_tx = rowl / lex_per_tile;
+  const int nb = rowl / lex_per_tile;
+  bool ok = a.nlat == 1 && a.tblock != 0 && rowl % lex_per_tile == 0;
+  if (a.tblock > 0) {
+    ok = ok && g.T % a.tblock == 0;
+  } else if (a.tblock < 0) {
+    const int bx = (-a.tblock) / 10, by = (-a.tblock) % 10;
+    ok = ok && bx > 0 && by > 0 && g.X % bx == 0 && nb % by == 0;
+  }
+  if (ok) {
+    a.tiles_per_tx = nb;
   } else {
     a.tblock = 0;
     a.tiles_per_tx = 0;

@@ -105,6 +105,10 @@ def test_null_and_range_checks(W):
     assert L.wdirac_set_option(h, W.OPT_CG_CHECK_EVERY, 0.0) == W.EINVAL
     assert L.wdirac_set_option(h, W.OPT_MIXED_DELTA, 1.5) == W.EINVAL
     assert L.wdirac_set_option(h, 99, 1.0) == W.EINVAL
+    assert L.wdirac_set_option(h, W.OPT_TILE_TBLOCK, -100.0) == W.EINVAL
+    assert L.wdirac_set_option(h, W.OPT_TILE_TBLOCK, 65.0) == W.EINVAL
+    for tb in (-99.0, -33.0, 64.0, 0.0):
+        assert L.wdirac_set_option(h, W.OPT_TILE_TBLOCK, tb) == W.OK
     assert L.wdirac_set_option(h, W.OPT_HOP_VARIANT_F64, W.HOP_SITE) == W.OK
     assert L.wdirac_field_bytes(h, 9, 1, 0) == 0
     assert L.wdirac_workspace_bytes(h, 10, 1, 0) == 0

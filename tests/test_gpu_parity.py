@@ -180,10 +180,12 @@ def test_cg_multi_rhs_staged_links(W, mode):
 
 @pytest.mark.parametrize('variant', [1, 2, 0])
 def test_dslash_tile_orders(W, variant):
-    """t-blocked tile orders permute the work, never the result."""
+    """t-blocked and sub-lattice tile orders permute the work, never the
+    result (codes -(10 bx + by) with bx | X = 6 and by | 1 tile per row; -22
+    does not fit and falls back to lexicographic order)."""
     s = Setup(3, 'FUND', (8, 6, 8, 16), seed=270)   # Y*Z = 128: whole tiles per (t, x) row
     psi = s.spinor(271, 2)
-    for tb in (0, 2, 4, 8):
+    for tb in (0, 2, 4, 8, -11, -21, -31, -61, -22):
         s.lat.set_option(W.OPT_TILE_TBLOCK, tb)
         for prec in (0, 1):
             s.lat.set_option(W.OPT_HOP_VARIANT_F64 if prec == 0 else W.OPT_HOP_VARIANT_F32, variant)
@@ -193,6 +195,25 @@ def test_dslash_tile_orders(W, variant):
                 s.lat.dslash_eo(out, inp, s.URg[prec], p, dagger, 2, 0.0, None, 1.0, prec)
                 got = s.from_gpu_half(out, p, 2, prec)
                 assert rel(got, hop_expect(s, psi, p, dagger, 0.0, 1.0, None)) < TOL[prec], (tb, prec, p)
+
+
+@pytest.mark.parametrize('N,rep', [(3, 'SYM'), (3, 'FUND')])
+def test_multi_rhs_tile_orders(W, N, rep):
+    """The multi-rhs form (12 rhs, 4 per block, 3 groups) under the
+    sub-lattice sweeps and t-blocks: with d_R = 6 a tile is 32 sites, so a
+    (t, x) row of Y*Z = 128 sites holds 2 tiles and by may be 1 or 2."""
+    s = Setup(N, rep, (4, 4, 8, 16), seed=275, precs=(0,))
+    nrhs = 12
+    psi = s.spinor(276, nrhs)
+    exp = hop_expect(s, psi, 0, 0, 0.0, 1.0, None)
+    s.lat.set_option(W.OPT_HOP_VARIANT_F64, W.HOP_MULTI)
+    s.lat.set_option(W.OPT_HOP_NR_F64, 4)
+    for tb in (0, 2, -11, -21, -41, -12, -22, -42):
+        s.lat.set_option(W.OPT_TILE_TBLOCK, tb)
+        inp = s.to_gpu_half(psi, 1, 0)
+        out = s.lat.new_half(nrhs, 0)
+        s.lat.dslash_eo(out, inp, s.URg[0], 0, 0, nrhs, 0.0, None, 1.0, 0)
+        assert rel(s.from_gpu_half(out, 0, nrhs, 0), exp) < TOL[0], tb
 
 
 def test_autotune_keeps_results(W):
