@@ -162,24 +162,6 @@ __device__ __forceinline__ void mr_project_loaded(cplx<T> (&h0)[D], cplx<T> (&h1
   }
 }
 
-// Spin-project this lane's colour rows (row group rg) of the neighbour spinor
-// at index nb (direction MU, projector sign SIG) into slots 0 .. RPL - 1 of
-// h0/h1.  in: this wavefront's right-hand side (uniform); roff = rg RPL stride.
-template <int D, typename T, int MU, int SIG>
-__device__ __forceinline__ void mr_project(cplx<T> (&h0)[D], cplx<T> (&h1)[D], const cplx<T> *in, int stride,
-                                           uint32_t roff, int nb) {
-  constexpr int RPL = MrShape<D>::RPL;
-  const uint32_t off = roff + (uint32_t)nb;
-#pragma unroll
-  for (int k = 0; k < RPL; ++k) {
-    cplx<T> p[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) p[s] = *at(in + (size_t)(s * D + k) * stride, off);
-    h0[k] = p[0] + ipow<PROJ_PH(MU, SIG, 0)>(p[2 + ECOL(MU, 0)]);
-    h1[k] = p[1] + ipow<PROJ_PH(MU, SIG, 1)>(p[2 + ECOL(MU, 1)]);
-  }
-}
-
 // Complete h0/h1 (own colours in slots 0 .. RPL - 1) to the full projected
 // two-spinor in colour order (with two lanes per site; see split_halves).
 template <int D, typename T>
