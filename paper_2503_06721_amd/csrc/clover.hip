@@ -1019,9 +1019,73 @@ __device__ __forceinline__ void g_load(cplx<double> (&gm)[N][N], const cplx<doub
     }
 }
 
-// Thread per link (y, rho): P = coef sum over the planes (rho, nu) and the
-// leaf steps along rho of +-B^+ g B (see above); out as in the hopping force:
-// P, or G = 2i P U (gradient), stored or accumulated.
+// X <- S^+ X S for a Hermitian X, S a fundamental link (dag: its adjoint)
+// read from the structure-of-arrays copy; the upper triangle is formed and
+// mirrored, so X stays exactly Hermitian.
+template <int N>
+__device__ __forceinline__ void herm_transport(cplx<double> (&X)[N][N], const cplx<double> *Us, size_t V, size_t lex,
+                                               int mu, bool dag) {
+  cplx<double> S[N][N], T[N][N];
+  load_link<N>(S, Us, V, lex, mu, dag);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      cplx<double> s = mk(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < N; ++q) s = cfma(X[i][q], S[q][j], s);
+      T[i][j] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      cplx<double> s = mk(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < N; ++q) s = cfma_conj(S[q][i], T[q][j], s);
+      X[i][j] = i == j ? mk(s.re, 0.0) : s;
+      if (j != i) X[j][i] = mk(s.re, -s.im);
+    }
+}
+
+// The plaquette of plane p = (lo, hi) with lower corner z (offsets za, zb
+// along lo, hi from y), traversed lo, hi, lo^+, hi^+: steps S_0 = U_lo(z),
+// S_1 = U_hi(z+lo), S_2 = U_lo(z+hi)^+, S_3 = U_hi(z)^+, corners c_m = start
+// of S_m.  The leaf k of a site is this loop started at c_k (leaf 0 at z,
+// 1 at z+lo, 2 at z+lo+hi, 3 at z+hi), so for the link at step J every leaf
+// of the plaquette contributes B^+ g_k B with B the path from c_k to step J,
+// and the four nest as
+//   H_J = g_J + S_{J+3}^+ [g_{J+3} + S_{J+2}^+ [g_{J+2} + S_{J+1}^+ g_{J+1} S_{J+1}] S_{J+2}] S_{J+3}
+// (indices mod 4): three transports instead of four separate paths.  The
+// link at a forward step receives +H_J, at a backward one -S_J^+ H_J S_J.
+template <int N, int J>
+__device__ __forceinline__ void plaquette_horner(cplx<double> (&acc)[N][N], const cplx<double> *Us,
+                                                 const cplx<double> *Gl, size_t V, const Geom &g,
+                                                 const int (&cy)[4], int lo, int hi, int p, int za, int zb) {
+  constexpr int ca[4] = {0, 1, 1, 0}, cb[4] = {0, 0, 1, 1};   // corner c_m - z
+  constexpr int sa[4] = {0, 1, 0, 0}, sb[4] = {0, 0, 1, 0};   // start of the link of S_m - z
+  cplx<double> H[N][N], gm[N][N];
+#pragma unroll
+  for (int s = 1; s <= 3; ++s) {
+    const int m = (J + s) & 3;
+    g_load<N>(gm, Gl, p * 4 + m, lex_at(g, cy, lo, za + ca[m], hi, zb + cb[m]), V);
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) H[i][j] = s == 1 ? gm[i][j] : H[i][j] + gm[i][j];
+    herm_transport<N>(H, Us, V, lex_at(g, cy, lo, za + sa[m], hi, zb + sb[m]), (m & 1) ? hi : lo, m >= 2);
+  }
+  g_load<N>(gm, Gl, p * 4 + J, lex_at(g, cy, lo, za + ca[J], hi, zb + cb[J]), V);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc[i][j] = acc[i][j] + H[i][j] + gm[i][j];
+}
+
+// Thread per link (y, rho): P = coef sum over the planes (rho, nu) of the
+// contributions of the two plaquettes that hold the link (see
+// plaquette_horner); out as in the hopping force: P, or G = 2i P U
+// (gradient), stored or accumulated.
 template <int N>
 __global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__restrict__ U,
                                                        const cplx<double> *__restrict__ Gl, double *P, Geom g,
@@ -1040,51 +1104,28 @@ __global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__res
   cy[2] = (int)(r % g.Y); r /= g.Y;
   cy[1] = (int)(r % g.X);
   cy[0] = (int)(r / g.X);
-  cplx<double> acc[N][N];
+  // forward (af) and backward (ab) occurrences; the backward sum is
+  // transported by the link itself once at the end
+  cplx<double> af[N][N], ab[N][N];
   for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) acc[i][j] = mk(0.0, 0.0);
+    for (int j = 0; j < N; ++j) af[i][j] = ab[i][j] = mk(0.0, 0.0);
   for (int nu = 0; nu < 4; ++nu) {
     if (nu == rho) continue;
     const int lo = rho < nu ? rho : nu, hi = rho < nu ? nu : rho;
     const int p = lo == 0 ? hi - 1 : lo == 1 ? hi + 1 : 5;
-    const int dsel = rho == lo ? 0 : 1;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int f = 0; f < 4; ++f) {
-        const LeafStep st = kLeafC[k][f];
-        if (st.dir != dsel) continue;
-        // path from the corner x = y - a lo - b hi, links placed relative to y
-        cplx<double> B[N][N];
-        for (int i = 0; i < N; ++i)
-          for (int j = 0; j < N; ++j) B[i][j] = mk(i == j ? 1.0 : 0.0, 0.0);
-        const int nsteps = st.dag ? f + 1 : f;
-#pragma unroll
-        for (int j = 0; j < nsteps; ++j) {
-          const LeafStep sj = kLeafC[k][j];
-          cplx<double> u[N][N];
-          load_link<N>(u, U, V, lex_at(g, cy, lo, sj.a - st.a, hi, sj.b - st.b), sj.dir ? hi : lo, sj.dag != 0);
-          mul_right<N>(B, u);
-        }
-        const size_t xl = lex_at(g, cy, lo, -st.a, hi, -st.b);
-        cplx<double> gm[N][N];
-        g_load<N>(gm, Gl, p * 4 + k, xl, V);
-        cplx<double> T1[N][N];
-        for (int i = 0; i < N; ++i)
-          for (int j = 0; j < N; ++j) {
-            cplx<double> sum = mk(0.0, 0.0);
-            for (int q = 0; q < N; ++q) sum = cfma(gm[i][q], B[q][j], sum);
-            T1[i][j] = sum;
-          }
-        const double sg = st.dag ? -1.0 : 1.0;
-        for (int i = 0; i < N; ++i)
-          for (int j = 0; j < N; ++j) {
-            cplx<double> sum = mk(0.0, 0.0);
-            for (int q = 0; q < N; ++q) sum = cfma_conj(B[q][i], T1[q][j], sum);   // (B^+)_iq T1_qj
-            acc[i][j] = acc[i][j] + sg * sum;
-          }
-      }
+    if (rho == lo) {
+      plaquette_horner<N, 0>(af, U, Gl, V, g, cy, lo, hi, p, 0, 0);    // S_0 of the plaquette at y
+      plaquette_horner<N, 2>(ab, U, Gl, V, g, cy, lo, hi, p, 0, -1);   // S_2 of the one at y - hi
+    } else {
+      plaquette_horner<N, 1>(af, U, Gl, V, g, cy, lo, hi, p, -1, 0);   // S_1 of the one at y - lo
+      plaquette_horner<N, 3>(ab, U, Gl, V, g, cy, lo, hi, p, 0, 0);    // S_3 of the one at y
+    }
   }
+  // S_J = U_rho(y)^+ for the backward steps: S_J^+ ab S_J = U ab U^+
+  herm_transport<N>(ab, U, V, lex, rho, true);
+  cplx<double> acc[N][N];
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) acc[i][j] = af[i][j] - ab[i][j];
   cplx<double> Fo[N][N];
   for (int i = 0; i < N; ++i)
     for (int j = 0; j < N; ++j) Fo[i][j] = coef * acc[i][j];
