@@ -39,16 +39,32 @@ __device__ __forceinline__ cplx<T> herm_entry(const cplx<T> *P, size_t es, int N
   return mk<T>(v.re, -v.im);
 }
 
-// Lexicographic index of c + a e_mu + b e_nu (periodic wrap).
-__device__ __forceinline__ size_t lex_at(const Geom &g, const int (&c)[4], int mu, int a, int nu, int b) {
-  int q[4] = {c[0], c[1], c[2], c[3]};
-  const int L[4] = {g.T, g.X, g.Y, g.Z};
-  q[mu] += a;
-  q[nu] += b;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) q[k] = (q[k] + L[k]) % L[k];
-  return (((size_t)q[0] * g.X + q[1]) * g.Y + q[2]) * g.Z + q[3];
-}
+// Sites c + a e_lo + b e_hi (|a|, |b| <= 1) around one site in the plane
+// (lo, hi), lexicographic: only the two coordinates that move are wrapped,
+// by compare and select (no integer division).
+struct PlaneNb {
+  long long base, slo, shi;
+  int clo, chi, Llo, Lhi;
+  __device__ __forceinline__ static long long pick(int i, long long v0, long long v1, long long v2, long long v3) {
+    return i == 0 ? v0 : i == 1 ? v1 : i == 2 ? v2 : v3;
+  }
+  __device__ __forceinline__ PlaneNb(const Geom &g, const int (&c)[4], size_t lex, int lo, int hi) {
+    const long long sz = g.Z, sy = (long long)g.Y * g.Z, sx = sy * g.X;
+    base = (long long)lex;
+    slo = pick(lo, sx, sy, sz, 1);
+    shi = pick(hi, sx, sy, sz, 1);
+    clo = (int)pick(lo, c[0], c[1], c[2], c[3]);
+    chi = (int)pick(hi, c[0], c[1], c[2], c[3]);
+    Llo = (int)pick(lo, g.T, g.X, g.Y, g.Z);
+    Lhi = (int)pick(hi, g.T, g.X, g.Y, g.Z);
+  }
+  __device__ __forceinline__ size_t at(int a, int b) const {
+    const int qa = clo + a, qb = chi + b;
+    const int da = qa < 0 ? a + Llo : qa >= Llo ? a - Llo : a;
+    const int db = qb < 0 ? b + Lhi : qb >= Lhi ? b - Lhi : b;
+    return (size_t)(base + da * slo + db * shi);
+  }
+};
 
 // The clover kernels read the fundamental links from a structure-of-arrays
 // copy Us[mu][N*N][V] (lexicographic site minor; k_links_soa), so that the
@@ -145,6 +161,7 @@ __global__ __launch_bounds__(256) void k_clover_F(const cplx<double> *__restrict
   c[2] = (int)(r % g.Y); r /= g.Y;
   c[1] = (int)(r % g.X);
   c[0] = (int)(r / g.X);
+  const PlaneNb pn(g, c, lex, mu, nu);
   cplx<double> *Fp = F + (size_t)p * D * D * V + lex;
   if constexpr (REP == 0) {
     // fundamental representation (R = 1): the four leaves summed in
@@ -165,7 +182,7 @@ __global__ __launch_bounds__(256) void k_clover_F(const cplx<double> *__restrict
       for (int f = 0; f < 4; ++f) {
         const LeafStep st = kLeafC[k][f];
         cplx<double> u[N][N];
-        load_link<N>(u, U, V, lex_at(g, c, mu, st.a, nu, st.b), st.dir ? nu : mu, st.dag != 0);
+        load_link<N>(u, U, V, pn.at(st.a, st.b), st.dir ? nu : mu, st.dag != 0);
         if (f == 0) {
 #pragma unroll
           for (int i = 0; i < N; ++i)
@@ -207,7 +224,7 @@ __global__ __launch_bounds__(256) void k_clover_F(const cplx<double> *__restrict
     for (int f = 0; f < 4; ++f) {
       const LeafStep s = kLeafC[k][f];
       cplx<double> u[N][N];
-      load_link<N>(u, U, V, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
+      load_link<N>(u, U, V, pn.at(s.a, s.b), s.dir ? nu : mu, s.dag != 0);
       if (f == 0) {
 #pragma unroll
         for (int i = 0; i < N; ++i)
@@ -946,6 +963,7 @@ __global__ __launch_bounds__(64) void k_clover_leafgen(const cplx<double> *__res
   c[2] = (int)(r % g.Y); r /= g.Y;
   c[1] = (int)(r % g.X);
   c[0] = (int)(r / g.X);
+  const PlaneNb pn(g, c, lex, mu, nu);
   cplx<double> Kh[D][D];
   {
     cplx<double> lam[D][D];
@@ -962,7 +980,7 @@ __global__ __launch_bounds__(64) void k_clover_leafgen(const cplx<double> *__res
     for (int f = 0; f < 4; ++f) {
       const LeafStep s = kLeafC[k][f];
       cplx<double> u[N][N];
-      load_link<N>(u, U, V, lex_at(g, c, mu, s.a, nu, s.b), s.dir ? nu : mu, s.dag != 0);
+      load_link<N>(u, U, V, pn.at(s.a, s.b), s.dir ? nu : mu, s.dag != 0);
       if (f == 0) {
         for (int i = 0; i < N; ++i)
           for (int j = 0; j < N; ++j) L[i][j] = u[i][j];
@@ -1060,22 +1078,22 @@ __device__ __forceinline__ void herm_transport(cplx<double> (&X)[N][N], const cp
 // link at a forward step receives +H_J, at a backward one -S_J^+ H_J S_J.
 template <int N, int J>
 __device__ __forceinline__ void plaquette_horner(cplx<double> (&acc)[N][N], const cplx<double> *Us,
-                                                 const cplx<double> *Gl, size_t V, const Geom &g,
-                                                 const int (&cy)[4], int lo, int hi, int p, int za, int zb) {
+                                                 const cplx<double> *Gl, size_t V, const PlaneNb &pn, int lo, int hi,
+                                                 int p, int za, int zb) {
   constexpr int ca[4] = {0, 1, 1, 0}, cb[4] = {0, 0, 1, 1};   // corner c_m - z
   constexpr int sa[4] = {0, 1, 0, 0}, sb[4] = {0, 0, 1, 0};   // start of the link of S_m - z
   cplx<double> H[N][N], gm[N][N];
 #pragma unroll
   for (int s = 1; s <= 3; ++s) {
     const int m = (J + s) & 3;
-    g_load<N>(gm, Gl, p * 4 + m, lex_at(g, cy, lo, za + ca[m], hi, zb + cb[m]), V);
+    g_load<N>(gm, Gl, p * 4 + m, pn.at(za + ca[m], zb + cb[m]), V);
 #pragma unroll
     for (int i = 0; i < N; ++i)
 #pragma unroll
       for (int j = 0; j < N; ++j) H[i][j] = s == 1 ? gm[i][j] : H[i][j] + gm[i][j];
-    herm_transport<N>(H, Us, V, lex_at(g, cy, lo, za + sa[m], hi, zb + sb[m]), (m & 1) ? hi : lo, m >= 2);
+    herm_transport<N>(H, Us, V, pn.at(za + sa[m], zb + sb[m]), (m & 1) ? hi : lo, m >= 2);
   }
-  g_load<N>(gm, Gl, p * 4 + J, lex_at(g, cy, lo, za + ca[J], hi, zb + cb[J]), V);
+  g_load<N>(gm, Gl, p * 4 + J, pn.at(za + ca[J], zb + cb[J]), V);
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
@@ -1113,12 +1131,13 @@ __global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__res
     if (nu == rho) continue;
     const int lo = rho < nu ? rho : nu, hi = rho < nu ? nu : rho;
     const int p = lo == 0 ? hi - 1 : lo == 1 ? hi + 1 : 5;
+    const PlaneNb pn(g, cy, lex, lo, hi);
     if (rho == lo) {
-      plaquette_horner<N, 0>(af, U, Gl, V, g, cy, lo, hi, p, 0, 0);    // S_0 of the plaquette at y
-      plaquette_horner<N, 2>(ab, U, Gl, V, g, cy, lo, hi, p, 0, -1);   // S_2 of the one at y - hi
+      plaquette_horner<N, 0>(af, U, Gl, V, pn, lo, hi, p, 0, 0);    // S_0 of the plaquette at y
+      plaquette_horner<N, 2>(ab, U, Gl, V, pn, lo, hi, p, 0, -1);   // S_2 of the one at y - hi
     } else {
-      plaquette_horner<N, 1>(af, U, Gl, V, g, cy, lo, hi, p, -1, 0);   // S_1 of the one at y - lo
-      plaquette_horner<N, 3>(ab, U, Gl, V, g, cy, lo, hi, p, 0, 0);    // S_3 of the one at y
+      plaquette_horner<N, 1>(af, U, Gl, V, pn, lo, hi, p, -1, 0);   // S_1 of the one at y - lo
+      plaquette_horner<N, 3>(ab, U, Gl, V, pn, lo, hi, p, 0, 0);    // S_3 of the one at y
     }
   }
   // S_J = U_rho(y)^+ for the backward steps: S_J^+ ab S_J = U ab U^+
