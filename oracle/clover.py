@@ -109,9 +109,11 @@ def apply_sitewise(M, psi):
     return np.einsum('...ij,...j->...i', M, v).reshape(sh)
 
 
-def dirac_clover(psi, UR, m, csw, bc, exponential=False):
-    """Full-lattice clover operator: diagonal blocks + hopping term."""
-    return apply_sitewise(diagonal_blocks(UR, m, csw, exponential), psi) + dirac.hopping(psi, UR, bc)
+def dirac_clover(psi, UR, m, csw, bc, exponential=False, blocks=None):
+    """Full-lattice clover operator: diagonal blocks + hopping term (blocks:
+    as in Dhat_clover)."""
+    M = diagonal_blocks(UR, m, csw, exponential) if blocks is None else blocks
+    return apply_sitewise(M, psi) + dirac.hopping(psi, UR, bc)
 
 
 def half_blocks(M, dims, p):
@@ -119,9 +121,11 @@ def half_blocks(M, dims, p):
     return L.to_half(M, dims, p)
 
 
-def Dhat_clover(x_e, UR, m, csw, bc, dims, exponential=False, dagger=False):
-    """D-hat = D_ee - D_eo D_oo^{-1} D_oe on an even half field (dagger: its adjoint)."""
-    M = diagonal_blocks(UR, m, csw, exponential)
+def Dhat_clover(x_e, UR, m, csw, bc, dims, exponential=False, dagger=False, blocks=None):
+    """D-hat = D_ee - D_eo D_oo^{-1} D_oe on an even half field (dagger: its adjoint).
+    blocks: diagonal_blocks(UR, m, csw, exponential) when the caller already
+    holds them (a solver applying the operator many times)."""
+    M = diagonal_blocks(UR, m, csw, exponential) if blocks is None else blocks
     Me, Mo = half_blocks(M, dims, 0), half_blocks(M, dims, 1)
     if dagger:
         Me, Mo = _dag(Me), _dag(Mo)
@@ -131,7 +135,7 @@ def Dhat_clover(x_e, UR, m, csw, bc, dims, exponential=False, dagger=False):
     return apply_sitewise(Me, x_e) - dirac.hop_block(t, UR, bc, dims, 0, dagger=dagger)
 
 
-def normal_op_clover(x_e, UR, m, csw, bc, dims, exponential=False):
-    """A = D-hat^dagger D-hat with the clover term."""
-    y = Dhat_clover(x_e, UR, m, csw, bc, dims, exponential)
-    return Dhat_clover(y, UR, m, csw, bc, dims, exponential, dagger=True)
+def normal_op_clover(x_e, UR, m, csw, bc, dims, exponential=False, blocks=None):
+    """A = D-hat^dagger D-hat with the clover term (blocks: as in Dhat_clover)."""
+    y = Dhat_clover(x_e, UR, m, csw, bc, dims, exponential, blocks=blocks)
+    return Dhat_clover(y, UR, m, csw, bc, dims, exponential, dagger=True, blocks=blocks)

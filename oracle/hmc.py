@@ -114,8 +114,9 @@ class Action:
     def _solve(self, UR, dims):
         if self.csw is None:
             return cg_eo(self.phi, UR, self.m, self.bc, dims, self.tol, 50000)[0]
+        M = CL.diagonal_blocks(UR, self.m, self.csw, self.exponential)
         def A(v):
-            return CL.normal_op_clover(v, UR, self.m, self.csw, self.bc, dims, self.exponential)
+            return CL.normal_op_clover(v, UR, self.m, self.csw, self.bc, dims, self.exponential, blocks=M)
         return cg(A, self.phi, self.tol, 50000)[0]
 
     def value(self, U):

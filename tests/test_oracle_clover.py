@@ -101,7 +101,8 @@ def test_even_odd_schur_complement(exponential):
     UR = R.represent(synth.haar_links(dims, N, 65), rep)
     d = UR.shape[-1]
     n = 4 * d
-    Dm = dense.dense_matrix(lambda v: CL.dirac_clover(v, UR, m, csw, APBC, exponential), dims + (4, d))
+    M = CL.diagonal_blocks(UR, m, csw, exponential)
+    Dm = dense.dense_matrix(lambda v: CL.dirac_clover(v, UR, m, csw, APBC, exponential, blocks=M), dims + (4, d))
     ev = L.parity_field(dims).ravel() == 0
     idx = np.arange(Dm.shape[0]).reshape(dims + (n,))
     ie = np.concatenate([idx[tuple(c)] for c in np.argwhere(L.parity_field(dims) == 0)])
@@ -109,10 +110,10 @@ def test_even_odd_schur_complement(exponential):
     Dee, Deo, Doe, Doo = Dm[np.ix_(ie, ie)], Dm[np.ix_(ie, io)], Dm[np.ix_(io, ie)], Dm[np.ix_(io, io)]
     schur = Dee - Deo @ np.linalg.solve(Doo, Doe)
     half_shape = (int(ev.sum()), 4, d)
-    Dh = dense.dense_matrix(lambda v: CL.Dhat_clover(v, UR, m, csw, APBC, dims, exponential), half_shape)
+    Dh = dense.dense_matrix(lambda v: CL.Dhat_clover(v, UR, m, csw, APBC, dims, exponential, blocks=M), half_shape)
     assert np.allclose(Dh, schur, atol=1e-12)
-    Dhd = dense.dense_matrix(lambda v: CL.Dhat_clover(v, UR, m, csw, APBC, dims, exponential, dagger=True),
-                             half_shape)
+    Dhd = dense.dense_matrix(lambda v: CL.Dhat_clover(v, UR, m, csw, APBC, dims, exponential, dagger=True,
+                                                      blocks=M), half_shape)
     assert np.allclose(Dhd, schur.conj().T, atol=1e-12)
     s0, l0 = np.linalg.slogdet(Dm)
     s1, l1 = np.linalg.slogdet(Doo)

@@ -57,7 +57,8 @@ def test_exp_adjoint_is_the_block_exponential():
 
 
 def normal_op(UR, m, csw, dims, expo):
-    return lambda v: CL.normal_op_clover(v, UR, m, csw, APBC, dims, expo)
+    M = CL.diagonal_blocks(UR, m, csw, expo)
+    return lambda v: CL.normal_op_clover(v, UR, m, csw, APBC, dims, expo, blocks=M)
 
 
 def pf_action(U, phi, rep, m, csw, dims, expo):
