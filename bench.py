@@ -752,13 +752,14 @@ def rhmc_and_clover(W, torch, synth, name='su3_fund_32x32x32x32'):
     return {'workload': name, 'multi_shift_time_to_1e-10': ms, 'clover_cg_time_to_1e-10': cl}
 
 
-def hmc_trajectory(W, torch, synth, name='su2_adj_32x16x16x16', n_therm=20, n_meas=4):
+def hmc_trajectory(W, torch, synth, name='su2_adj_32x16x16x16', n_therm=40, n_meas=4):
     """HMC on SU(2) ADJ 32x16^3 (second-order Omelyan, tau = 0.5 in 5
     steps, Wilson plaquette beta = 2.2 plus the two-flavour adjoint
     pseudofermion): n_therm thermalisation trajectories from the synthetic
-    start (each accepted, fresh momenta and pseudofermions every time), then
-    n_meas timed HMC updates with the Metropolis test: seconds per
-    trajectory, CG iterations, dH and acceptance."""
+    start (each accepted, fresh momenta and pseudofermions every time; the
+    same tau in 10 steps, so that the integration stays stable while the
+    smooth start heats up), then n_meas timed HMC updates with the Metropolis
+    test: seconds per trajectory, CG iterations, dH and acceptance."""
     import numpy as np
     from paper_2503_06721_amd.hmc import HMC
     cfg = synth.CONFIGS[name]
@@ -778,7 +779,7 @@ def hmc_trajectory(W, torch, synth, name='su2_adj_32x16x16x16', n_therm=20, n_me
         re = torch.randn((1,) + tuple(dims) + (4, lat.d), dtype=torch.float64, device='cuda', generator=g)
         im = torch.randn((1,) + tuple(dims) + (4, lat.d), dtype=torch.float64, device='cuda', generator=g)
         pi, phi = hmc.refresh(U, w, lat.pack_half(torch.complex(re, im) * (0.5 ** 0.5), 0))
-        H0, H1 = hmc.trajectory(U, pi, phi, eps, nsteps, 'omelyan2')
+        H0, H1 = hmc.trajectory(U, pi, phi, eps / 2, 2 * nsteps, 'omelyan2')
         dH_therm.append(H1 - H0)
     torch.cuda.synchronize()
     t_therm = time.perf_counter() - t0
@@ -799,7 +800,8 @@ def hmc_trajectory(W, torch, synth, name='su2_adj_32x16x16x16', n_therm=20, n_me
                                'first_dH': dH_therm[0], 'last_dH': dH_therm[-1]},
             'seconds_per_trajectory': round(float(np.median(secs)), 4), 'dH': dH, 'accepted': acc,
             'cg_iterations_per_trajectory': (hmc.cg_iters - it0) / n_meas,
-            'start': f'{n_therm} always-accepted trajectories from the synthetic exp(i 0.3 H) links'}
+            'start': f'{n_therm} always-accepted trajectories ({2 * nsteps} steps) from the synthetic '
+                     f'exp(i 0.3 H) links'}
 
 
 SECTIONS = {'multi_rhs': multi_rhs_cg, 'mixed_large': mixed_cg_large, 'lattice_batch': lattice_batch_cg,
