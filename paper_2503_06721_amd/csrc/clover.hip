@@ -150,9 +150,13 @@ __global__ __launch_bounds__(256) void k_clover_F(const cplx<double> *__restrict
   constexpr int D = rep_dim(N, REP);
   const size_t V = 2 * (size_t)g.Vh;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= 6 * V) return;
-  const int p = (int)(gid / V);
-  const size_t lex = gid - (size_t)p * V;
+  // 64-site chunks, the six planes of a chunk in consecutive wavefronts (the
+  // planes that share a link direction read it close together in time)
+  const size_t chunk = gid / 384;
+  const int r6 = (int)(gid - chunk * 384);
+  const int p = r6 >> 6;
+  const size_t lex = chunk * 64 + (r6 & 63);
+  if (lex >= V) return;
   int mu, nu;
   plane_dirs(p, mu, nu);
   size_t r = lex;
@@ -562,7 +566,7 @@ __global__ __launch_bounds__(256) void k_clover_apply(cplx<T> *out, const cplx<T
 // ------------------------------------------------------------------ launch
 template <int N, int REP>
 static hipError_t F_launch(const void *U, double *F, const Geom &g, hipStream_t st) {
-  const size_t n = 6 * 2 * (size_t)g.Vh;
+  const size_t n = 384 * ((2 * (size_t)g.Vh + 63) / 64);   // six planes per 64-site chunk
   hipLaunchKernelGGL((k_clover_F<N, REP>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
                      (const cplx<double> *)U, (cplx<double> *)F, g);
   return hipGetLastError();
@@ -952,9 +956,13 @@ __global__ __launch_bounds__(64) void k_clover_leafgen(const cplx<double> *__res
   constexpr int D = rep_dim(N, REP);
   const size_t V = 2 * (size_t)g.Vh;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= 6 * V) return;
-  const int p = (int)(gid / V);
-  const size_t lex = gid - (size_t)p * V;
+  // 64-site chunks, the six planes of a chunk in consecutive wavefronts (the
+  // planes that share a link direction read it close together in time)
+  const size_t chunk = gid / 384;
+  const int r6 = (int)(gid - chunk * 384);
+  const int p = r6 >> 6;
+  const size_t lex = chunk * 64 + (r6 & 63);
+  if (lex >= V) return;
   int mu, nu;
   plane_dirs(p, mu, nu);
   size_t r = lex;
@@ -1110,12 +1118,16 @@ __global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__res
                                                        double coef, int gradient, int accumulate) {
   const size_t V = 2 * (size_t)g.Vh;
   const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= 4 * V) return;
-  // direction slowest: the lanes of a wavefront hold one direction on
-  // consecutive sites (coalesced structure-of-arrays link reads, the same
-  // planes in every lane)
-  const int rho = (int)(gid / V);
-  const size_t lex = gid - (size_t)rho * V;
+  // 64-site chunks, the four directions of a chunk in consecutive
+  // wavefronts: the lanes of a wavefront hold one direction on consecutive
+  // sites (coalesced structure-of-arrays link reads, the same planes in every
+  // lane), and the two directions of a plane read its leaf matrices close
+  // together in time
+  const size_t chunk = gid / 256;
+  const int r4 = (int)(gid - chunk * 256);
+  const int rho = r4 >> 6;
+  const size_t lex = chunk * 64 + (r4 & 63);
+  if (lex >= V) return;
   size_t r = lex;
   int cy[4];
   cy[3] = (int)(r % g.Z); r /= g.Z;
@@ -1257,9 +1269,9 @@ static hipError_t clover_force_nr(void *P, const void *Xe, const void *Xo, const
       hipLaunchKernelGGL((k_clover_insert<D>), ig, dim3(64), 0, st, (const cplx<double> *)Xe,
                          (const cplx<double> *)Xo, (const cplx<double> *)Ye, (const cplx<double> *)Yo,
                          (const cplx<double> *)clov, (const cplx<double> *)F, (cplx<double> *)K, g, S, m0, csw, cdet);
-    hipLaunchKernelGGL((k_clover_leafgen<N, REP>), dim3((unsigned)((6 * V + 63) / 64)), dim3(64), 0, st,
+    hipLaunchKernelGGL((k_clover_leafgen<N, REP>), dim3((unsigned)(6 * ((V + 63) / 64))), dim3(64), 0, st,
                        (const cplx<double> *)U, (const cplx<double> *)K, (cplx<double> *)Gl, g);
-    hipLaunchKernelGGL((k_clover_gather<N>), dim3((unsigned)((4 * V + 127) / 128)), dim3(128), 0, st,
+    hipLaunchKernelGGL((k_clover_gather<N>), dim3((unsigned)(2 * ((V + 63) / 64))), dim3(128), 0, st,
                        (const cplx<double> *)U, (const cplx<double> *)Gl, (double *)P, g, coef, gradient, accumulate);
     return hipGetLastError();
   } else {

@@ -97,3 +97,27 @@ def test_clover_force_batch(W):
         assert rel(got[o:o + v].reshape(exp.shape), exp) < TOL[0], k
         assert abs(lds[k] - CF.logdet_odd(b.U[k], 'FUND', m, csw, dd)) <= 1e-12 * abs(lds[k])
         o += v
+
+
+@pytest.mark.parametrize('dims', [(2, 6, 2, 2), (4, 2, 6, 2), (6, 2, 2, 6)])
+@pytest.mark.parametrize('N,rep,m,csw,expo', [(3, 'FUND', 0.1, 1.7, 0), (2, 'ADJ', -0.2, 1.3, 1)])
+def test_clover_force_ragged_volume(W, dims, N, rep, m, csw, expo):
+    """Volumes that are not a multiple of the 64-site chunks the clover field,
+    leaf and gather kernels assign to one wavefront per plane or direction:
+    the clover field (through log det D_oo), the pseudofermion force and the
+    determinant force on every link."""
+    s = Setup(N, rep, dims, seed=990 + N, links='expH', eps=0.5, precs=(0,))
+    x_e = s.half(s.spinor(991), 0)[0]
+    clov = s.lat.new_clover(0)
+    s.lat.clover_field(clov, s.Ug, m, csw, expo, 0)
+    ld, ld_or = s.lat.clover_logdet(clov), CF.logdet_odd(s.U, rep, m, csw, dims, bool(expo))
+    assert abs(ld - ld_or) <= 1e-12 * max(abs(ld_or), 1.0), (ld, ld_or)
+    xg = s.to_gpu_half(L.from_half(x_e, dims, 0)[None], 0)
+    P = torch.zeros(tuple(dims) + (4, N, N), dtype=torch.complex128, device='cuda')
+    s.lat.force_eo_clover(P, xg, s.URg[0], s.Ug, clov, m, csw, expo)
+    s.lat.force_clover_logdet(P, s.Ug, clov, m, csw, expo, accumulate=1)
+    g = (CF.pseudofermion_force_components(x_e, s.U, rep, m, csw, APBC, dims, bool(expo))
+         + CF.det_force_components(s.U, rep, m, csw, dims, bool(expo)))
+    err = rel(P.cpu().numpy(), components_to_P(g, N))
+    log(f'  {dims} N={N} {rep} expo={expo}: force error {err:.2e}')
+    assert err < TOL[0]
