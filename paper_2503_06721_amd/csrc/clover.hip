@@ -83,24 +83,30 @@ __device__ __forceinline__ void load_link(cplx<double> (&u)[N][N], const cplx<do
 }
 
 // Us[mu][e][lex] = U[lex][mu][e] (canonical [T][X][Y][Z][4][N][N] complex).
-// Thread per (site, direction), site fastest, so the writes are coalesced.
+// A block transposes 64 sites through LDS: the 64 x 4 N^2 entries are read in
+// canonical order (consecutive threads, consecutive addresses) and written
+// per (mu, e) as a run of 64 consecutive sites.
 template <int N>
 __global__ __launch_bounds__(256) void k_links_soa(const cplx<double> *__restrict__ U, cplx<double> *__restrict__ Us,
                                                    size_t V) {
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= 4 * V) return;
-  const int mu = (int)(gid / V);
-  const size_t lex = gid - (size_t)mu * V;
-  const cplx<double> *src = U + (lex * 4 + mu) * N * N;
-  cplx<double> *dst = Us + (size_t)mu * N * N * V + lex;
-#pragma unroll
-  for (int e = 0; e < N * N; ++e) dst[(size_t)e * V] = src[e];
+  constexpr int E = 4 * N * N;   // complex entries per site
+  constexpr int S = E + 1;       // LDS row, padded against bank conflicts
+  __shared__ cplx<double> t[64 * S];
+  const size_t s0 = (size_t)blockIdx.x * 64;
+  const int ns = V - s0 < 64 ? (int)(V - s0) : 64;
+  const cplx<double> *src = U + s0 * E;
+  for (int k = threadIdx.x; k < ns * E; k += 256) t[(k / E) * S + k % E] = src[k];
+  __syncthreads();
+  for (int k = threadIdx.x; k < 64 * E; k += 256) {
+    const int j = k >> 6, site = k & 63;   // j = mu N^2 + e
+    if (site < ns) Us[(size_t)j * V + s0 + site] = t[site * S + j];
+  }
 }
 
 template <int N>
 static hipError_t links_soa_launch(const void *U, double *Us, const Geom &g, hipStream_t st) {
   const size_t V = 2 * (size_t)g.Vh;
-  hipLaunchKernelGGL((k_links_soa<N>), dim3((unsigned)((4 * V + 255) / 256)), dim3(256), 0, st,
+  hipLaunchKernelGGL((k_links_soa<N>), dim3((unsigned)((V + 63) / 64)), dim3(256), 0, st,
                      (const cplx<double> *)U, (cplx<double> *)Us, V);
   return hipGetLastError();
 }
