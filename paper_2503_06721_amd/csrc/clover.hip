@@ -39,6 +39,16 @@ __device__ __forceinline__ cplx<T> herm_entry(const cplx<T> *P, size_t es, int N
   return mk<T>(v.re, -v.im);
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin; block b is given the
+// logical index that makes each XCD's blocks one contiguous range, so that
+// consecutive logical blocks (the planes or directions of one site chunk)
+// run on the same XCD and share its L2 (the leaf and gather kernels; the F
+// kernel is faster without it).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned n) {
+  const unsigned q = n >> 3, rmd = n & 7, x = b & 7, j = b >> 3;
+  return x * q + (x < rmd ? x : rmd) + j;
+}
+
 // Sites c + a e_lo + b e_hi (|a|, |b| <= 1) around one site in the plane
 // (lo, hi), lexicographic: only the two coordinates that move are wrapped,
 // by compare and select (no integer division).
@@ -961,7 +971,7 @@ __global__ __launch_bounds__(64) void k_clover_leafgen(const cplx<double> *__res
                                                        cplx<double> *__restrict__ G, Geom g) {
   constexpr int D = rep_dim(N, REP);
   const size_t V = 2 * (size_t)g.Vh;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t gid = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   // 64-site chunks, the six planes of a chunk in consecutive wavefronts (the
   // planes that share a link direction read it close together in time)
   const size_t chunk = gid / 384;
@@ -1123,7 +1133,7 @@ __global__ __launch_bounds__(128) void k_clover_gather(const cplx<double> *__res
                                                        const cplx<double> *__restrict__ Gl, double *P, Geom g,
                                                        double coef, int gradient, int accumulate) {
   const size_t V = 2 * (size_t)g.Vh;
-  const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t gid = (size_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   // 64-site chunks, the four directions of a chunk in consecutive
   // wavefronts: the lanes of a wavefront hold one direction on consecutive
   // sites (coalesced structure-of-arrays link reads, the same planes in every
